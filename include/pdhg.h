@@ -1,0 +1,180 @@
+/*
+ * pdhg.h -- C ABI of the MI355X PDHG solver for LP relaxations of unit
+ * commitment (restarted, adaptive-step primal-dual hybrid gradient).
+ *
+ * Problem (the LP pair of the paper's "PDHG Background" section, read with
+ * the signs of its Lagrangian and update equations and widened to equality
+ * rows and bounds):
+ *
+ *     min  c'x   s.t.  a_i'x  = b_i   (row_kind[i] == PDHG_ROW_EQ)
+ *                      a_i'x >= b_i   (row_kind[i] == PDHG_ROW_GE)
+ *                      l <= x <= u
+ *
+ * Iteration (the Chambolle-Pock update of that section with the box
+ * projection on x and the sign-cone projection on the duals of >= rows),
+ * on the diagonally rescaled problem, tau = eta/omega, sigma = eta*omega:
+ *
+ *     x' = proj_[l,u]( x - tau (c - A'y) )
+ *     y' = proj_Y  ( y + sigma (b - A(2x' - x)) )
+ *
+ * with the adaptive step size and restart scheme of the PDLP method that the
+ * section cites.  Every call returns PDHG_OK (0) or a negative error code;
+ * pdhg_last_error() gives a thread-local message for the last failure.
+ * No C++ exception crosses this interface.
+ *
+ * Memory: the library never allocates device memory.  The caller passes a
+ * device workspace (size from pdhg_workspace_bytes) that must stay alive
+ * until pdhg_destroy.  All device work is queued on the stream given to
+ * pdhg_setup (0 = the null stream).
+ */
+#ifndef PDHG_H
+#define PDHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+enum {
+  PDHG_OK = 0,
+  PDHG_ERR_ARG = -1,       /* bad argument: null pointer, m or n <= 0, bad row kind, bad option */
+  PDHG_ERR_CSR = -2,       /* not canonical CSR: row_ptr[0] != 0, row_ptr not monotone,
+                              row_ptr[m] != nnz, column out of range, columns of a row not
+                              strictly ascending */
+  PDHG_ERR_BOUNDS = -3,    /* l > u, l = +inf, u = -inf or a NaN bound */
+  PDHG_ERR_NONFINITE = -4, /* non-finite entry of A, b or c */
+  PDHG_ERR_OOM = -5,       /* workspace smaller than pdhg_workspace_bytes */
+  PDHG_ERR_HIP = -6,       /* a HIP runtime call failed; the handle is unusable afterwards */
+  PDHG_ERR_STATE = -7      /* call out of order (e.g. backward without an unrolled forward) */
+};
+
+/* solve status (pdhg_info.status) */
+enum {
+  PDHG_OPTIMAL = 1,        /* relative KKT error <= tol */
+  PDHG_ITER_LIMIT = 2,
+  PDHG_TIME_LIMIT = 3,
+  PDHG_NUMERICAL = 4       /* NaN or Inf reached the iterates */
+};
+
+enum { PDHG_ROW_EQ = 0, PDHG_ROW_GE = 1 };
+enum { PDHG_FP64 = 0, PDHG_MIXED = 1 };
+
+/* The LP, borrowed for the duration of pdhg_setup (which copies it).
+ * CSR: row_ptr[m+1] int32 with row_ptr[0] = 0 and row_ptr[m] = nnz,
+ * col_idx[nnz] int32 strictly ascending inside each row, val[nnz] finite.
+ * row_kind[m] uint8; b[m], c[n] finite; l[n] may hold -INFINITY, u[n] +INFINITY.
+ * on_device = 0: host pointers; 1: device pointers (validated on the GPU). */
+typedef struct {
+  int64_t m, n, nnz;
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  const double *val;
+  const uint8_t *row_kind;
+  const double *b, *c, *l, *u;
+  int on_device;
+} pdhg_lp;
+
+typedef struct {
+  double tol;             /* relative KKT target (default 1e-4) */
+  int64_t max_iter;       /* attempts (default 1e7) */
+  double time_limit_s;    /* wall-clock limit of pdhg_solve (default 1e30) */
+  int precision;          /* PDHG_FP64 or PDHG_MIXED */
+  int eval_period;        /* attempts between evaluations (default 64) */
+  int step_mode;          /* 0 adaptive (default), 1 constant eta */
+  double fixed_eta;       /* step_mode 1 / unrolled mode: eta; <= 0: 0.9/||A^||_2 */
+  double fixed_omega;     /* > 0: initial primal weight; <= 0: ||c^||/||b^|| */
+  int scaling_iters;      /* Ruiz passes (default 10) */
+  int pock_chambolle;     /* 1 (default): one Pock-Chambolle pass after Ruiz */
+  int restart;            /* 1 (default): restart scheme on */
+  int use_average;        /* 1 (default): weighted average is a candidate */
+  int64_t unroll_iters;   /* > 0: unrolled fixed-step mode with this many steps */
+  int64_t checkpoint_every; /* unrolled mode: checkpoint period (default 50) */
+  int use_graph;          /* 1 (default): replay iteration blocks as HIP graphs */
+  int verbose;            /* 1: one log line per evaluation on stderr */
+  double polish_tol;      /* mixed precision: FP32 phase stops at this KKT (default tol) */
+  int pw_update;          /* 1 (default): primal weight updated at restarts; 0: kept */
+  double pw_theta;        /* smoothing of the primal-weight update in log space (default 0.5) */
+} pdhg_opts;
+
+typedef struct {
+  int status;
+  int which;              /* returned point: 0 current iterate, 1 average */
+  int64_t attempts;       /* one attempt = one A'y and one Ax product */
+  int64_t accepted, restarts;
+  int64_t attempts_fp32;  /* mixed precision: attempts spent in the FP32 phase */
+  double primal_obj, dual_obj;
+  double rel_primal, rel_dual, rel_gap, rel_kkt;
+  double eta, omega;      /* final step size and primal weight (scaled space) */
+  double setup_s, solve_s;
+} pdhg_info;
+
+typedef struct pdhg_handle pdhg_handle;
+
+void pdhg_default_opts(pdhg_opts *opts);
+
+/* Bytes of device workspace needed for this LP and options. */
+int pdhg_workspace_bytes(const pdhg_lp *lp, const pdhg_opts *opts, size_t *bytes);
+
+/* Validate the LP, copy it into the workspace, build the bound kinds, the
+ * transpose A' (canonical CSR, rows ascending inside each column) and the
+ * power-of-two diagonal scaling (Ruiz, then Pock-Chambolle).  stream is a
+ * hipStream_t passed as void*.  Synchronizes the stream once. */
+int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace,
+               size_t workspace_bytes, void *stream, pdhg_handle **handle);
+
+/* Solve from x0, y0 (nullable; original space, device pointers if the LP
+ * was given on the device, else host) and write x[n], y[m] (same memory
+ * kind).  info is host memory. */
+int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x,
+               double *y, pdhg_info *info);
+
+/* One instance of a batched solve.  Instances whose base handle is the same
+ * share that handle's matrix; b, c, l, u override the base's vectors when
+ * non-null (original space, same memory kind as the base LP), and the
+ * n_fix (index, value) pairs fix variables (l = u = value) on top. */
+typedef struct {
+  int32_t base;
+  const double *b, *c, *l, *u;
+  const int32_t *fix_idx;
+  const double *fix_val;
+  int64_t n_fix;
+} pdhg_instance;
+
+/* Solve `batch` instances.  x[k], y[k] receive instance k's solution and
+ * infos[k] its report.  Handles are used with their own options. */
+int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles,
+                     const pdhg_instance *inst, int batch, double *const *x,
+                     double *const *y, pdhg_info *infos);
+
+/* After a pdhg_solve in unrolled mode (opts.unroll_iters > 0), the gradient
+ * of V = c'x_K with respect to b and c (original space), scaled by
+ * grad_value.  grad_b[m], grad_c[n]: same memory kind as the LP. */
+int pdhg_backward(pdhg_handle *h, double grad_value, double *grad_b, double *grad_c);
+
+void pdhg_destroy(pdhg_handle *h);
+
+const char *pdhg_last_error(void);
+
+/* ---- inspection entry points (diagnostics and parity tests) ---- */
+
+/* Copy the preprocessed problem to host memory (any pointer may be null):
+ * bound kinds var_kind[n] (0 free, 1 lower, 2 upper, 3 boxed, 4 fixed),
+ * the transpose (colptr[n+1], rowidx[nnz], valT[nnz]), the scaled A values
+ * val_s[nnz], and the scaling diagonals Dr[m], Dc[n]
+ * (A_scaled = diag(Dr) A diag(Dc)). */
+int pdhg_export_setup(pdhg_handle *h, uint8_t *var_kind, int32_t *colptr,
+                      int32_t *rowidx, double *valT, double *val_s, double *Dr,
+                      double *Dc);
+
+/* out = A_scaled x (transpose = 0, x[n], out[m]) or A_scaled' x
+ * (transpose = 1, x[m], out[n]) with the solver's FP64 SpMV kernels; host
+ * memory. */
+int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDHG_H */

@@ -1,0 +1,754 @@
+// PDHG iteration kernels.
+//
+// One attempt (Chambolle-Pock step of the paper's "PDHG Background" section,
+// box projection on x, sign-cone projection on >= rows, PDLP adaptive step):
+//   k_primal   x' = proj_[l,u](x - tau (c - A'y))      (A'y fused, row-dot over A')
+//   k_dual     y' = proj_Y(y + sigma (b - (2 A x' - A x)))   (A x' fused, cached as Ax')
+//   k_control  step-size test, accept/reject by flipping the buffer index
+// Every 'eval_period' attempts an evaluation computes the KKT error of the
+// current and the averaged iterate, decides termination and restarts.
+// All control state lives in device memory so that a block of attempts can be
+// replayed as one HIP graph; the host reads the state only between blocks.
+#include "internal.h"
+
+#include <math.h>
+
+namespace {
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = (n + PDHG_BLOCK - 1) / PDHG_BLOCK;
+  return (unsigned)(g > 0 ? g : 1);
+}
+
+// The hardware hands consecutive workgroups to the 8 XCDs in turn.  Map them
+// so that each XCD works on one contiguous range of logical blocks, which keeps
+// the gathered vector windows of neighbouring rows inside one L2.
+__device__ inline int xcd_remap(int b, int nb) {
+  int xcd = b & 7, local = b >> 3;
+  int per = nb >> 3, rem = nb & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+template <typename T>
+__device__ inline T clamp_box(T x, T lo, T hi) {
+  // explicit comparisons keep NaN visible (fmin/fmax would drop it)
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+
+// Deterministic block reduction of NQ doubles (fixed shuffle tree, then the
+// four waves in order).  Bit q of maxmask selects max instead of sum.
+template <int NQ>
+__device__ inline void block_reduce(double (&v)[NQ], unsigned maxmask, double *out) {
+  __shared__ double lds[PDHG_BLOCK / 64][NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    double a = v[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_down(a, off, 64);
+      a = ((maxmask >> q) & 1) ? fmax(a, o) : a + o;
+    }
+    v[q] = a;
+  }
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; q++) lds[wid][q] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+      double a = lds[0][q];
+      for (int w = 1; w < PDHG_BLOCK / 64; w++)
+        a = ((maxmask >> q) & 1) ? fmax(a, lds[w][q]) : a + lds[w][q];
+      out[q] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// Sum (or max) of `cnt` partials with stride `stride`, one workgroup, fixed order.
+template <int NQ>
+__device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t stride,
+                                       unsigned maxmask, double *out) {
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) v[q] = 0.0;
+  for (int64_t b = threadIdx.x; b < cnt; b += PDHG_BLOCK) {
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+      double a = p[q * stride + b];
+      v[q] = ((maxmask >> q) & 1) ? fmax(v[q], a) : v[q] + a;
+    }
+  }
+  block_reduce<NQ>(v, maxmask, out);
+}
+
+// ---------------------------------------------------------------------------
+// attempt kernels
+
+template <typename T>
+__device__ inline void primal_update(const IterView<T> &w, int64_t j, T t, T tau, const T *x,
+                                     T *xn, double pend, int fresh, double &d2) {
+  T xj = x[j];
+  T xv = clamp_box<T>(xj - tau * (w.c[j] - t), w.l[j], w.u[j]);
+  xn[j] = xv;
+  double d = (double)xv - (double)xj;
+  d2 = d * d;
+  if (pend > 0.0) w.XS[j] = (fresh ? (T)0 : w.XS[j]) + (T)pend * xj;
+}
+
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_primal(IterView<T> w, const CtlState *st) {
+  int lb = xcd_remap(blockIdx.x, gridDim.x);
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  const int cur = st->cur;
+  const T tau = (T)(st->eta / st->omega);
+  const double pend = st->pending;
+  const int fresh = st->fresh;
+  const T *__restrict__ x = w.X[cur];
+  T *__restrict__ xn = w.X[cur ^ 1];
+  const T *__restrict__ y = w.Y[cur];
+  double d2[1] = {0.0};
+  if (j < w.n) {
+    int s = w.cp[j], e = w.cp[j + 1];
+    if (e - s <= PDHG_LONG_SEG) {
+      T t = 0;
+      for (int k = s; k < e; k++) t += w.vt[k] * y[w.ri[k]];
+      primal_update(w, j, t, tau, x, xn, pend, fresh, d2[0]);
+    }
+  }
+  double out[1];
+  block_reduce<1>(d2, 0u, out);
+  if (threadIdx.x == 0) w.part_dx2[lb] = out[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_primal_long(IterView<T> w, const CtlState *st) {
+  int64_t j = w.long_cols[blockIdx.x];
+  const int cur = st->cur;
+  const T tau = (T)(st->eta / st->omega);
+  const T *__restrict__ y = w.Y[cur];
+  int s = w.cp[j], e = w.cp[j + 1];
+  double acc[1] = {0.0};
+  for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)(w.vt[k] * y[w.ri[k]]);
+  double tot[1];
+  block_reduce<1>(acc, 0u, tot);
+  if (threadIdx.x == 0) {
+    double d2 = 0.0;
+    primal_update(w, j, (T)tot[0], tau, w.X[cur], w.X[cur ^ 1], st->pending, st->fresh, d2);
+    w.part_dx2[w.nblk_cols + blockIdx.x] = d2;
+  }
+}
+
+template <typename T>
+__device__ inline void dual_update(const IterView<T> &w, int64_t i, T s, T sigma, int cur,
+                                   double pend, int fresh, double &dy2, double &inter) {
+  const T *y = w.Y[cur];
+  T axi = w.AX[cur][i], yi = y[i];
+  T yv = yi + sigma * (w.b[i] - (s + s - axi));
+  if (w.kind[i] == 1 && yv < (T)0) yv = (T)0;
+  w.Y[cur ^ 1][i] = yv;
+  w.AX[cur ^ 1][i] = s;
+  double dy = (double)yv - (double)yi;
+  dy2 = dy * dy;
+  inter = dy * ((double)s - (double)axi);
+  if (pend > 0.0) w.YS[i] = (fresh ? (T)0 : w.YS[i]) + (T)pend * yi;
+}
+
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_dual(IterView<T> w, const CtlState *st) {
+  int lb = xcd_remap(blockIdx.x, gridDim.x);
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  const int cur = st->cur;
+  const T sigma = (T)(st->eta * st->omega);
+  const double pend = st->pending;
+  const int fresh = st->fresh;
+  const T *__restrict__ xn = w.X[cur ^ 1];
+  double v[2] = {0.0, 0.0};
+  if (i < w.m) {
+    int s = w.rp[i], e = w.rp[i + 1];
+    if (e - s <= PDHG_LONG_SEG) {
+      T acc = 0;
+      for (int k = s; k < e; k++) acc += w.v[k] * xn[w.ci[k]];
+      dual_update(w, i, acc, sigma, cur, pend, fresh, v[0], v[1]);
+    }
+  }
+  double out[2];
+  block_reduce<2>(v, 0u, out);
+  if (threadIdx.x == 0) {
+    int64_t nb = w.nblk_rows + w.n_long_rows;
+    w.part_dy[lb] = out[0];
+    w.part_dy[nb + lb] = out[1];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_dual_long(IterView<T> w, const CtlState *st) {
+  int64_t i = w.long_rows[blockIdx.x];
+  const int cur = st->cur;
+  const T sigma = (T)(st->eta * st->omega);
+  const T *__restrict__ xn = w.X[cur ^ 1];
+  int s = w.rp[i], e = w.rp[i + 1];
+  double acc[1] = {0.0};
+  for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)(w.v[k] * xn[w.ci[k]]);
+  double tot[1];
+  block_reduce<1>(acc, 0u, tot);
+  if (threadIdx.x == 0) {
+    double dy2 = 0.0, inter = 0.0;
+    dual_update(w, i, (T)tot[0], sigma, cur, st->pending, st->fresh, dy2, inter);
+    int64_t nb = w.nblk_rows + w.n_long_rows;
+    w.part_dy[w.nblk_rows + blockIdx.x] = dy2;
+    w.part_dy[nb + w.nblk_rows + blockIdx.x] = inter;
+  }
+}
+
+// Step-size control of one attempt (PDLP adaptive rule):
+//   ebar = ||dz||_omega^2 / (2 |dy' A dx|),  accept iff eta <= ebar,
+//   eta <- min((1 - (k+1)^-0.3) ebar, (1 + (k+1)^-0.6) eta),  k = attempts so far.
+__global__ __launch_bounds__(PDHG_BLOCK) void k_control(const double *part_dx2, int64_t ncols_p,
+                                                        const double *part_dy, int64_t nrows_p,
+                                                        int adaptive, CtlState *st) {
+  __shared__ double r[3];
+  reduce_partials<1>(part_dx2, ncols_p, 0, 0u, &r[0]);
+  reduce_partials<2>(part_dy, nrows_p, nrows_p, 0u, &r[1]);
+  if (threadIdx.x != 0) return;
+  double dx2 = r[0], dy2 = r[1], inter = r[2];
+  double eta = st->eta, omega = st->omega;
+  long long k = st->k + 1;
+  if (st->pending > 0.0) st->fresh = 0;  // this attempt's kernels folded it
+  st->pending = 0.0;
+  int accept = 1;
+  double eta_new = eta;
+  if (adaptive) {
+    double nz = omega * dx2 + dy2 / omega;
+    double ebar = (inter != 0.0) ? nz / (2.0 * fabs(inter)) : INFINITY;
+    double kk = (double)(k + 1);
+    double e1 = (1.0 - pow(kk, -0.3)) * ebar;
+    double e2 = (1.0 + pow(kk, -0.6)) * eta;
+    accept = (eta <= ebar);
+    eta_new = e1 < e2 ? e1 : e2;
+  }
+  if (accept) {
+    st->cur ^= 1;
+    st->pending = eta;
+    st->wsum += eta;
+    st->accepted += 1;
+  }
+  st->eta = eta_new;
+  st->k = k;
+  st->dx2 = dx2;
+  st->dy2 = dy2;
+  st->inter = inter;
+}
+
+// ---------------------------------------------------------------------------
+// evaluation kernels (FP64)
+
+__device__ inline bool have_avg(const CtlState *st, int use_average) {
+  return use_average && st->wsum > 0.0;
+}
+
+template <typename T>
+__global__ void k_avg_cols(EvalView<T> e, const CtlState *st) {
+  if (!have_avg(st, e.use_average)) return;
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= e.n) return;
+  double pend = st->pending;
+  T xs = e.XS[j];
+  if (pend > 0.0) {
+    xs = (st->fresh ? (T)0 : xs) + (T)pend * e.X[st->cur][j];
+    e.XS[j] = xs;
+  }
+  e.XA[j] = (double)xs / st->wsum;
+}
+
+template <typename T>
+__global__ void k_avg_rows(EvalView<T> e, const CtlState *st) {
+  if (!have_avg(st, e.use_average)) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= e.m) return;
+  double pend = st->pending;
+  T ys = e.YS[i];
+  if (pend > 0.0) {
+    ys = (st->fresh ? (T)0 : ys) + (T)pend * e.Y[st->cur][i];
+    e.YS[i] = ys;
+  }
+  e.YA[i] = (double)ys / st->wsum;
+}
+
+// out = M x for a CSR M (FP64 values).  x is x0/x1 picked by the current
+// buffer index (sel_cur) or x0; gate_avg skips the product when there is no
+// average.  Rows longer than PDHG_LONG_SEG are left to k_spmv_long.
+template <typename TX>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_spmv_sel(const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         const double *__restrict__ v,
+                                                         int64_t rows, const TX *x0,
+                                                         const TX *x1, const CtlState *st,
+                                                         int sel_cur, int gate_avg,
+                                                         double *__restrict__ out) {
+  if (gate_avg && !have_avg(st, gate_avg)) return;
+  int lb = xcd_remap(blockIdx.x, gridDim.x);
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  if (i >= rows) return;
+  const TX *__restrict__ x = (sel_cur && st->cur) ? x1 : x0;
+  int s = rp[i], e = rp[i + 1];
+  if (e - s > PDHG_LONG_SEG) return;
+  double acc = 0.0;
+  for (int k = s; k < e; k++) acc += v[k] * (double)x[ci[k]];
+  out[i] = acc;
+}
+
+template <typename TX>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_spmv_sel_long(const int32_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ ci,
+                                                              const double *__restrict__ v,
+                                                              const int32_t *long_rows,
+                                                              const TX *x0, const TX *x1,
+                                                              const CtlState *st, int sel_cur,
+                                                              int gate_avg, double *out) {
+  if (gate_avg && !have_avg(st, gate_avg)) return;
+  int64_t i = long_rows[blockIdx.x];
+  const TX *__restrict__ x = (sel_cur && st->cur) ? x1 : x0;
+  int s = rp[i], e = rp[i + 1];
+  double acc[1] = {0.0};
+  for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += v[k] * (double)x[ci[k]];
+  double tot[1];
+  block_reduce<1>(acc, 0u, tot);
+  if (threadIdx.x == 0) out[i] = tot[0];
+}
+
+// Row-space KKT pieces for the current point and the average:
+// [0] ||r_p||^2 scaled [1] ||r_p||^2 unscaled [2] ||r_p||_inf unscaled
+// [3] b'y [4] ||y - y_last||^2, then the same five for the average.
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(EvalView<T> e, const CtlState *st) {
+  int64_t i = (int64_t)blockIdx.x * PDHG_BLOCK + threadIdx.x;
+  bool avg = have_avg(st, e.use_average);
+  double q[EV_ROWQ];
+#pragma unroll
+  for (int t = 0; t < EV_ROWQ; t++) q[t] = 0.0;
+  if (i < e.m) {
+    int cur = st->cur;
+    double bi = e.b[i], dr = e.Dr[i], yl = e.YL[i];
+    bool ge = e.kind[i] == 1;
+    for (int p = 0; p < (avg ? 2 : 1); p++) {
+      double yi = p ? e.YA[i] : (double)e.Y[cur][i];
+      double axi = p ? e.AXA[i] : (double)e.AX[cur][i];
+      double r = bi - axi;
+      if (ge && r < 0.0) r = 0.0;
+      double ru = r / dr;
+      q[5 * p + 0] = r * r;
+      q[5 * p + 1] = ru * ru;
+      q[5 * p + 2] = fabs(ru);
+      q[5 * p + 3] = bi * yi;
+      q[5 * p + 4] = (yi - yl) * (yi - yl);
+    }
+  }
+  double out[EV_ROWQ];
+  block_reduce<EV_ROWQ>(q, (1u << 2) | (1u << 7), out);
+  if (threadIdx.x == 0)
+    for (int t = 0; t < EV_ROWQ; t++) e.part_rows[(int64_t)t * e.nblk_rows + blockIdx.x] = out[t];
+}
+
+__device__ inline double proj_lambda(uint8_t vk, double lam) {
+  if (vk == VK_FREE) return 0.0;
+  if (vk == VK_LOWER) return lam > 0.0 ? lam : 0.0;
+  if (vk == VK_UPPER) return lam < 0.0 ? lam : 0.0;
+  return lam;
+}
+
+__device__ inline double bound_term(uint8_t vk, double lam, double l, double u) {
+  double t = 0.0;
+  if (lam > 0.0 && (vk == VK_LOWER || vk == VK_BOXED || vk == VK_FIXED)) t += l * lam;
+  if (lam < 0.0 && (vk == VK_UPPER || vk == VK_BOXED || vk == VK_FIXED)) t += u * lam;
+  return t;
+}
+
+// Column-space KKT pieces: [0] ||r_d||^2 scaled [1] ||r_d||^2 unscaled
+// [2] ||r_d||_inf unscaled [3] bound part of the dual objective [4] c'x
+// [5] ||x - x_last||^2, then the same six for the average.
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(EvalView<T> e, const CtlState *st) {
+  int64_t j = (int64_t)blockIdx.x * PDHG_BLOCK + threadIdx.x;
+  bool avg = have_avg(st, e.use_average);
+  double q[EV_COLQ];
+#pragma unroll
+  for (int t = 0; t < EV_COLQ; t++) q[t] = 0.0;
+  if (j < e.n) {
+    int cur = st->cur;
+    double cj = e.c[j], dc = e.Dc[j], lj = e.l[j], uj = e.u[j], xl = e.XL[j];
+    uint8_t vk = e.vk[j];
+    for (int p = 0; p < (avg ? 2 : 1); p++) {
+      double xj = p ? e.XA[j] : (double)e.X[cur][j];
+      double aty = p ? e.ATYA[j] : e.ATY[j];
+      double lam = cj - aty;
+      double pl = proj_lambda(vk, lam);
+      double rd = lam - pl;
+      double rdu = rd / dc;
+      q[6 * p + 0] = rd * rd;
+      q[6 * p + 1] = rdu * rdu;
+      q[6 * p + 2] = fabs(rdu);
+      q[6 * p + 3] = bound_term(vk, pl, lj, uj);
+      q[6 * p + 4] = cj * xj;
+      q[6 * p + 5] = (xj - xl) * (xj - xl);
+    }
+  }
+  double out[EV_COLQ];
+  block_reduce<EV_COLQ>(q, (1u << 2) | (1u << 8), out);
+  if (threadIdx.x == 0)
+    for (int t = 0; t < EV_COLQ; t++) e.part_cols[(int64_t)t * e.nblk_cols + blockIdx.x] = out[t];
+}
+
+struct PointKKT {
+  double komega, rel_kkt, pobj, dobj, rel_p, rel_d, rel_g, sp2, sd2, gap, dl_x, dl_y;
+};
+
+__device__ inline PointKKT point_kkt(const double *rq, const double *cq, double omega, double nb,
+                                     double nc) {
+  PointKKT p;
+  p.sp2 = rq[0];
+  p.sd2 = cq[0];
+  p.pobj = cq[4];
+  p.dobj = rq[3] + cq[3];
+  p.gap = fabs(p.pobj - p.dobj);
+  p.komega = sqrt(omega * p.sp2 + p.sd2 / omega + p.gap * p.gap);
+  p.rel_p = sqrt(rq[1]) / (1.0 + nb);
+  p.rel_d = sqrt(cq[1]) / (1.0 + nc);
+  p.rel_g = p.gap / (1.0 + fabs(p.pobj) + fabs(p.dobj));
+  double r = p.rel_p;
+  if (p.rel_d > r) r = p.rel_d;
+  if (p.rel_g > r) r = p.rel_g;
+  p.rel_kkt = r;
+  p.dl_x = sqrt(cq[5]);
+  p.dl_y = sqrt(rq[4]);
+  return p;
+}
+
+// Termination (relative KKT on the original problem), restart decision on
+// the scaled KKT_omega (restart at the better of current and average when it
+// fell to 0.2 of the last restart's, or to 0.8 with no progress since the
+// previous evaluation, or after 0.36 of all attempts), primal-weight update.
+__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const double *part_rows,
+                                                             int64_t nbr, const double *part_cols,
+                                                             int64_t nbc, int use_average,
+                                                             int restart, double pw_theta,
+                                                             double tol, long long max_iter,
+                                                             CtlState *st) {
+  __shared__ double rq[EV_ROWQ], cq[EV_COLQ];
+  reduce_partials<EV_ROWQ>(part_rows, nbr, nbr, (1u << 2) | (1u << 7), rq);
+  reduce_partials<EV_COLQ>(part_cols, nbc, nbc, (1u << 2) | (1u << 8), cq);
+  if (threadIdx.x != 0) return;
+  bool avg = use_average && st->wsum > 0.0;
+  double omega = st->omega;
+  PointKKT pc = point_kkt(rq, cq, omega, st->nb, st->nc);
+  PointKKT pa = pc;
+  if (avg) pa = point_kkt(rq + 5, cq + 6, omega, st->nb, st->nc);
+  long long k = st->k;
+  if (st->pending > 0.0) st->fresh = 0;  // the average kernels folded it
+  st->pending = 0.0;
+  st->have_avg = avg;
+  st->restart_flag = 0;
+  if (k == 0) st->kkt_last = pc.komega;
+  const PointKKT *rep = &pc;
+  int which = 0;
+  if (!isfinite(pc.rel_kkt)) {
+    st->done = 1;
+    st->status = 4;
+  } else if (pc.rel_kkt <= tol) {
+    st->done = 1;
+    st->status = 1;
+  } else if (avg && pa.rel_kkt <= tol) {
+    st->done = 1;
+    st->status = 1;
+    which = 1;
+    rep = &pa;
+  } else if (k >= max_iter) {
+    st->done = 1;
+    st->status = 2;
+  } else if (restart && k > 0) {
+    bool cand_avg = avg && pa.komega < pc.komega;
+    const PointKKT *cd = cand_avg ? &pa : &pc;
+    double kc = cd->komega;
+    bool do_restart = (kc <= 0.2 * st->kkt_last) ||
+                      (kc <= 0.8 * st->kkt_last && kc > st->kkt_prev) ||
+                      ((double)(k - st->last_restart) >= 0.36 * (double)k);
+    st->kkt_prev = kc;
+    if (do_restart) {
+      st->restart_flag = cand_avg ? 2 : 1;
+      double dx = cd->dl_x, dy = cd->dl_y;
+      if (pw_theta > 0.0 && dx > 1e-10 && dy > 1e-10)
+        omega = exp(pw_theta * log(dy / dx) + (1.0 - pw_theta) * log(omega));
+      st->omega = omega;
+      st->kkt_last = sqrt(omega * cd->sp2 + cd->sd2 / omega + cd->gap * cd->gap);
+      st->kkt_prev = INFINITY;
+      st->wsum = 0.0;
+      st->fresh = 1;
+      st->last_restart = k;
+      st->restarts += 1;
+      rep = cd;
+    }
+  }
+  st->which = which;
+  st->pobj = rep->pobj;
+  st->dobj = rep->dobj;
+  st->rel_p = rep->rel_p;
+  st->rel_d = rep->rel_d;
+  st->rel_gap = rep->rel_g;
+  st->rel_kkt = rep->rel_kkt;
+}
+
+template <typename T>
+__global__ void k_restart_cols(EvalView<T> e, const CtlState *st) {
+  int f = st->restart_flag;
+  if (f == 0) return;
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= e.n) return;
+  T *x = e.X[st->cur];
+  if (f == 2) x[j] = (T)e.XA[j];
+  e.XL[j] = (double)x[j];
+}
+
+template <typename T>
+__global__ void k_restart_rows(EvalView<T> e, const CtlState *st) {
+  int f = st->restart_flag;
+  if (f == 0) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= e.m) return;
+  T *y = e.Y[st->cur];
+  if (f == 2) {
+    y[i] = (T)e.YA[i];
+    e.AX[st->cur][i] = (T)e.AXA[i];
+  }
+  e.YL[i] = (double)y[i];
+}
+
+// Start point: x = proj_[l,u](x0 / Dc) (0 if no x0), y = proj_Y(y0 / Dr).
+template <typename T>
+__global__ void k_init_cols(EvalView<T> e, const double *x0) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= e.n) return;
+  double xv = x0 ? x0[j] / e.Dc[j] : 0.0;
+  xv = clamp_box<double>(xv, e.l[j], e.u[j]);
+  e.X[0][j] = (T)xv;
+  e.XL[j] = (double)(T)xv;
+}
+
+template <typename T>
+__global__ void k_init_rows(EvalView<T> e, const double *y0) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= e.m) return;
+  double yv = y0 ? y0[i] / e.Dr[i] : 0.0;
+  if (e.kind[i] == 1 && yv < 0.0) yv = 0.0;
+  e.Y[0][i] = (T)yv;
+  e.YL[i] = (double)(T)yv;
+}
+
+template <typename T>
+__global__ void k_ax_to_iter(EvalView<T> e, const double *ax) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < e.m) e.AX[0][i] = (T)ax[i];
+}
+
+__global__ void k_init_state(CtlState *st) {
+  st->cur = 0;
+  st->fresh = 1;
+  st->pending = 0.0;
+  st->wsum = 0.0;
+  st->k = 0;
+  st->accepted = 0;
+  st->restarts = 0;
+  st->last_restart = 0;
+  st->kkt_prev = INFINITY;
+  st->kkt_last = INFINITY;
+  st->done = 0;
+  st->status = 0;
+  st->which = 0;
+  st->restart_flag = 0;
+  st->have_avg = 0;
+  st->eta = st->eta0;
+  st->omega = st->omega0;
+}
+
+template <typename T>
+__global__ void k_unscale_cols(EvalView<T> e, const CtlState *st, double *x) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= e.n) return;
+  double xv = st->which ? e.XA[j] : (double)e.X[st->cur][j];
+  x[j] = e.Dc[j] * xv;
+}
+
+template <typename T>
+__global__ void k_unscale_rows(EvalView<T> e, const CtlState *st, double *y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= e.m) return;
+  double yv = st->which ? e.YA[i] : (double)e.Y[st->cur][i];
+  y[i] = e.Dr[i] * yv;
+}
+
+// ---------------------------------------------------------------------------
+// setup reductions for the initial step size and primal weight
+
+__global__ __launch_bounds__(PDHG_BLOCK) void k_norm_partials(const double *v, int64_t nnz,
+                                                              const double *b, const double *c,
+                                                              const double *b0, const double *c0,
+                                                              int64_t m, int64_t n,
+                                                              double *part, int nparts) {
+  // [0] max|v| [1] ||b||^2 [2] ||c||^2 [3] ||b0||^2 [4] ||c0||^2
+  double q[5] = {0, 0, 0, 0, 0};
+  int64_t stride = (int64_t)gridDim.x * PDHG_BLOCK;
+  for (int64_t k = (int64_t)blockIdx.x * PDHG_BLOCK + threadIdx.x; k < nnz; k += stride)
+    q[0] = fmax(q[0], fabs(v[k]));
+  for (int64_t i = (int64_t)blockIdx.x * PDHG_BLOCK + threadIdx.x; i < m; i += stride) {
+    q[1] += b[i] * b[i];
+    q[3] += b0[i] * b0[i];
+  }
+  for (int64_t j = (int64_t)blockIdx.x * PDHG_BLOCK + threadIdx.x; j < n; j += stride) {
+    q[2] += c[j] * c[j];
+    q[4] += c0[j] * c0[j];
+  }
+  double out[5];
+  block_reduce<5>(q, 1u, out);
+  if (threadIdx.x == 0)
+    for (int t = 0; t < 5; t++) part[t * nparts + blockIdx.x] = out[t];
+}
+
+__global__ __launch_bounds__(PDHG_BLOCK) void k_init_ctl(const double *part, int nparts,
+                                                         int step_mode, double fixed_eta,
+                                                         double fixed_omega, CtlState *st) {
+  __shared__ double r[5];
+  reduce_partials<5>(part, nparts, nparts, 1u, r);
+  if (threadIdx.x != 0) return;
+  double amax = r[0], nbs = sqrt(r[1]), ncs = sqrt(r[2]);
+  st->nb = sqrt(r[3]);
+  st->nc = sqrt(r[4]);
+  st->eta0 = (fixed_eta > 0.0) ? fixed_eta : (amax > 0.0 ? 1.0 / amax : 1.0);
+  if (fixed_omega > 0.0)
+    st->omega0 = fixed_omega;
+  else
+    st->omega0 = (ncs > 1e-10 && nbs > 1e-10) ? ncs / nbs : 1.0;
+  (void)step_mode;
+}
+
+__global__ void k_spmv_plain(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                             const double *__restrict__ v, int64_t rows,
+                             const double *__restrict__ x, double *__restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  double acc = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; k++) acc += v[k] * x[ci[k]];
+  y[i] = acc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+
+template <typename T>
+void launch_attempt(const IterView<T> &w, CtlState *st, int64_t, hipStream_t s) {
+  k_primal<T><<<w.nblk_cols, PDHG_BLOCK, 0, s>>>(w, st);
+  if (w.n_long_cols) k_primal_long<T><<<w.n_long_cols, PDHG_BLOCK, 0, s>>>(w, st);
+  k_dual<T><<<w.nblk_rows, PDHG_BLOCK, 0, s>>>(w, st);
+  if (w.n_long_rows) k_dual_long<T><<<w.n_long_rows, PDHG_BLOCK, 0, s>>>(w, st);
+  k_control<<<1, PDHG_BLOCK, 0, s>>>(w.part_dx2, w.nblk_cols + w.n_long_cols, w.part_dy,
+                                     w.nblk_rows + w.n_long_rows, w.adaptive, st);
+}
+
+// The evaluation needs the long-row lists too; they are passed through the
+// IterView that shares the matrix pointers.
+struct LongLists {
+  const int32_t *rows, *cols;
+  int nrows, ncols;
+};
+
+template <typename T>
+void launch_evaluate_impl(const EvalView<T> &e, const LongLists &ll, CtlState *st, double tol,
+                          int64_t max_iter, hipStream_t s) {
+  k_avg_cols<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e, st);
+  k_avg_rows<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, st);
+  // A'y of the current point, A x_avg, A'y_avg
+  k_spmv_sel<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e.cp, e.ri, e.vt, e.n, e.Y[0], e.Y[1], st,
+                                                      1, 0, e.ATY);
+  if (ll.ncols)
+    k_spmv_sel_long<T><<<ll.ncols, PDHG_BLOCK, 0, s>>>(e.cp, e.ri, e.vt, ll.cols, e.Y[0], e.Y[1],
+                                                        st, 1, 0, e.ATY);
+  k_spmv_sel<double><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e.rp, e.ci, e.v, e.m, e.XA, e.XA, st,
+                                                           0, e.use_average, e.AXA);
+  if (ll.nrows)
+    k_spmv_sel_long<double><<<ll.nrows, PDHG_BLOCK, 0, s>>>(e.rp, e.ci, e.v, ll.rows, e.XA, e.XA,
+                                                             st, 0, e.use_average, e.AXA);
+  k_spmv_sel<double><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e.cp, e.ri, e.vt, e.n, e.YA, e.YA, st,
+                                                           0, e.use_average, e.ATYA);
+  if (ll.ncols)
+    k_spmv_sel_long<double><<<ll.ncols, PDHG_BLOCK, 0, s>>>(e.cp, e.ri, e.vt, ll.cols, e.YA,
+                                                             e.YA, st, 0, e.use_average, e.ATYA);
+  k_eval_rows<T><<<e.nblk_rows, PDHG_BLOCK, 0, s>>>(e, st);
+  k_eval_cols<T><<<e.nblk_cols, PDHG_BLOCK, 0, s>>>(e, st);
+  k_eval_control<<<1, PDHG_BLOCK, 0, s>>>(e.part_rows, e.nblk_rows, e.part_cols, e.nblk_cols,
+                                          e.use_average, e.restart, e.pw_theta, tol,
+                                          (long long)max_iter, st);
+  k_restart_cols<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e, st);
+  k_restart_rows<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, st);
+}
+
+template <typename T>
+void launch_evaluate_ll(const EvalView<T> &e, const int32_t *long_rows, int n_long_rows,
+                        const int32_t *long_cols, int n_long_cols, CtlState *st, double tol,
+                        int64_t max_iter, hipStream_t s) {
+  LongLists ll{long_rows, long_cols, n_long_rows, n_long_cols};
+  launch_evaluate_impl<T>(e, ll, st, tol, max_iter, s);
+}
+
+template <typename T>
+void launch_init_point(const EvalView<T> &e, const int32_t *long_rows, int n_long_rows,
+                       const double *x0, const double *y0, CtlState *st, double *ax_tmp,
+                       hipStream_t s) {
+  k_init_state<<<1, 1, 0, s>>>(st);
+  k_init_cols<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e, x0);
+  k_init_rows<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, y0);
+  // A x of the start point (FP64 matrix, then cast to the iterate type)
+  k_spmv_sel<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e.rp, e.ci, e.v, e.m, e.X[0], e.X[0], st, 0,
+                                                      0, ax_tmp);
+  if (n_long_rows)
+    k_spmv_sel_long<T><<<n_long_rows, PDHG_BLOCK, 0, s>>>(e.rp, e.ci, e.v, long_rows, e.X[0],
+                                                           e.X[0], st, 0, 0, ax_tmp);
+  k_ax_to_iter<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, ax_tmp);
+}
+
+template <typename T>
+void launch_unscale(const EvalView<T> &e, const CtlState *st, double *x, double *y,
+                    hipStream_t s) {
+  k_unscale_cols<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e, st, x);
+  k_unscale_rows<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, st, y);
+}
+
+void launch_init_ctl(const double *v, int64_t nnz, const double *b, const double *c,
+                     const double *b0, const double *c0, int64_t m, int64_t n, double *scratch,
+                     int nscratch, CtlState *st, int step_mode, double fixed_eta,
+                     double fixed_omega, hipStream_t s) {
+  int np = nscratch / 5;
+  if (np > 1024) np = 1024;
+  k_norm_partials<<<np, PDHG_BLOCK, 0, s>>>(v, nnz, b, c, b0, c0, m, n, scratch, np);
+  k_init_ctl<<<1, PDHG_BLOCK, 0, s>>>(scratch, np, step_mode, fixed_eta, fixed_omega, st);
+}
+
+void launch_spmv(const int32_t *rp, const int32_t *ci, const double *v, int64_t rows,
+                 const double *x, double *y, hipStream_t s) {
+  k_spmv_plain<<<grid_for(rows), PDHG_BLOCK, 0, s>>>(rp, ci, v, rows, x, y);
+}
+
+#define INST(T)                                                                               \
+  template void launch_attempt<T>(const IterView<T> &, CtlState *, int64_t, hipStream_t);    \
+  template void launch_evaluate_ll<T>(const EvalView<T> &, const int32_t *, int,              \
+                                      const int32_t *, int, CtlState *, double, int64_t,      \
+                                      hipStream_t);                                           \
+  template void launch_init_point<T>(const EvalView<T> &, const int32_t *, int,              \
+                                     const double *, const double *, CtlState *, double *,    \
+                                     hipStream_t);                                            \
+  template void launch_unscale<T>(const EvalView<T> &, const CtlState *, double *, double *, \
+                                  hipStream_t);
+INST(double)
+INST(float)

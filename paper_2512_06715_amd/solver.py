@@ -1,0 +1,137 @@
+"""Python front end of libpdhg: a Problem owns one handle and its workspace.
+
+Every step of the solve runs in the HIP library; this module only moves
+arguments across the C ABI.  PyTorch provides the device workspace and the
+stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+OPTION_NAMES = [f for f, _ in L.PdhgOpts._fields_]
+
+
+def default_opts(**overrides) -> L.PdhgOpts:
+    o = L.PdhgOpts()
+    L.load().pdhg_default_opts(ctypes.byref(o))
+    for k, v in overrides.items():
+        if k not in OPTION_NAMES:
+            raise KeyError(f"unknown option {k}")
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": L.PDHG_FP64, "mixed": L.PDHG_MIXED}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Problem:
+    """An LP set up on the GPU.
+
+    `lp` has attributes m, n, row_ptr, col_idx, val, row_kind, b, c, l, u
+    (numpy arrays: host input, or torch CUDA tensors with device=True).
+    """
+
+    def __init__(self, lp, device: bool = False, stream=None, **opts):
+        import torch
+        lib = L.load()
+        self.m, self.n = int(lp.m), int(lp.n)
+        self.device = device
+        if device:
+            arrs = dict(row_ptr=lp.row_ptr, col_idx=lp.col_idx, val=lp.val,
+                        row_kind=lp.row_kind, b=lp.b, c=lp.c, l=lp.l, u=lp.u)
+            nnz = int(arrs["col_idx"].numel())
+        else:
+            arrs = dict(row_ptr=_host(lp.row_ptr, np.int32), col_idx=_host(lp.col_idx, np.int32),
+                        val=_host(lp.val, np.float64), row_kind=_host(lp.row_kind, np.uint8),
+                        b=_host(lp.b, np.float64), c=_host(lp.c, np.float64),
+                        l=_host(lp.l, np.float64), u=_host(lp.u, np.float64))
+            nnz = int(len(arrs["col_idx"]))
+        self._keep = arrs
+        self.nnz = nnz
+        self._lp = L.PdhgLP(self.m, self.n, nnz, *[_ptr(arrs[k]) for k in
+                            ("row_ptr", "col_idx", "val", "row_kind", "b", "c", "l", "u")],
+                            1 if device else 0)
+        self.opts = default_opts(**opts)
+        nbytes = ctypes.c_size_t()
+        L.check(lib.pdhg_workspace_bytes(ctypes.byref(self._lp), ctypes.byref(self.opts),
+                                         ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        L.check(lib.pdhg_setup(ctypes.byref(self._lp), ctypes.byref(self.opts),
+                               ctypes.c_void_p(self.workspace.data_ptr()),
+                               self.workspace_bytes, ctypes.c_void_p(stream.cuda_stream),
+                               ctypes.byref(h)))
+        self.handle = h
+        self._keep = None if not device else arrs
+
+    def solve(self, x0=None, y0=None, out=None):
+        """Returns (x, y, info dict); numpy arrays for host problems."""
+        lib = L.load()
+        if self.device:
+            import torch
+            x = torch.empty(self.n, dtype=torch.float64, device="cuda") if out is None else out[0]
+            y = torch.empty(self.m, dtype=torch.float64, device="cuda") if out is None else out[1]
+        else:
+            x = np.zeros(self.n) if out is None else out[0]
+            y = np.zeros(self.m) if out is None else out[1]
+            x0 = None if x0 is None else _host(x0, np.float64)
+            y0 = None if y0 is None else _host(y0, np.float64)
+        info = L.PdhgInfo()
+        L.check(lib.pdhg_solve(self.handle, _ptr(x0), _ptr(y0), _ptr(x), _ptr(y),
+                               ctypes.byref(info)))
+        return x, y, info.as_dict()
+
+    def export_setup(self) -> dict:
+        lib = L.load()
+        out = dict(var_kind=np.zeros(self.n, np.uint8), colptr=np.zeros(self.n + 1, np.int32),
+                   rowidx=np.zeros(self.nnz, np.int32), valT=np.zeros(self.nnz),
+                   val_s=np.zeros(self.nnz), Dr=np.zeros(self.m), Dc=np.zeros(self.n))
+        L.check(lib.pdhg_export_setup(self.handle, *[_ptr(out[k]) for k in
+                                      ("var_kind", "colptr", "rowidx", "valT", "val_s", "Dr", "Dc")]))
+        return out
+
+    def spmv(self, x, transpose: bool = False) -> np.ndarray:
+        lib = L.load()
+        x = _host(x, np.float64)
+        out = np.zeros(self.n if transpose else self.m)
+        L.check(lib.pdhg_spmv(self.handle, 1 if transpose else 0, _ptr(x), _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.load().pdhg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(lp, x0=None, y0=None, **opts):
+    p = Problem(lp, **opts)
+    try:
+        return p.solve(x0, y0)
+    finally:
+        p.close()

@@ -1,0 +1,123 @@
+"""The C ABI on the host: the library loads, exports every declared entry
+point, and rejects bad input before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2512_06715_amd import _lib as L
+from paper_2512_06715_amd import ucgen
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pdhg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdhg_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.SIGNATURES)
+
+
+def test_default_opts():
+    lib = L.load()
+    o = L.PdhgOpts()
+    lib.pdhg_default_opts(ctypes.byref(o))
+    assert o.tol == 1e-4 and o.eval_period == 64 and o.scaling_iters == 10
+    assert o.pock_chambolle == 1 and o.restart == 1 and o.use_average == 1
+    assert o.step_mode == 0 and o.precision == L.PDHG_FP64 and o.pw_theta == 0.5
+
+
+def _lp_struct(lp):
+    arrs = [np.ascontiguousarray(lp.row_ptr, np.int32), np.ascontiguousarray(lp.col_idx, np.int32),
+            np.ascontiguousarray(lp.val, np.float64), np.ascontiguousarray(lp.row_kind, np.uint8),
+            np.ascontiguousarray(lp.b, np.float64), np.ascontiguousarray(lp.c, np.float64),
+            np.ascontiguousarray(lp.l, np.float64), np.ascontiguousarray(lp.u, np.float64)]
+    s = L.PdhgLP(lp.m, lp.n, len(lp.col_idx), *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs], 0)
+    return s, arrs
+
+
+def _setup_rc(lp, opts=None):
+    lib = L.load()
+    s, keep = _lp_struct(lp)
+    o = L.PdhgOpts()
+    lib.pdhg_default_opts(ctypes.byref(o))
+    if opts:
+        for k, v in opts.items():
+            setattr(o, k, v)
+    # no workspace: input checks come first, and a valid LP stops at the
+    # workspace check (PDHG_ERR_OOM) before any device call
+    h = ctypes.c_void_p()
+    rc = lib.pdhg_setup(ctypes.byref(s), ctypes.byref(o), None, 0, None, ctypes.byref(h))
+    return rc, lib.pdhg_last_error().decode()
+
+
+def test_workspace_bytes_grows_with_size_and_precision():
+    lib = L.load()
+    out = []
+    for name in ("uc14_t24", "uc1000_t48"):
+        lp = ucgen.workload(name)
+        s, keep = _lp_struct(lp)
+        for prec in (L.PDHG_FP64, L.PDHG_MIXED):
+            o = L.PdhgOpts()
+            lib.pdhg_default_opts(ctypes.byref(o))
+            o.precision = prec
+            nb = ctypes.c_size_t()
+            assert lib.pdhg_workspace_bytes(ctypes.byref(s), ctypes.byref(o), ctypes.byref(nb)) == 0
+            out.append(nb.value)
+    assert out[0] < out[1] < out[3] and out[0] < out[2]
+    # FP64 bytes at least cover A and A' (12 bytes per nonzero each) and 16 vectors
+    lp = ucgen.workload("uc1000_t48")
+    assert out[2] >= 24 * lp.nnz + 8 * 16 * (lp.m + lp.n) // 2
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda lp: setattr(lp, "col_idx", np.where(np.arange(len(lp.col_idx)) == 1, lp.col_idx[0], lp.col_idx)), -2),
+    (lambda lp: setattr(lp, "row_ptr", np.concatenate([[1], lp.row_ptr[1:]]).astype(np.int32)), -2),
+    (lambda lp: setattr(lp, "row_kind", np.where(np.arange(lp.m) == 3, 2, lp.row_kind).astype(np.uint8)), -1),
+    (lambda lp: setattr(lp, "l", np.where(np.arange(lp.n) == 0, 5.0, lp.l)), -3),
+    (lambda lp: setattr(lp, "u", np.where(np.arange(lp.n) == 7, -np.inf, lp.u)), -3),
+    (lambda lp: setattr(lp, "val", np.where(np.arange(len(lp.val)) == 9, np.inf, lp.val)), -4),
+    (lambda lp: setattr(lp, "b", np.where(np.arange(lp.m) == 9, np.nan, lp.b)), -4),
+    (lambda lp: setattr(lp, "c", np.where(np.arange(lp.n) == 2, np.nan, lp.c)), -4),
+])
+def test_setup_rejects_bad_input_on_host(mutate, code, oracle_mod):
+    lp = ucgen.workload("uc14_t24").copy()
+    mutate(lp)
+    rc, msg = _setup_rc(lp)
+    assert rc == code, msg
+    assert msg
+    assert oracle_mod.validate(lp) == code   # same category as the oracle
+
+
+def test_setup_rejects_bad_options_and_small_workspace():
+    lp = ucgen.workload("uc14_t24")
+    assert _setup_rc(lp, dict(tol=0.0))[0] == -1
+    assert _setup_rc(lp, dict(eval_period=0))[0] == -1
+    assert _setup_rc(lp, dict(precision=7))[0] == -1
+    assert _setup_rc(lp, dict(pw_theta=2.0))[0] == -1
+    lib = L.load()
+    s, keep = _lp_struct(lp)
+    o = L.PdhgOpts()
+    lib.pdhg_default_opts(ctypes.byref(o))
+    buf = (ctypes.c_uint8 * 16)()
+    h = ctypes.c_void_p()
+    rc = lib.pdhg_setup(ctypes.byref(s), ctypes.byref(o), ctypes.cast(buf, ctypes.c_void_p), 16,
+                        None, ctypes.byref(h))
+    assert rc == -5
+
+
+def test_shape_errors():
+    lp = ucgen.workload("uc14_t24").copy()
+    assert _setup_rc(lp)[0] == -5     # valid LP, no workspace
+    lp.m = 0
+    assert _setup_rc(lp)[0] == -1
