@@ -1,0 +1,211 @@
+"""Benchmark: restarted PDHG on the 6717-bus-shaped UC LP relaxation.
+
+One step = one full pdhg_solve from a cold start to relative KKT 1e-4 on the
+seeded synthetic 6717-bus, 96-period UC LP (3.22M variables, 2.03M rows,
+7.19M nonzeros), with the problem already resident in HBM.  value = PDHG
+attempts per second over the timed solves (one attempt = one A'y and one Ax
+product); ms_per_step = time to 1e-4.
+
+Also reported: a live HIP-event timing of the dominant kernel against its
+algorithmic bytes (roofline), and the FP64 CPU oracle timed on a bounded
+sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PDHG iters/s + time-to-1e-4 KKT (6717-bus UC LP); batched LPs/s; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(kind: str, m: int, n: int, nnz: int, vb: int) -> int:
+    """Algorithmic HBM bytes of one launch (each array element moved once).
+
+    vb = bytes per matrix value and per iterate element (8 FP64, 4 FP32).
+    dual:   row pointers 4(m+1), columns 4 nnz, values vb nnz, gather x' vb n,
+            read y, Ax, b (3 vb m) and the row kind (m), write y', Ax' (2 vb m),
+            fold the accepted y into the running sum (read + write, 2 vb m).
+    primal: column pointers 4(n+1), rows 4 nnz, values vb nnz, gather y vb m,
+            read x, c, l, u (4 vb n), write x' (vb n), fold x into the sum (2 vb n).
+    """
+    if kind == "dual":
+        return 4 * (m + 1) + (4 + vb) * nnz + vb * n + 3 * vb * m + m + 2 * vb * m + 2 * vb * m
+    if kind == "primal":
+        return 4 * (n + 1) + (4 + vb) * nnz + vb * m + 4 * vb * n + vb * n + 2 * vb * n
+    raise ValueError(kind)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("iterate.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2512_06715_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(lp, sample_lo: int, sample_hi: int):
+    """Oracle attempts/s from two capped runs (difference removes setup)."""
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.pdhg(lp, tol=1e-4, max_iter=sample_lo)
+    t1 = time.perf_counter()
+    oracle.pdhg(lp, tol=1e-4, max_iter=sample_hi)
+    t2 = time.perf_counter()
+    per_attempt = ((t2 - t1) - (t1 - t0)) / (sample_hi - sample_lo)
+    return dict(value=1.0 / per_attempt, unit="attempts/s", cores=1, kind="oracle",
+                sample=f"FP64 oracle PDHG, {sample_hi - sample_lo} attempts "
+                       f"(runs capped at {sample_lo} and {sample_hi} attempts, difference), "
+                       f"same LP, single thread; {t2 - t0:.1f}s of CPU work")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="uc6717_t96")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--max-iter", type=int, default=2_000_000)
+    ap.add_argument("--kernel-attempts", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", default="64,192")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this solver has no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2512_06715_amd import ucgen
+    from paper_2512_06715_amd.solver import Problem
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {src.numel() * 8} bytes read and written per launch",
+              file=sys.stderr, flush=True)
+        del src, dst
+
+    lp = ucgen.workload(args.workload)
+    print(f"[bench] {args.workload}: {ucgen.describe(lp)}", file=sys.stderr, flush=True)
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).cuda()
+
+    class DevLP:
+        m, n = lp.m, lp.n
+        row_ptr = dev(lp.row_ptr, torch.int32)
+        col_idx = dev(lp.col_idx, torch.int32)
+        val = dev(lp.val, torch.float64)
+        row_kind = dev(lp.row_kind, torch.uint8)
+        b = dev(lp.b, torch.float64)
+        c = dev(lp.c, torch.float64)
+        l = dev(lp.l, torch.float64)
+        u = dev(lp.u, torch.float64)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob = Problem(DevLP, device=True, tol=args.tol, max_iter=args.max_iter,
+                   precision=args.precision)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] setup {setup_s:.3f}s", file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        _, _, info = prob.solve()
+        print(f"[bench] warmup {w}: {info['attempts']} attempts, {info['solve_s']:.2f}s, "
+              f"{info['status_name']}", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for s in range(args.steps):
+        _, _, info = prob.solve()
+        infos.append(info)
+        print(f"[bench] step {s}: {info['attempts']} attempts, {info['solve_s']:.2f}s, "
+              f"{info['status_name']} kkt={info['rel_kkt']:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    attempts = sum(i["attempts"] for i in infos)
+
+    # live per-kernel timing on the library stream
+    kt = prob.time_kernels(args.kernel_attempts)
+    vb = 8 if args.precision == "fp64" else 4
+    dom = "dual" if kt["dual"] >= kt["primal"] else "primal"
+    nbytes = kernel_bytes(dom, lp.m, lp.n, lp.nnz, vb)
+    achieved = nbytes / (kt[dom] * 1e-3) / 1e9
+    kname = f"k_{dom}"
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=load_traffic(kname, args.workload, args.precision),
+                    kernel=kname, ms_per_launch=round(kt[dom], 5),
+                    algorithmic_bytes_per_launch=nbytes,
+                    kernel_ms=dict((k, round(v, 5)) for k, v in kt.items()))
+    prob.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        lo, hi = (int(v) for v in args.cpu_sample.split(","))
+        print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(lp, lo, hi)
+
+    last = infos[-1]
+    out = dict(
+        metric=METRIC,
+        value=round(attempts / elapsed, 1),
+        unit="attempts/s",
+        n_gpus=1,
+        steps=args.steps,
+        warmup=args.warmup,
+        ms_per_step=round(1e3 * elapsed / args.steps, 2),
+        higher_is_better=True,
+        scaling="weak",
+        vs_baseline=None,
+        dtype="f64" if args.precision == "fp64" else "f32+f64",
+        data="synthetic",
+        config=dict(workload=f"{args.workload} (seeded DC-UC LP relaxation, 6717 buses, "
+                             f"1100 units, 9000 lines, 96 periods)",
+                    m=lp.m, n=lp.n, nnz=lp.nnz, tol=args.tol, precision=args.precision),
+        time_to_tol_s=round(elapsed / args.steps, 3),
+        attempts_per_solve=last["attempts"],
+        status=last["status_name"],
+        rel_kkt=last["rel_kkt"],
+        primal_obj=last["primal_obj"],
+        setup_s=round(setup_s, 3),
+        roofline=roofline,
+        cpu_baseline=cpu,
+    )
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

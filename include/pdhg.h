@@ -174,6 +174,14 @@ int pdhg_export_setup(pdhg_handle *h, uint8_t *var_kind, int32_t *colptr,
  * memory. */
 int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out);
 
+/* Run `attempts` more attempts from the handle's current iterate (the state
+ * the last pdhg_solve left) with HIP events around each kernel on the
+ * library's stream, and report average milliseconds per launch:
+ * ms_out[0] primal step (A'y row-dot + projection, long columns included),
+ * ms_out[1] dual step (Ax row-dot + projection, long rows included),
+ * ms_out[2] step control, ms_out[3] whole attempt.  Precision as set up. */
+int pdhg_time_kernels(pdhg_handle *h, int attempts, double *ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,6 +70,7 @@ SIGNATURES = {
     "pdhg_last_error": (ctypes.c_char_p, []),
     "pdhg_export_setup": (c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
     "pdhg_spmv": (c_int, [vp, c_int, vp, vp]),
+    "pdhg_time_kernels": (c_int, [vp, c_int, ctypes.POINTER(c_dbl)]),
 }
 
 _lib = None

@@ -733,3 +733,44 @@ int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out) {
 }
 
 }  // extern "C"
+
+namespace {
+template <typename T>
+int time_kernels(pdhg_handle *h, int attempts, double *ms) {
+  IterView<T> w = iter_view<T>(h);
+  hipEvent_t ev[4];
+  for (auto &e : ev) HC(hipEventCreate(&e));
+  double acc[4] = {0, 0, 0, 0};
+  for (int a = 0; a < attempts; a++) {
+    HC(hipEventRecord(ev[0], h->hs));
+    launch_primal<T>(w, h->st, h->hs);
+    HC(hipEventRecord(ev[1], h->hs));
+    launch_dual<T>(w, h->st, h->hs);
+    HC(hipEventRecord(ev[2], h->hs));
+    launch_control<T>(w, h->st, h->hs);
+    HC(hipEventRecord(ev[3], h->hs));
+    HK();
+    HC(hipEventSynchronize(ev[3]));
+    float t;
+    for (int q = 0; q < 3; q++) {
+      HC(hipEventElapsedTime(&t, ev[q], ev[q + 1]));
+      acc[q] += t;
+    }
+    HC(hipEventElapsedTime(&t, ev[0], ev[3]));
+    acc[3] += t;
+  }
+  for (auto &e : ev) HC(hipEventDestroy(e));
+  for (int q = 0; q < 4; q++) ms[q] = acc[q] / attempts;
+  return PDHG_OK;
+}
+}  // namespace
+
+extern "C" int pdhg_time_kernels(pdhg_handle *h, int attempts, double *ms_out) {
+  if (!h || !ms_out || attempts < 1) return fail(PDHG_ERR_ARG, "bad argument");
+  int rc = enter(h);
+  if (rc) return rc;
+  rc = h->o.precision == PDHG_MIXED ? time_kernels<float>(h, attempts, ms_out)
+                                    : time_kernels<double>(h, attempts, ms_out);
+  if (rc) return rc;
+  return leave(h);
+}

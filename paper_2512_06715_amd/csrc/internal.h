@@ -104,6 +104,12 @@ void launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 template <typename T>
 void launch_attempt(const IterView<T> &w, CtlState *st, int64_t max_iter, hipStream_t s);
 template <typename T>
+void launch_primal(const IterView<T> &w, CtlState *st, hipStream_t s);
+template <typename T>
+void launch_dual(const IterView<T> &w, CtlState *st, hipStream_t s);
+template <typename T>
+void launch_control(const IterView<T> &w, CtlState *st, hipStream_t s);
+template <typename T>
 void launch_evaluate_ll(const EvalView<T> &e, const int32_t *long_rows, int n_long_rows,
                         const int32_t *long_cols, int n_long_cols, CtlState *st, double tol,
                         int64_t max_iter, hipStream_t s);

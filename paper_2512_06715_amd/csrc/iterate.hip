@@ -648,13 +648,28 @@ __global__ void k_spmv_plain(const int32_t *__restrict__ rp, const int32_t *__re
 // launchers
 
 template <typename T>
-void launch_attempt(const IterView<T> &w, CtlState *st, int64_t, hipStream_t s) {
+void launch_primal(const IterView<T> &w, CtlState *st, hipStream_t s) {
   k_primal<T><<<w.nblk_cols, PDHG_BLOCK, 0, s>>>(w, st);
   if (w.n_long_cols) k_primal_long<T><<<w.n_long_cols, PDHG_BLOCK, 0, s>>>(w, st);
+}
+
+template <typename T>
+void launch_dual(const IterView<T> &w, CtlState *st, hipStream_t s) {
   k_dual<T><<<w.nblk_rows, PDHG_BLOCK, 0, s>>>(w, st);
   if (w.n_long_rows) k_dual_long<T><<<w.n_long_rows, PDHG_BLOCK, 0, s>>>(w, st);
+}
+
+template <typename T>
+void launch_control(const IterView<T> &w, CtlState *st, hipStream_t s) {
   k_control<<<1, PDHG_BLOCK, 0, s>>>(w.part_dx2, w.nblk_cols + w.n_long_cols, w.part_dy,
                                      w.nblk_rows + w.n_long_rows, w.adaptive, st);
+}
+
+template <typename T>
+void launch_attempt(const IterView<T> &w, CtlState *st, int64_t, hipStream_t s) {
+  launch_primal<T>(w, st, s);
+  launch_dual<T>(w, st, s);
+  launch_control<T>(w, st, s);
 }
 
 // The evaluation needs the long-row lists too; they are passed through the
@@ -742,6 +757,9 @@ void launch_spmv(const int32_t *rp, const int32_t *ci, const double *v, int64_t 
 
 #define INST(T)                                                                               \
   template void launch_attempt<T>(const IterView<T> &, CtlState *, int64_t, hipStream_t);    \
+  template void launch_primal<T>(const IterView<T> &, CtlState *, hipStream_t);              \
+  template void launch_dual<T>(const IterView<T> &, CtlState *, hipStream_t);                \
+  template void launch_control<T>(const IterView<T> &, CtlState *, hipStream_t);             \
   template void launch_evaluate_ll<T>(const EvalView<T> &, const int32_t *, int,              \
                                       const int32_t *, int, CtlState *, double, int64_t,      \
                                       hipStream_t);                                           \

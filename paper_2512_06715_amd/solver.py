@@ -117,6 +117,13 @@ class Problem:
         L.check(lib.pdhg_spmv(self.handle, 1 if transpose else 0, _ptr(x), _ptr(out)))
         return out
 
+    def time_kernels(self, attempts: int = 200) -> dict:
+        """Average ms per launch of the attempt kernels, timed with HIP events."""
+        lib = L.load()
+        ms = (ctypes.c_double * 4)()
+        L.check(lib.pdhg_time_kernels(self.handle, int(attempts), ms))
+        return dict(primal=ms[0], dual=ms[1], control=ms[2], attempt=ms[3])
+
     def close(self):
         if getattr(self, "handle", None):
             L.load().pdhg_destroy(self.handle)
