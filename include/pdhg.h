@@ -97,6 +97,7 @@ typedef struct {
   double polish_tol;      /* mixed precision: FP32 phase stops at this KKT (default tol) */
   int pw_update;          /* 1 (default): primal weight updated at restarts; 0: kept */
   double pw_theta;        /* smoothing of the primal-weight update in log space (default 0.5) */
+  int tiles_per_block;    /* SpMV partition: 256-row tiles per workgroup; 0 = automatic */
 } pdhg_opts;
 
 typedef struct {

@@ -33,7 +33,7 @@ class PdhgOpts(ctypes.Structure):
                 ("pock_chambolle", c_int), ("restart", c_int), ("use_average", c_int),
                 ("unroll_iters", c_i64), ("checkpoint_every", c_i64), ("use_graph", c_int),
                 ("verbose", c_int), ("polish_tol", c_dbl), ("pw_update", c_int),
-                ("pw_theta", c_dbl)]
+                ("pw_theta", c_dbl), ("tiles_per_block", c_int)]
 
 
 class PdhgInfo(ctypes.Structure):

@@ -74,6 +74,7 @@ struct pdhg_handle {
   CtlState *st;
   int *err;
   int n_long_rows = 0, n_long_cols = 0, nblk_rows = 0, nblk_cols = 0;
+  int tpb_rows = 1, tpb_cols = 1, grid_rows = 1, grid_cols = 1;
   CtlState *host_st = nullptr;
 
   struct Graph {
@@ -162,6 +163,7 @@ int check_opts(const pdhg_opts *o) {
   if (o->scaling_iters < 0) return fail(PDHG_ERR_ARG, "scaling_iters must be >= 0");
   if (o->unroll_iters < 0) return fail(PDHG_ERR_ARG, "unroll_iters must be >= 0");
   if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return fail(PDHG_ERR_ARG, "pw_theta must be in [0, 1]");
+  if (o->tiles_per_block < 0) return fail(PDHG_ERR_ARG, "tiles_per_block must be >= 0");
   return PDHG_OK;
 }
 
@@ -263,6 +265,10 @@ IterView<double> iter_view<double>(pdhg_handle *h) {
   w.long_cols = h->long_cols;
   w.n_long_rows = h->n_long_rows;
   w.n_long_cols = h->n_long_cols;
+  w.tpb_rows = h->tpb_rows;
+  w.tpb_cols = h->tpb_cols;
+  w.grid_rows = h->grid_rows;
+  w.grid_cols = h->grid_cols;
   w.part_dx2 = h->part_dx2;
   w.part_dy = h->part_dy;
   w.adaptive = h->o.step_mode == 0;
@@ -299,6 +305,10 @@ IterView<float> iter_view<float>(pdhg_handle *h) {
   w.long_cols = h->long_cols;
   w.n_long_rows = h->n_long_rows;
   w.n_long_cols = h->n_long_cols;
+  w.tpb_rows = h->tpb_rows;
+  w.tpb_cols = h->tpb_cols;
+  w.grid_rows = h->grid_rows;
+  w.grid_cols = h->grid_cols;
   w.part_dx2 = h->part_dx2;
   w.part_dy = h->part_dy;
   w.adaptive = h->o.step_mode == 0;
@@ -383,8 +393,11 @@ int capture_block(pdhg_handle *h, int slot, int period, double tol, int64_t max_
 
 // Run attempts in blocks until the device reports done; the start point must
 // already be initialised (launch_init_point) or carried over.
+// stall_evals > 0: return with *status_out = 0 when the reported relative KKT
+// error has not dropped below 0.9 of its best value for that many evaluations.
 template <typename T>
-int run_blocks(pdhg_handle *h, double tol, int64_t max_iter, double t_start, int *status_out) {
+int run_blocks(pdhg_handle *h, double tol, int64_t max_iter, double t_start, int *status_out,
+               int stall_evals = 0) {
   IterView<T> w = iter_view<T>(h);
   EvalView<T> e = eval_view<T>(h);
   const int slot = sizeof(T) == 4 ? 1 : 0;
@@ -394,6 +407,8 @@ int run_blocks(pdhg_handle *h, double tol, int64_t max_iter, double t_start, int
   HK();
   int rc = read_state(h);
   if (rc) return rc;
+  double best = h->host_st->rel_kkt;
+  int since = 0;
   while (!h->host_st->done) {
     int64_t k = h->host_st->k;
     int64_t nb = std::min<int64_t>(P, max_iter - k);
@@ -418,6 +433,13 @@ int run_blocks(pdhg_handle *h, double tol, int64_t max_iter, double t_start, int
               s->restarts);
     if (!s->done && now_s() - t_start > h->o.time_limit_s) {
       *status_out = PDHG_TIME_LIMIT;
+      return PDHG_OK;
+    }
+    if (s->rel_kkt < 0.9 * best) {
+      best = s->rel_kkt;
+      since = 0;
+    } else if (stall_evals > 0 && ++since >= stall_evals && !s->done) {
+      *status_out = 0;
       return PDHG_OK;
     }
   }
@@ -581,6 +603,14 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
       if (hp[j + 1] - hp[j] > PDHG_LONG_SEG) lc.push_back((int32_t)j);
     h->n_long_rows = (int)lr.size();
     h->n_long_cols = (int)lc.size();
+    h->tpb_rows = h->o.tiles_per_block > 0
+                      ? h->o.tiles_per_block
+                      : std::max(1, (h->nblk_rows + PDHG_TARGET_GROUPS - 1) / PDHG_TARGET_GROUPS);
+    h->tpb_cols = h->o.tiles_per_block > 0
+                      ? h->o.tiles_per_block
+                      : std::max(1, (h->nblk_cols + PDHG_TARGET_GROUPS - 1) / PDHG_TARGET_GROUPS);
+    h->grid_rows = h->n_long_rows + (h->nblk_rows + h->tpb_rows - 1) / h->tpb_rows;
+    h->grid_cols = h->n_long_cols + (h->nblk_cols + h->tpb_cols - 1) / h->tpb_cols;
     if (!lr.empty())
       HC(hipMemcpyAsync(h->long_rows, lr.data(), sizeof(int32_t) * lr.size(), hipMemcpyHostToDevice,
                         h->hs));
@@ -631,22 +661,46 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, do
     }
   }
   int status = 0;
+  bool final_fp32 = false;
+  int64_t attempts_fp32 = 0;
+  EvalView<double> e = eval_view<double>(h);
   if (h->o.precision == PDHG_FP64) {
-    EvalView<double> e = eval_view<double>(h);
     launch_init_point<double>(e, h->long_rows, h->n_long_rows, dx0, dy0, h->st, h->AXA, h->hs);
     HK();
     rc = run_blocks<double>(h, h->o.tol, h->o.max_iter, t0, &status);
     if (rc) return rc;
   } else {
-    return fail(PDHG_ERR_ARG, "mixed precision not available in this build");
+    // FP32 phase: FP32 matrix, iterates and SpMVs; FP64 evaluation and control
+    EvalView<float> ef = eval_view<float>(h);
+    double tol32 = h->o.polish_tol > h->o.tol ? h->o.polish_tol : h->o.tol;
+    launch_init_point<float>(ef, h->long_rows, h->n_long_rows, dx0, dy0, h->st, h->AXA, h->hs);
+    HK();
+    rc = run_blocks<float>(h, tol32, h->o.max_iter, t0, &status, 300);
+    if (rc) return rc;
+    attempts_fp32 = h->host_st->k;
+    final_fp32 = true;
+    bool polish = (status == 0) || (status == PDHG_OPTIMAL && tol32 > h->o.tol);
+    if (polish) {
+      // FP64 refinement from the FP32 iterate
+      launch_switch_to_fp64(ef, e, h->long_rows, h->n_long_rows, h->st, h->hs);
+      HK();
+      rc = run_blocks<double>(h, h->o.tol, h->o.max_iter, t0, &status);
+      if (rc) return rc;
+      final_fp32 = false;
+    }
   }
   // unscale into the caller's arrays
-  EvalView<double> e = eval_view<double>(h);
   if (h->on_device) {
-    launch_unscale<double>(e, h->st, x, y, h->hs);
+    if (final_fp32)
+      launch_unscale<float>(eval_view<float>(h), h->st, x, y, h->hs);
+    else
+      launch_unscale<double>(e, h->st, x, y, h->hs);
     HK();
   } else {
-    launch_unscale<double>(e, h->st, h->ATYA, h->AXA, h->hs);
+    if (final_fp32)
+      launch_unscale<float>(eval_view<float>(h), h->st, h->ATYA, h->AXA, h->hs);
+    else
+      launch_unscale<double>(e, h->st, h->ATYA, h->AXA, h->hs);
     HK();
     HC(hipMemcpyAsync(x, h->ATYA, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->hs));
     HC(hipMemcpyAsync(y, h->AXA, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->hs));
@@ -657,6 +711,7 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, do
   info->status = status;
   info->which = s->which;
   info->attempts = s->k;
+  info->attempts_fp32 = attempts_fp32;
   info->accepted = s->accepted;
   info->restarts = s->restarts;
   info->primal_obj = s->pobj;

@@ -6,6 +6,8 @@
 #define PDHG_BLOCK 256
 // rows / columns longer than this are handled by a workgroup each
 #define PDHG_LONG_SEG 64
+// tile groups per launch above which a workgroup takes several tiles
+#define PDHG_TARGET_GROUPS 65536
 // columns longer than this are sorted with a workgroup during the transpose
 #define PDHG_SORT_SHORT 32
 
@@ -34,7 +36,7 @@ struct CtlState {
   int done, status, which;
   int restart_flag;       // 0 none, 1 restart at current, 2 restart to average
   int have_avg;
-  int pad;
+  int init_pending;       // 1: the next evaluation records the restart reference
 };
 
 // One precision's view of the scaled problem and iterates.
@@ -47,11 +49,13 @@ struct IterView {
   const uint8_t *kind, *vk;
   T *X[2], *Y[2], *AX[2];
   T *XS, *YS;
-  int nblk_rows, nblk_cols;      // short-segment blocks
+  int nblk_rows, nblk_cols;      // 256-row tiles
   const int32_t *long_rows, *long_cols;
   int n_long_rows, n_long_cols;
-  double *part_dx2;              // [nblk_cols + n_long_cols]
-  double *part_dy;               // [2 * (nblk_rows + n_long_rows)]
+  int tpb_rows, tpb_cols;        // tiles per workgroup
+  int grid_rows, grid_cols;      // long segments + tile groups
+  double *part_dx2;              // [grid_cols]
+  double *part_dy;               // [2 * grid_rows]
   int adaptive;
 };
 
@@ -117,6 +121,9 @@ template <typename T>
 void launch_init_point(const EvalView<T> &e, const int32_t *long_rows, int n_long_rows,
                        const double *x0, const double *y0, CtlState *st, double *ax_tmp,
                        hipStream_t s);
+void launch_switch_to_fp64(const EvalView<float> &ef, const EvalView<double> &ed,
+                           const int32_t *long_rows, int n_long_rows, CtlState *st,
+                           hipStream_t s);
 template <typename T>
 void launch_unscale(const EvalView<T> &e, const CtlState *st, double *x, double *y,
                     hipStream_t s);

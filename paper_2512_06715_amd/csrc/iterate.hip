@@ -37,9 +37,9 @@ __device__ inline T clamp_box(T x, T lo, T hi) {
 
 // Deterministic block reduction of NQ doubles (fixed shuffle tree, then the
 // four waves in order).  Bit q of maxmask selects max instead of sum.
-template <int NQ>
+template <int NQ, int BS = PDHG_BLOCK>
 __device__ inline void block_reduce(double (&v)[NQ], unsigned maxmask, double *out) {
-  __shared__ double lds[PDHG_BLOCK / 64][NQ];
+  __shared__ double lds[BS / 64][NQ];
 #pragma unroll
   for (int q = 0; q < NQ; q++) {
     double a = v[q];
@@ -60,7 +60,7 @@ __device__ inline void block_reduce(double (&v)[NQ], unsigned maxmask, double *o
 #pragma unroll
     for (int q = 0; q < NQ; q++) {
       double a = lds[0][q];
-      for (int w = 1; w < PDHG_BLOCK / 64; w++)
+      for (int w = 1; w < BS / 64; w++)
         a = ((maxmask >> q) & 1) ? fmax(a, lds[w][q]) : a + lds[w][q];
       out[q] = a;
     }
@@ -68,56 +68,129 @@ __device__ inline void block_reduce(double (&v)[NQ], unsigned maxmask, double *o
   __syncthreads();
 }
 
-// Sum (or max) of `cnt` partials with stride `stride`, one workgroup, fixed order.
-template <int NQ>
+// Sum (or max) of `cnt` partials with stride `stride`, one workgroup of BS
+// threads, fixed order.
+#define CTL_BLOCK 1024
+template <int NQ, int BS = CTL_BLOCK>
 __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t stride,
                                        unsigned maxmask, double *out) {
   double v[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; q++) v[q] = 0.0;
-  for (int64_t b = threadIdx.x; b < cnt; b += PDHG_BLOCK) {
+#pragma unroll 8
+  for (int64_t b = threadIdx.x; b < cnt; b += BS) {
 #pragma unroll
     for (int q = 0; q < NQ; q++) {
       double a = p[q * stride + b];
       v[q] = ((maxmask >> q) & 1) ? fmax(v[q], a) : v[q] + a;
     }
   }
-  block_reduce<NQ>(v, maxmask, out);
+  block_reduce<NQ, BS>(v, maxmask, out);
 }
 
 // ---------------------------------------------------------------------------
 // attempt kernels
+//
+// Both SpMV-fused kernels walk 256-row tiles of a CSR matrix (A for the dual
+// step, the stored A' for the primal step).  A tile's nonzeros are one
+// contiguous range, so the workgroup streams column indices and values with
+// consecutive lanes on consecutive nonzeros (coalesced), forms the products
+// with the gathered vector into LDS, and each lane then sums its own row from
+// LDS in CSR order.  Tiles whose nonzeros do not fit the LDS buffer fall back
+// to one lane per row.  Rows longer than PDHG_LONG_SEG get a workgroup each
+// (the first blocks of the grid).  Each workgroup covers `tpb` consecutive
+// tiles and writes one partial per reduced quantity.
+
+#define TILE_CAP 2048
+
+// Streams read exactly once per launch bypass the cache hierarchy's reuse
+// policy so that L2 keeps the gathered vector windows.
+template <typename T>
+__device__ inline T ld_stream(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+
+// Row dot products of one 256-row tile: s = sum_k v[k] x[idx[k]] over row
+// r0 + threadIdx.x.  rs/re are the row's bounds (already loaded).
+template <typename T>
+__device__ inline T tile_rowdot(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                const T *__restrict__ v, const T *__restrict__ x, int64_t nrows,
+                                int64_t r0, int rs, int re, bool mine, T *lds) {
+  int64_t rend = r0 + PDHG_BLOCK < nrows ? r0 + PDHG_BLOCK : nrows;
+  int base = ptr[r0], top = ptr[rend];
+  int cnt = top - base;
+  T acc = 0;
+  if (cnt <= TILE_CAP) {
+    for (int k = threadIdx.x; k < cnt; k += PDHG_BLOCK)
+      lds[k] = ld_stream(v + base + k) * x[ld_stream(idx + base + k)];
+    __syncthreads();
+    if (mine)
+      for (int k = rs - base; k < re - base; k++) acc += lds[k];
+    __syncthreads();
+  } else if (mine) {
+    for (int k = rs; k < re; k++) acc += v[k] * x[idx[k]];
+  }
+  return acc;
+}
 
 template <typename T>
-__device__ inline void primal_update(const IterView<T> &w, int64_t j, T t, T tau, const T *x,
-                                     T *xn, double pend, int fresh, double &d2) {
-  T xj = x[j];
-  T xv = clamp_box<T>(xj - tau * (w.c[j] - t), w.l[j], w.u[j]);
+__device__ inline void primal_finish(const IterView<T> &w, int64_t j, T t, T tau, T xj, T cj, T lj,
+                                     T uj, T xsj, T *xn, double pend, int fresh, double &d2) {
+  T xv = clamp_box<T>(xj - tau * (cj - t), lj, uj);
   xn[j] = xv;
   double d = (double)xv - (double)xj;
-  d2 = d * d;
-  if (pend > 0.0) w.XS[j] = (fresh ? (T)0 : w.XS[j]) + (T)pend * xj;
+  d2 += d * d;
+  if (pend > 0.0) w.XS[j] = (fresh ? (T)0 : xsj) + (T)pend * xj;
 }
 
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(IterView<T> w, const CtlState *st) {
+  __shared__ T lds[TILE_CAP];
   int lb = xcd_remap(blockIdx.x, gridDim.x);
-  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   const int cur = st->cur;
   const T tau = (T)(st->eta / st->omega);
   const double pend = st->pending;
   const int fresh = st->fresh;
+  const bool fold_read = pend > 0.0 && !fresh;
   const T *__restrict__ x = w.X[cur];
   T *__restrict__ xn = w.X[cur ^ 1];
   const T *__restrict__ y = w.Y[cur];
   double d2[1] = {0.0};
-  if (j < w.n) {
+  if (lb < w.n_long_cols) {
+    int64_t j = w.long_cols[lb];
     int s = w.cp[j], e = w.cp[j + 1];
-    if (e - s <= PDHG_LONG_SEG) {
-      T t = 0;
-      for (int k = s; k < e; k++) t += w.vt[k] * y[w.ri[k]];
-      primal_update(w, j, t, tau, x, xn, pend, fresh, d2[0]);
+    double acc[1] = {0.0};
+    for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)(w.vt[k] * y[w.ri[k]]);
+    double tot[1];
+    block_reduce<1>(acc, 0u, tot);
+    if (threadIdx.x == 0) {
+      double dd = 0.0;
+      primal_finish(w, j, (T)tot[0], tau, x[j], w.c[j], w.l[j], w.u[j], fold_read ? w.XS[j] : (T)0,
+                    xn, pend, fresh, dd);
+      w.part_dx2[lb] = dd;
     }
+    return;
+  }
+  int64_t t0 = (int64_t)(lb - w.n_long_cols) * w.tpb_cols;
+  int64_t ntiles = (w.n + PDHG_BLOCK - 1) / PDHG_BLOCK;
+  int64_t t1 = t0 + w.tpb_cols < ntiles ? t0 + w.tpb_cols : ntiles;
+  for (int64_t t = t0; t < t1; t++) {
+    int64_t j = t * PDHG_BLOCK + threadIdx.x;
+    bool valid = j < w.n;
+    int rs = 0, re = 0;
+    T xj = 0, cj = 0, lj = 0, uj = 0, xsj = 0;
+    if (valid) {  // issue the column's own loads before the SpMV phase
+      rs = w.cp[j];
+      re = w.cp[j + 1];
+      xj = x[j];
+      cj = ld_stream(w.c + j);
+      lj = ld_stream(w.l + j);
+      uj = ld_stream(w.u + j);
+      if (fold_read) xsj = w.XS[j];
+    }
+    bool mine = valid && (re - rs <= PDHG_LONG_SEG);
+    T s = tile_rowdot<T>(w.cp, w.ri, w.vt, y, w.n, t * PDHG_BLOCK, rs, re, mine, lds);
+    if (mine) primal_finish(w, j, s, tau, xj, cj, lj, uj, xsj, xn, pend, fresh, d2[0]);
   }
   double out[1];
   block_reduce<1>(d2, 0u, out);
@@ -125,89 +198,83 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(IterView<T> w, const CtlS
 }
 
 template <typename T>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_primal_long(IterView<T> w, const CtlState *st) {
-  int64_t j = w.long_cols[blockIdx.x];
-  const int cur = st->cur;
-  const T tau = (T)(st->eta / st->omega);
-  const T *__restrict__ y = w.Y[cur];
-  int s = w.cp[j], e = w.cp[j + 1];
-  double acc[1] = {0.0};
-  for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)(w.vt[k] * y[w.ri[k]]);
-  double tot[1];
-  block_reduce<1>(acc, 0u, tot);
-  if (threadIdx.x == 0) {
-    double d2 = 0.0;
-    primal_update(w, j, (T)tot[0], tau, w.X[cur], w.X[cur ^ 1], st->pending, st->fresh, d2);
-    w.part_dx2[w.nblk_cols + blockIdx.x] = d2;
-  }
-}
-
-template <typename T>
-__device__ inline void dual_update(const IterView<T> &w, int64_t i, T s, T sigma, int cur,
-                                   double pend, int fresh, double &dy2, double &inter) {
-  const T *y = w.Y[cur];
-  T axi = w.AX[cur][i], yi = y[i];
-  T yv = yi + sigma * (w.b[i] - (s + s - axi));
-  if (w.kind[i] == 1 && yv < (T)0) yv = (T)0;
+__device__ inline void dual_finish(const IterView<T> &w, int64_t i, T s, T sigma, int cur, T yi,
+                                   T axi, T bi, uint8_t ki, T ysi, double pend, int fresh,
+                                   double &dy2, double &inter) {
+  T yv = yi + sigma * (bi - (s + s - axi));
+  if (ki == 1 && yv < (T)0) yv = (T)0;
   w.Y[cur ^ 1][i] = yv;
   w.AX[cur ^ 1][i] = s;
   double dy = (double)yv - (double)yi;
-  dy2 = dy * dy;
-  inter = dy * ((double)s - (double)axi);
-  if (pend > 0.0) w.YS[i] = (fresh ? (T)0 : w.YS[i]) + (T)pend * yi;
+  dy2 += dy * dy;
+  inter += dy * ((double)s - (double)axi);
+  if (pend > 0.0) w.YS[i] = (fresh ? (T)0 : ysi) + (T)pend * yi;
 }
 
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(IterView<T> w, const CtlState *st) {
+  __shared__ T lds[TILE_CAP];
   int lb = xcd_remap(blockIdx.x, gridDim.x);
-  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   const int cur = st->cur;
   const T sigma = (T)(st->eta * st->omega);
   const double pend = st->pending;
   const int fresh = st->fresh;
+  const bool fold_read = pend > 0.0 && !fresh;
   const T *__restrict__ xn = w.X[cur ^ 1];
-  double v[2] = {0.0, 0.0};
-  if (i < w.m) {
+  const T *__restrict__ y = w.Y[cur];
+  const T *__restrict__ ax = w.AX[cur];
+  const int64_t G = gridDim.x;
+  if (lb < w.n_long_rows) {
+    int64_t i = w.long_rows[lb];
     int s = w.rp[i], e = w.rp[i + 1];
-    if (e - s <= PDHG_LONG_SEG) {
-      T acc = 0;
-      for (int k = s; k < e; k++) acc += w.v[k] * xn[w.ci[k]];
-      dual_update(w, i, acc, sigma, cur, pend, fresh, v[0], v[1]);
+    double acc[1] = {0.0};
+    for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)(w.v[k] * xn[w.ci[k]]);
+    double tot[1];
+    block_reduce<1>(acc, 0u, tot);
+    if (threadIdx.x == 0) {
+      double dy2 = 0.0, inter = 0.0;
+      dual_finish(w, i, (T)tot[0], sigma, cur, y[i], ax[i], w.b[i], w.kind[i],
+                  fold_read ? w.YS[i] : (T)0, pend, fresh, dy2, inter);
+      w.part_dy[lb] = dy2;
+      w.part_dy[G + lb] = inter;
     }
+    return;
+  }
+  double v[2] = {0.0, 0.0};
+  int64_t t0 = (int64_t)(lb - w.n_long_rows) * w.tpb_rows;
+  int64_t ntiles = (w.m + PDHG_BLOCK - 1) / PDHG_BLOCK;
+  int64_t t1 = t0 + w.tpb_rows < ntiles ? t0 + w.tpb_rows : ntiles;
+  for (int64_t t = t0; t < t1; t++) {
+    int64_t i = t * PDHG_BLOCK + threadIdx.x;
+    bool valid = i < w.m;
+    int rs = 0, re = 0;
+    T yi = 0, axi = 0, bi = 0, ysi = 0;
+    uint8_t ki = 0;
+    if (valid) {  // issue the row's own loads before the SpMV phase
+      rs = w.rp[i];
+      re = w.rp[i + 1];
+      yi = y[i];
+      axi = ax[i];
+      bi = ld_stream(w.b + i);
+      ki = w.kind[i];
+      if (fold_read) ysi = w.YS[i];
+    }
+    bool mine = valid && (re - rs <= PDHG_LONG_SEG);
+    T s = tile_rowdot<T>(w.rp, w.ci, w.v, xn, w.m, t * PDHG_BLOCK, rs, re, mine, lds);
+    if (mine) dual_finish(w, i, s, sigma, cur, yi, axi, bi, ki, ysi, pend, fresh, v[0], v[1]);
   }
   double out[2];
   block_reduce<2>(v, 0u, out);
   if (threadIdx.x == 0) {
-    int64_t nb = w.nblk_rows + w.n_long_rows;
     w.part_dy[lb] = out[0];
-    w.part_dy[nb + lb] = out[1];
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_dual_long(IterView<T> w, const CtlState *st) {
-  int64_t i = w.long_rows[blockIdx.x];
-  const int cur = st->cur;
-  const T sigma = (T)(st->eta * st->omega);
-  const T *__restrict__ xn = w.X[cur ^ 1];
-  int s = w.rp[i], e = w.rp[i + 1];
-  double acc[1] = {0.0};
-  for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)(w.v[k] * xn[w.ci[k]]);
-  double tot[1];
-  block_reduce<1>(acc, 0u, tot);
-  if (threadIdx.x == 0) {
-    double dy2 = 0.0, inter = 0.0;
-    dual_update(w, i, (T)tot[0], sigma, cur, st->pending, st->fresh, dy2, inter);
-    int64_t nb = w.nblk_rows + w.n_long_rows;
-    w.part_dy[w.nblk_rows + blockIdx.x] = dy2;
-    w.part_dy[nb + w.nblk_rows + blockIdx.x] = inter;
+    w.part_dy[G + lb] = out[1];
   }
 }
 
 // Step-size control of one attempt (PDLP adaptive rule):
 //   ebar = ||dz||_omega^2 / (2 |dy' A dx|),  accept iff eta <= ebar,
 //   eta <- min((1 - (k+1)^-0.3) ebar, (1 + (k+1)^-0.6) eta),  k = attempts so far.
-__global__ __launch_bounds__(PDHG_BLOCK) void k_control(const double *part_dx2, int64_t ncols_p,
+__global__ __launch_bounds__(CTL_BLOCK) void k_control(const double *part_dx2, int64_t ncols_p,
                                                         const double *part_dy, int64_t nrows_p,
                                                         int adaptive, CtlState *st) {
   __shared__ double r[3];
@@ -431,7 +498,7 @@ __device__ inline PointKKT point_kkt(const double *rq, const double *cq, double 
 // the scaled KKT_omega (restart at the better of current and average when it
 // fell to 0.2 of the last restart's, or to 0.8 with no progress since the
 // previous evaluation, or after 0.36 of all attempts), primal-weight update.
-__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const double *part_rows,
+__global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const double *part_rows,
                                                              int64_t nbr, const double *part_cols,
                                                              int64_t nbc, int use_average,
                                                              int restart, double pw_theta,
@@ -451,7 +518,10 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const double *part_
   st->pending = 0.0;
   st->have_avg = avg;
   st->restart_flag = 0;
-  if (k == 0) st->kkt_last = pc.komega;
+  if (st->init_pending) {
+    st->kkt_last = pc.komega;
+    st->init_pending = 0;
+  }
   const PointKKT *rep = &pc;
   int which = 0;
   if (!isfinite(pc.rel_kkt)) {
@@ -568,8 +638,43 @@ __global__ void k_init_state(CtlState *st) {
   st->which = 0;
   st->restart_flag = 0;
   st->have_avg = 0;
+  st->init_pending = 1;
   st->eta = st->eta0;
   st->omega = st->omega0;
+}
+
+// FP32 -> FP64 hand-over of the mixed-precision solve: the FP32 phase's
+// current iterate becomes the FP64 start point; attempts, accepted steps,
+// restarts, the step size and the primal weight carry over, the average and
+// the restart reference start afresh.
+__global__ void k_switch_cols(EvalView<float> ef, EvalView<double> ed, const CtlState *st) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ed.n) return;
+  double xv = (double)ef.X[st->cur][j];
+  ed.X[0][j] = xv;
+  ed.XL[j] = xv;
+}
+
+__global__ void k_switch_rows(EvalView<float> ef, EvalView<double> ed, const CtlState *st) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ed.m) return;
+  double yv = (double)ef.Y[st->cur][i];
+  ed.Y[0][i] = yv;
+  ed.YL[i] = yv;
+}
+
+__global__ void k_switch_state(CtlState *st) {
+  st->cur = 0;
+  st->fresh = 1;
+  st->pending = 0.0;
+  st->wsum = 0.0;
+  st->done = 0;
+  st->status = 0;
+  st->which = 0;
+  st->restart_flag = 0;
+  st->kkt_prev = INFINITY;
+  st->init_pending = 1;
+  st->last_restart = st->k;
 }
 
 template <typename T>
@@ -615,7 +720,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_norm_partials(const double *v, i
     for (int t = 0; t < 5; t++) part[t * nparts + blockIdx.x] = out[t];
 }
 
-__global__ __launch_bounds__(PDHG_BLOCK) void k_init_ctl(const double *part, int nparts,
+__global__ __launch_bounds__(CTL_BLOCK) void k_init_ctl(const double *part, int nparts,
                                                          int step_mode, double fixed_eta,
                                                          double fixed_omega, CtlState *st) {
   __shared__ double r[5];
@@ -649,20 +754,18 @@ __global__ void k_spmv_plain(const int32_t *__restrict__ rp, const int32_t *__re
 
 template <typename T>
 void launch_primal(const IterView<T> &w, CtlState *st, hipStream_t s) {
-  k_primal<T><<<w.nblk_cols, PDHG_BLOCK, 0, s>>>(w, st);
-  if (w.n_long_cols) k_primal_long<T><<<w.n_long_cols, PDHG_BLOCK, 0, s>>>(w, st);
+  k_primal<T><<<w.grid_cols, PDHG_BLOCK, 0, s>>>(w, st);
 }
 
 template <typename T>
 void launch_dual(const IterView<T> &w, CtlState *st, hipStream_t s) {
-  k_dual<T><<<w.nblk_rows, PDHG_BLOCK, 0, s>>>(w, st);
-  if (w.n_long_rows) k_dual_long<T><<<w.n_long_rows, PDHG_BLOCK, 0, s>>>(w, st);
+  k_dual<T><<<w.grid_rows, PDHG_BLOCK, 0, s>>>(w, st);
 }
 
 template <typename T>
 void launch_control(const IterView<T> &w, CtlState *st, hipStream_t s) {
-  k_control<<<1, PDHG_BLOCK, 0, s>>>(w.part_dx2, w.nblk_cols + w.n_long_cols, w.part_dy,
-                                     w.nblk_rows + w.n_long_rows, w.adaptive, st);
+  k_control<<<1, CTL_BLOCK, 0, s>>>(w.part_dx2, w.grid_cols, w.part_dy, w.grid_rows, w.adaptive,
+                                     st);
 }
 
 template <typename T>
@@ -702,7 +805,7 @@ void launch_evaluate_impl(const EvalView<T> &e, const LongLists &ll, CtlState *s
                                                              e.YA, st, 0, e.use_average, e.ATYA);
   k_eval_rows<T><<<e.nblk_rows, PDHG_BLOCK, 0, s>>>(e, st);
   k_eval_cols<T><<<e.nblk_cols, PDHG_BLOCK, 0, s>>>(e, st);
-  k_eval_control<<<1, PDHG_BLOCK, 0, s>>>(e.part_rows, e.nblk_rows, e.part_cols, e.nblk_cols,
+  k_eval_control<<<1, CTL_BLOCK, 0, s>>>(e.part_rows, e.nblk_rows, e.part_cols, e.nblk_cols,
                                           e.use_average, e.restart, e.pw_theta, tol,
                                           (long long)max_iter, st);
   k_restart_cols<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e, st);
@@ -733,6 +836,20 @@ void launch_init_point(const EvalView<T> &e, const int32_t *long_rows, int n_lon
   k_ax_to_iter<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, ax_tmp);
 }
 
+void launch_switch_to_fp64(const EvalView<float> &ef, const EvalView<double> &ed,
+                           const int32_t *long_rows, int n_long_rows, CtlState *st,
+                           hipStream_t s) {
+  k_switch_cols<<<grid_for(ed.n), PDHG_BLOCK, 0, s>>>(ef, ed, st);
+  k_switch_rows<<<grid_for(ed.m), PDHG_BLOCK, 0, s>>>(ef, ed, st);
+  k_switch_state<<<1, 1, 0, s>>>(st);
+  k_spmv_sel<double><<<grid_for(ed.m), PDHG_BLOCK, 0, s>>>(ed.rp, ed.ci, ed.v, ed.m, ed.X[0],
+                                                            ed.X[0], st, 0, 0, ed.AX[0]);
+  if (n_long_rows)
+    k_spmv_sel_long<double><<<n_long_rows, PDHG_BLOCK, 0, s>>>(ed.rp, ed.ci, ed.v, long_rows,
+                                                                ed.X[0], ed.X[0], st, 0, 0,
+                                                                ed.AX[0]);
+}
+
 template <typename T>
 void launch_unscale(const EvalView<T> &e, const CtlState *st, double *x, double *y,
                     hipStream_t s) {
@@ -747,7 +864,7 @@ void launch_init_ctl(const double *v, int64_t nnz, const double *b, const double
   int np = nscratch / 5;
   if (np > 1024) np = 1024;
   k_norm_partials<<<np, PDHG_BLOCK, 0, s>>>(v, nnz, b, c, b0, c0, m, n, scratch, np);
-  k_init_ctl<<<1, PDHG_BLOCK, 0, s>>>(scratch, np, step_mode, fixed_eta, fixed_omega, st);
+  k_init_ctl<<<1, CTL_BLOCK, 0, s>>>(scratch, np, step_mode, fixed_eta, fixed_omega, st);
 }
 
 void launch_spmv(const int32_t *rp, const int32_t *ci, const double *v, int64_t rows,

@@ -1,0 +1,45 @@
+"""Mixed precision (FP32 iterates and SpMVs, FP64 control, evaluation and
+polish) against the FP64 oracle and exact optima."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact
+from paper_2512_06715_amd import ucgen
+
+pytestmark = pytest.mark.gpu
+REFS = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lp_refs.json")))
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-7])
+def test_mixed_small_uc(gpu, oracle_mod, tol):
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.random_uc(6, 3, 8, 6, 1.0, seed=11)
+    print("case small uc mixed", tol, flush=True)
+    _, _, ref, _ = exact.highs(lp)
+    p = Problem(lp, precision="mixed", tol=tol, max_iter=400000)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 1, info
+    k = oracle_mod.kkt(lp, x, y)
+    assert k["rel_kkt"] <= tol * 1.001, k
+    assert abs(k["pobj"] - ref) <= 10 * tol * abs(ref)
+    if tol < 1e-6:
+        assert info["attempts_fp32"] < info["attempts"]   # needed the FP64 polish
+
+
+def test_mixed_uc1000(gpu, oracle_mod):
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc1000_t48")
+    ref = REFS["uc1000_t48"]["objective"]
+    print("case uc1000 mixed", flush=True)
+    p = Problem(lp, precision="mixed", tol=1e-4, max_iter=2000000)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 1, info
+    k = oracle_mod.kkt(lp, x, y)
+    assert k["rel_kkt"] <= 1.001e-4, k
+    assert abs(k["pobj"] - ref) <= 1e-3 * abs(ref)
+    assert abs(info["primal_obj"] - k["pobj"]) <= 1e-9 * abs(ref)
