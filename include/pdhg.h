@@ -132,10 +132,11 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace,
 int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x,
                double *y, pdhg_info *info);
 
-/* One instance of a batched solve.  Instances whose base handle is the same
- * share that handle's matrix; b, c, l, u override the base's vectors when
- * non-null (original space, same memory kind as the base LP), and the
- * n_fix (index, value) pairs fix variables (l = u = value) on top. */
+/* One instance of a batched solve (for example a branch-and-bound node or a
+ * load scenario).  Instances whose base handle is the same share that
+ * handle's preprocessed matrix; b, c, l, u override the base's vectors when
+ * non-null (original space, same memory kind as the base LP), and the n_fix
+ * (index, value) pairs fix variables (l = u = value) on top of the bounds. */
 typedef struct {
   int32_t base;
   const double *b, *c, *l, *u;
@@ -144,11 +145,22 @@ typedef struct {
   int64_t n_fix;
 } pdhg_instance;
 
-/* Solve `batch` instances.  x[k], y[k] receive instance k's solution and
- * infos[k] its report.  Handles are used with their own options. */
+/* Device workspace bytes for pdhg_solve_batch with these instances. */
+int pdhg_batch_workspace_bytes(pdhg_handle *const *handles, int n_handles,
+                               const pdhg_instance *inst, int batch, size_t *bytes);
+
+/* Solve `batch` instances together: every kernel launch serves all instances
+ * still running (per-instance step size, primal weight, restarts and
+ * termination), blocks of attempts are replayed as HIP graphs, and finished
+ * instances leave the launch tables.  The options (tolerance, precision,
+ * limits) are those of handles[0]; all handles must share the precision.
+ * x[k], y[k] receive instance k's solution (memory kind of its base LP) and
+ * infos[k] its report (solve_s is the wall time of the whole batch).  Runs on
+ * handles[0]'s stream after synchronizing the other handles. */
 int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles,
-                     const pdhg_instance *inst, int batch, double *const *x,
-                     double *const *y, pdhg_info *infos);
+                     const pdhg_instance *inst, int batch, void *workspace,
+                     size_t workspace_bytes, double *const *x, double *const *y,
+                     pdhg_info *infos);
 
 /* After a pdhg_solve in unrolled mode (opts.unroll_iters > 0), the gradient
  * of V = c'x_K with respect to b and c (original space), scaled by

@@ -62,9 +62,12 @@ SIGNATURES = {
     "pdhg_setup": (c_int, [ctypes.POINTER(PdhgLP), ctypes.POINTER(PdhgOpts), vp,
                            ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
     "pdhg_solve": (c_int, [vp, vp, vp, vp, vp, ctypes.POINTER(PdhgInfo)]),
+    "pdhg_batch_workspace_bytes": (c_int, [ctypes.POINTER(vp), c_int,
+                                           ctypes.POINTER(PdhgInstance), c_int,
+                                           ctypes.POINTER(ctypes.c_size_t)]),
     "pdhg_solve_batch": (c_int, [ctypes.POINTER(vp), c_int, ctypes.POINTER(PdhgInstance),
-                                 c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
-                                 ctypes.POINTER(PdhgInfo)]),
+                                 c_int, vp, ctypes.c_size_t, ctypes.POINTER(vp),
+                                 ctypes.POINTER(vp), ctypes.POINTER(PdhgInfo)]),
     "pdhg_backward": (c_int, [vp, c_dbl, vp, vp]),
     "pdhg_destroy": (None, [vp]),
     "pdhg_last_error": (ctypes.c_char_p, []),

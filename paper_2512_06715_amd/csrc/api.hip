@@ -1,5 +1,7 @@
 // Host side of the C ABI: argument checks, workspace carving, setup
-// orchestration, the block-by-block solve driver with HIP graphs.
+// orchestration, and the block-by-block driver that replays iteration blocks
+// as HIP graphs over a group of instances (one for pdhg_solve, many for
+// pdhg_solve_batch).
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -32,7 +34,7 @@ double now_s() {
       .count();
 }
 
-// Bump allocator over the caller's workspace; with base == nullptr it only
+// Bump allocator over a caller's workspace; with base == nullptr it only
 // measures.
 struct Carver {
   char *base;
@@ -47,7 +49,66 @@ struct Carver {
   }
 };
 
-unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + PDHG_BLOCK - 1) / PDHG_BLOCK); }
+int nblk(int64_t n) { return (int)std::max<int64_t>(1, (n + PDHG_BLOCK - 1) / PDHG_BLOCK); }
+
+// Device tables of an instance group: the Inst arrays the kernels read and
+// the prefix tables of every launch shape, with room for `cap` instances.
+struct GroupDev {
+  int cap = 0;
+  Inst<double> *d64 = nullptr;
+  Inst<float> *d32 = nullptr;
+  int32_t *pre = nullptr;         // 6 * (cap + 1)
+  CtlState *dstates = nullptr;    // gathered states
+  CtlState *hstates = nullptr;    // pinned host mirror
+};
+
+void carve_group(Carver &cv, GroupDev &gd, int cap) {
+  gd.cap = cap;
+  gd.d64 = cv.take<Inst<double>>(cap);
+  gd.d32 = cv.take<Inst<float>>(cap);
+  gd.pre = cv.take<int32_t>(6 * (cap + 1));
+  gd.dstates = cv.take<CtlState>(cap);
+}
+
+// Per-instance buffers: iterates of both precisions, evaluation vectors,
+// partials and the control state.
+struct IterBufs {
+  double *X[2], *Y[2], *AX[2], *XS, *YS;
+  float *Xf[2], *Yf[2], *AXf[2], *XSf, *YSf;
+  double *XL, *YL, *XA, *YA, *AXA, *ATY, *ATYA;
+  double *part_dx2, *part_dy, *part_rows, *part_cols;
+  CtlState *st;
+};
+
+void carve_iter(Carver &cv, IterBufs &b, int64_t m, int64_t n, int grid_rows, int grid_cols,
+                bool mixed) {
+  for (int q = 0; q < 2; q++) {
+    b.X[q] = cv.take<double>(n);
+    b.Y[q] = cv.take<double>(m);
+    b.AX[q] = cv.take<double>(m);
+  }
+  b.XS = cv.take<double>(n);
+  b.YS = cv.take<double>(m);
+  for (int q = 0; q < 2; q++) {
+    b.Xf[q] = mixed ? cv.take<float>(n) : nullptr;
+    b.Yf[q] = mixed ? cv.take<float>(m) : nullptr;
+    b.AXf[q] = mixed ? cv.take<float>(m) : nullptr;
+  }
+  b.XSf = mixed ? cv.take<float>(n) : nullptr;
+  b.YSf = mixed ? cv.take<float>(m) : nullptr;
+  b.XL = cv.take<double>(n);
+  b.YL = cv.take<double>(m);
+  b.XA = cv.take<double>(n);
+  b.YA = cv.take<double>(m);
+  b.AXA = cv.take<double>(m);
+  b.ATY = cv.take<double>(n);
+  b.ATYA = cv.take<double>(n);
+  b.part_dx2 = cv.take<double>(grid_cols);
+  b.part_dy = cv.take<double>(2 * (int64_t)grid_rows);
+  b.part_rows = cv.take<double>((int64_t)nblk(m) * EV_ROWQ);
+  b.part_cols = cv.take<double>((int64_t)nblk(n) * EV_COLQ);
+  b.st = cv.take<CtlState>(1);
+}
 
 }  // namespace
 
@@ -61,35 +122,55 @@ struct pdhg_handle {
   bool hip_failed = false;
   double setup_s = 0.0;
 
+  // preprocessed problem (shared by every instance built on this handle)
   int32_t *rp, *ci, *cp, *ri, *long_rows, *long_cols, *scan_tmp, *tmp_next;
   double *v, *vt, *b0, *c0, *l0, *u0, *b, *c, *l, *u, *Dr, *Dc;
-  uint8_t *kind, *vk;
-  double *X[2], *Y[2], *AX[2], *XS, *YS, *XL, *YL, *XA, *YA, *AXA, *ATY, *ATYA;
   float *vf = nullptr, *vtf = nullptr, *bf = nullptr, *cf = nullptr, *lf = nullptr,
         *uf = nullptr;
-  float *Xf[2] = {nullptr, nullptr}, *Yf[2] = {nullptr, nullptr}, *AXf[2] = {nullptr, nullptr};
-  float *XSf = nullptr, *YSf = nullptr;
-  double *part_dx2, *part_dy, *part_rows, *part_cols, *scratch;
+  uint8_t *kind, *vk;
+  double *scratch;
   int nscratch = 0;
-  CtlState *st;
   int *err;
   int n_long_rows = 0, n_long_cols = 0, nblk_rows = 0, nblk_cols = 0;
   int tpb_rows = 1, tpb_cols = 1, grid_rows = 1, grid_cols = 1;
-  CtlState *host_st = nullptr;
 
-  struct Graph {
+  // the handle's own instance (pdhg_solve) and its cached block graphs
+  IterBufs it{};
+  GroupDev grp{};
+  struct Slot {
     hipGraphExec_t exec = nullptr;
     int period = 0;
     double tol = 0;
     int64_t max_iter = 0;
+    int version = 0;
   } graph[2];
 };
 
 namespace {
 
+typedef pdhg_handle::Slot GraphSlot;
+
+void partition(pdhg_handle *h) {
+  h->nblk_rows = nblk(h->m);
+  h->nblk_cols = nblk(h->n);
+  h->tpb_rows = h->o.tiles_per_block > 0
+                    ? h->o.tiles_per_block
+                    : std::max(1, (h->nblk_rows + PDHG_TARGET_GROUPS - 1) / PDHG_TARGET_GROUPS);
+  h->tpb_cols = h->o.tiles_per_block > 0
+                    ? h->o.tiles_per_block
+                    : std::max(1, (h->nblk_cols + PDHG_TARGET_GROUPS - 1) / PDHG_TARGET_GROUPS);
+}
+
+void set_grids(pdhg_handle *h) {
+  h->grid_rows = h->n_long_rows + (h->nblk_rows + h->tpb_rows - 1) / h->tpb_rows;
+  h->grid_cols = h->n_long_cols + (h->nblk_cols + h->tpb_cols - 1) / h->tpb_cols;
+}
+
 size_t layout(pdhg_handle *h, void *base) {
   Carver cv(base);
   int64_t m = h->m, n = h->n, nnz = h->nnz;
+  bool mixed = h->o.precision == PDHG_MIXED;
+  partition(h);
   h->rp = cv.take<int32_t>(m + 1);
   h->ci = cv.take<int32_t>(nnz);
   h->cp = cv.take<int32_t>(n + 1);
@@ -112,44 +193,22 @@ size_t layout(pdhg_handle *h, void *base) {
   h->Dc = cv.take<double>(n);
   h->kind = cv.take<uint8_t>(m);
   h->vk = cv.take<uint8_t>(n);
-  for (int q = 0; q < 2; q++) {
-    h->X[q] = cv.take<double>(n);
-    h->Y[q] = cv.take<double>(m);
-    h->AX[q] = cv.take<double>(m);
-  }
-  h->XS = cv.take<double>(n);
-  h->YS = cv.take<double>(m);
-  h->XL = cv.take<double>(n);
-  h->YL = cv.take<double>(m);
-  h->XA = cv.take<double>(n);
-  h->YA = cv.take<double>(m);
-  h->AXA = cv.take<double>(m);
-  h->ATY = cv.take<double>(n);
-  h->ATYA = cv.take<double>(n);
-  int64_t nbr = nblk(m), nbc = nblk(n);
-  h->part_dx2 = cv.take<double>(nbc + n);
-  h->part_dy = cv.take<double>(2 * (nbr + m));
-  h->part_rows = cv.take<double>(nbr * EV_ROWQ);
-  h->part_cols = cv.take<double>(nbc * EV_COLQ);
-  h->nscratch = 5 * 1024;
-  h->scratch = cv.take<double>(h->nscratch);
-  h->st = cv.take<CtlState>(1);
-  h->err = cv.take<int>(1);
-  if (h->o.precision == PDHG_MIXED) {
+  if (mixed) {
     h->vf = cv.take<float>(nnz);
     h->vtf = cv.take<float>(nnz);
     h->bf = cv.take<float>(m);
     h->cf = cv.take<float>(n);
     h->lf = cv.take<float>(n);
     h->uf = cv.take<float>(n);
-    for (int q = 0; q < 2; q++) {
-      h->Xf[q] = cv.take<float>(n);
-      h->Yf[q] = cv.take<float>(m);
-      h->AXf[q] = cv.take<float>(m);
-    }
-    h->XSf = cv.take<float>(n);
-    h->YSf = cv.take<float>(m);
   }
+  h->nscratch = 5 * 1024;
+  h->scratch = cv.take<double>(h->nscratch);
+  h->err = cv.take<int>(1);
+  // worst-case grids: every row and column long
+  int gr = (int)std::min<int64_t>(m + h->nblk_rows, 0x7fffffff);
+  int gc = (int)std::min<int64_t>(n + h->nblk_cols, 0x7fffffff);
+  carve_iter(cv, h->it, m, n, gr, gc, mixed);
+  carve_group(cv, h->grp, 1);
   return cv.off + 256;
 }
 
@@ -228,224 +287,11 @@ int validate_host(const pdhg_lp *lp) {
     }                                                                                     \
   } while (0)
 
-hipMemcpyKind in_kind(const pdhg_handle *h) {
-  return h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-}
-
-template <typename T>
-IterView<T> iter_view(pdhg_handle *h);
-
-template <>
-IterView<double> iter_view<double>(pdhg_handle *h) {
-  IterView<double> w{};
-  w.m = h->m;
-  w.n = h->n;
-  w.rp = h->rp;
-  w.ci = h->ci;
-  w.cp = h->cp;
-  w.ri = h->ri;
-  w.v = h->v;
-  w.vt = h->vt;
-  w.b = h->b;
-  w.c = h->c;
-  w.l = h->l;
-  w.u = h->u;
-  w.kind = h->kind;
-  w.vk = h->vk;
-  for (int q = 0; q < 2; q++) {
-    w.X[q] = h->X[q];
-    w.Y[q] = h->Y[q];
-    w.AX[q] = h->AX[q];
-  }
-  w.XS = h->XS;
-  w.YS = h->YS;
-  w.nblk_rows = h->nblk_rows;
-  w.nblk_cols = h->nblk_cols;
-  w.long_rows = h->long_rows;
-  w.long_cols = h->long_cols;
-  w.n_long_rows = h->n_long_rows;
-  w.n_long_cols = h->n_long_cols;
-  w.tpb_rows = h->tpb_rows;
-  w.tpb_cols = h->tpb_cols;
-  w.grid_rows = h->grid_rows;
-  w.grid_cols = h->grid_cols;
-  w.part_dx2 = h->part_dx2;
-  w.part_dy = h->part_dy;
-  w.adaptive = h->o.step_mode == 0;
-  return w;
-}
-
-template <>
-IterView<float> iter_view<float>(pdhg_handle *h) {
-  IterView<float> w{};
-  w.m = h->m;
-  w.n = h->n;
-  w.rp = h->rp;
-  w.ci = h->ci;
-  w.cp = h->cp;
-  w.ri = h->ri;
-  w.v = h->vf;
-  w.vt = h->vtf;
-  w.b = h->bf;
-  w.c = h->cf;
-  w.l = h->lf;
-  w.u = h->uf;
-  w.kind = h->kind;
-  w.vk = h->vk;
-  for (int q = 0; q < 2; q++) {
-    w.X[q] = h->Xf[q];
-    w.Y[q] = h->Yf[q];
-    w.AX[q] = h->AXf[q];
-  }
-  w.XS = h->XSf;
-  w.YS = h->YSf;
-  w.nblk_rows = h->nblk_rows;
-  w.nblk_cols = h->nblk_cols;
-  w.long_rows = h->long_rows;
-  w.long_cols = h->long_cols;
-  w.n_long_rows = h->n_long_rows;
-  w.n_long_cols = h->n_long_cols;
-  w.tpb_rows = h->tpb_rows;
-  w.tpb_cols = h->tpb_cols;
-  w.grid_rows = h->grid_rows;
-  w.grid_cols = h->grid_cols;
-  w.part_dx2 = h->part_dx2;
-  w.part_dy = h->part_dy;
-  w.adaptive = h->o.step_mode == 0;
-  return w;
-}
-
-template <typename T>
-EvalView<T> eval_view(pdhg_handle *h) {
-  EvalView<T> e{};
-  IterView<T> w = iter_view<T>(h);
-  e.m = h->m;
-  e.n = h->n;
-  e.rp = h->rp;
-  e.ci = h->ci;
-  e.cp = h->cp;
-  e.ri = h->ri;
-  e.v = h->v;
-  e.vt = h->vt;
-  e.b = h->b;
-  e.c = h->c;
-  e.l = h->l;
-  e.u = h->u;
-  e.Dr = h->Dr;
-  e.Dc = h->Dc;
-  e.kind = h->kind;
-  e.vk = h->vk;
-  for (int q = 0; q < 2; q++) {
-    e.X[q] = w.X[q];
-    e.Y[q] = w.Y[q];
-    e.AX[q] = w.AX[q];
-  }
-  e.XS = w.XS;
-  e.YS = w.YS;
-  e.XA = h->XA;
-  e.YA = h->YA;
-  e.AXA = h->AXA;
-  e.ATY = h->ATY;
-  e.ATYA = h->ATYA;
-  e.XL = h->XL;
-  e.YL = h->YL;
-  e.nblk_rows = h->nblk_rows;
-  e.nblk_cols = h->nblk_cols;
-  e.part_rows = h->part_rows;
-  e.part_cols = h->part_cols;
-  e.use_average = h->o.use_average;
-  e.restart = h->o.restart;
-  e.pw_theta = h->o.pw_update ? h->o.pw_theta : 0.0;
-  return e;
-}
-
-int read_state(pdhg_handle *h) {
-  HC(hipMemcpyAsync(h->host_st, h->st, sizeof(CtlState), hipMemcpyDeviceToHost, h->hs));
-  HC(hipStreamSynchronize(h->hs));
-  return PDHG_OK;
-}
-
-// Record one block (period attempts + evaluation) as a graph.
-template <typename T>
-int capture_block(pdhg_handle *h, int slot, int period, double tol, int64_t max_iter) {
-  auto &g = h->graph[slot];
-  if (g.exec && g.period == period && g.tol == tol && g.max_iter == max_iter) return PDHG_OK;
-  if (g.exec) {
-    HC(hipGraphExecDestroy(g.exec));
-    g.exec = nullptr;
-  }
-  IterView<T> w = iter_view<T>(h);
-  EvalView<T> e = eval_view<T>(h);
-  hipGraph_t graph;
-  HC(hipStreamBeginCapture(h->hs, hipStreamCaptureModeThreadLocal));
-  for (int i = 0; i < period; i++) launch_attempt<T>(w, h->st, max_iter, h->hs);
-  launch_evaluate_ll<T>(e, h->long_rows, h->n_long_rows, h->long_cols, h->n_long_cols, h->st, tol,
-                        max_iter, h->hs);
-  HC(hipStreamEndCapture(h->hs, &graph));
-  HK();
-  HC(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
-  HC(hipGraphDestroy(graph));
-  g.period = period;
-  g.tol = tol;
-  g.max_iter = max_iter;
-  return PDHG_OK;
-}
-
-// Run attempts in blocks until the device reports done; the start point must
-// already be initialised (launch_init_point) or carried over.
-// stall_evals > 0: return with *status_out = 0 when the reported relative KKT
-// error has not dropped below 0.9 of its best value for that many evaluations.
-template <typename T>
-int run_blocks(pdhg_handle *h, double tol, int64_t max_iter, double t_start, int *status_out,
-               int stall_evals = 0) {
-  IterView<T> w = iter_view<T>(h);
-  EvalView<T> e = eval_view<T>(h);
-  const int slot = sizeof(T) == 4 ? 1 : 0;
-  const int P = h->o.eval_period;
-  launch_evaluate_ll<T>(e, h->long_rows, h->n_long_rows, h->long_cols, h->n_long_cols, h->st, tol,
-                        max_iter, h->hs);
-  HK();
-  int rc = read_state(h);
-  if (rc) return rc;
-  double best = h->host_st->rel_kkt;
-  int since = 0;
-  while (!h->host_st->done) {
-    int64_t k = h->host_st->k;
-    int64_t nb = std::min<int64_t>(P, max_iter - k);
-    if (nb == P && h->o.use_graph) {
-      rc = capture_block<T>(h, slot, P, tol, max_iter);
-      if (rc) return rc;
-      HC(hipGraphLaunch(h->graph[slot].exec, h->hs));
-    } else {
-      for (int64_t i = 0; i < nb; i++) launch_attempt<T>(w, h->st, max_iter, h->hs);
-      launch_evaluate_ll<T>(e, h->long_rows, h->n_long_rows, h->long_cols, h->n_long_cols, h->st,
-                            tol, max_iter, h->hs);
-      HK();
-    }
-    rc = read_state(h);
-    if (rc) return rc;
-    const CtlState *s = h->host_st;
-    if (h->o.verbose)
-      fprintf(stderr,
-              "pdhg k=%lld kkt=%.3e (p %.2e d %.2e g %.2e) obj=%.10g eta=%.3e omega=%.3e "
-              "restarts=%lld\n",
-              s->k, s->rel_kkt, s->rel_p, s->rel_d, s->rel_gap, s->pobj, s->eta, s->omega,
-              s->restarts);
-    if (!s->done && now_s() - t_start > h->o.time_limit_s) {
-      *status_out = PDHG_TIME_LIMIT;
-      return PDHG_OK;
-    }
-    if (s->rel_kkt < 0.9 * best) {
-      best = s->rel_kkt;
-      since = 0;
-    } else if (stall_evals > 0 && ++since >= stall_evals && !s->done) {
-      *status_out = 0;
-      return PDHG_OK;
-    }
-  }
-  *status_out = h->host_st->status;
-  return PDHG_OK;
-}
+#define RC(call)       \
+  do {                 \
+    int r_ = (call);   \
+    if (r_) return r_; \
+  } while (0)
 
 int enter(pdhg_handle *h) {
   if (h->hip_failed) return fail(PDHG_ERR_HIP, "handle unusable after an earlier HIP error");
@@ -457,6 +303,365 @@ int enter(pdhg_handle *h) {
 int leave(pdhg_handle *h) {
   HC(hipEventRecord(h->ev, h->hs));
   HC(hipStreamWaitEvent(h->user, h->ev, 0));
+  return PDHG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// instance views
+
+// Scaled problem vectors of one instance; defaults are the handle's.
+struct InstData {
+  const double *b, *c, *l, *u;
+  const float *bf, *cf, *lf, *uf;
+  const uint8_t *vk;
+};
+
+InstData base_data(const pdhg_handle *h) {
+  return InstData{h->b, h->c, h->l, h->u, h->bf, h->cf, h->lf, h->uf, h->vk};
+}
+
+template <typename T>
+void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const IterBufs &b) {
+  IterView<T> &w = I.w;
+  EvalView<T> &e = I.e;
+  w.m = e.m = h->m;
+  w.n = e.n = h->n;
+  w.rp = e.rp = h->rp;
+  w.ci = e.ci = h->ci;
+  w.cp = e.cp = h->cp;
+  w.ri = e.ri = h->ri;
+  w.kind = e.kind = h->kind;
+  w.vk = e.vk = d.vk;
+  w.nblk_rows = e.nblk_rows = h->nblk_rows;
+  w.nblk_cols = e.nblk_cols = h->nblk_cols;
+  w.long_rows = h->long_rows;
+  w.long_cols = h->long_cols;
+  w.n_long_rows = h->n_long_rows;
+  w.n_long_cols = h->n_long_cols;
+  w.tpb_rows = h->tpb_rows;
+  w.tpb_cols = h->tpb_cols;
+  w.grid_rows = h->grid_rows;
+  w.grid_cols = h->grid_cols;
+  w.part_dx2 = b.part_dx2;
+  w.part_dy = b.part_dy;
+  w.adaptive = h->o.step_mode == 0;
+  e.v = h->v;
+  e.vt = h->vt;
+  e.b = d.b;
+  e.c = d.c;
+  e.l = d.l;
+  e.u = d.u;
+  e.Dr = h->Dr;
+  e.Dc = h->Dc;
+  e.XA = b.XA;
+  e.YA = b.YA;
+  e.AXA = b.AXA;
+  e.ATY = b.ATY;
+  e.ATYA = b.ATYA;
+  e.XL = b.XL;
+  e.YL = b.YL;
+  e.part_rows = b.part_rows;
+  e.part_cols = b.part_cols;
+  e.use_average = h->o.use_average;
+  e.restart = h->o.restart;
+  e.pw_theta = h->o.pw_update ? h->o.pw_theta : 0.0;
+  I.st = b.st;
+  I.x0 = I.y0 = nullptr;
+  I.xout = I.yout = nullptr;
+}
+
+template <typename T>
+Inst<T> make_inst(const pdhg_handle *h, const InstData &d, const IterBufs &b);
+
+template <>
+Inst<double> make_inst<double>(const pdhg_handle *h, const InstData &d, const IterBufs &b) {
+  Inst<double> I{};
+  fill_common(I, h, d, b);
+  I.w.v = h->v;
+  I.w.vt = h->vt;
+  I.w.b = d.b;
+  I.w.c = d.c;
+  I.w.l = d.l;
+  I.w.u = d.u;
+  for (int q = 0; q < 2; q++) {
+    I.w.X[q] = I.e.X[q] = b.X[q];
+    I.w.Y[q] = I.e.Y[q] = b.Y[q];
+    I.w.AX[q] = I.e.AX[q] = b.AX[q];
+  }
+  I.w.XS = I.e.XS = b.XS;
+  I.w.YS = I.e.YS = b.YS;
+  return I;
+}
+
+template <>
+Inst<float> make_inst<float>(const pdhg_handle *h, const InstData &d, const IterBufs &b) {
+  Inst<float> I{};
+  fill_common(I, h, d, b);
+  I.w.v = h->vf;
+  I.w.vt = h->vtf;
+  I.w.b = d.bf;
+  I.w.c = d.cf;
+  I.w.l = d.lf;
+  I.w.u = d.uf;
+  for (int q = 0; q < 2; q++) {
+    I.w.X[q] = I.e.X[q] = b.Xf[q];
+    I.w.Y[q] = I.e.Y[q] = b.Yf[q];
+    I.w.AX[q] = I.e.AX[q] = b.AXf[q];
+  }
+  I.w.XS = I.e.XS = b.XSf;
+  I.w.YS = I.e.YS = b.YSf;
+  return I;
+}
+
+template <typename T>
+Inst<T> *dev_insts(GroupDev &gd);
+template <>
+Inst<double> *dev_insts<double>(GroupDev &gd) {
+  return gd.d64;
+}
+template <>
+Inst<float> *dev_insts<float>(GroupDev &gd) {
+  return gd.d32;
+}
+
+// Upload the active instances and the prefix tables of every launch shape.
+template <typename T>
+int upload_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
+                 const std::vector<int> &act, Groups &g) {
+  int na = (int)act.size();
+  int c1 = gd.cap + 1;
+  std::vector<Inst<T>> sel(na);
+  std::vector<int32_t> pre(6 * c1, 0);
+  for (int k = 0; k < na; k++) {
+    const Inst<T> &I = all[act[k]];
+    sel[k] = I;
+    int cnt[6] = {I.w.grid_cols, I.w.grid_rows, I.e.nblk_rows, I.e.nblk_cols, I.w.n_long_rows,
+                  I.w.n_long_cols};
+    for (int s = 0; s < 6; s++) pre[s * c1 + k + 1] = pre[s * c1 + k] + cnt[s];
+  }
+  HC(hipMemcpyAsync(dev_insts<T>(gd), sel.data(), sizeof(Inst<T>) * na, hipMemcpyHostToDevice,
+                    h->hs));
+  HC(hipMemcpyAsync(gd.pre, pre.data(), sizeof(int32_t) * pre.size(), hipMemcpyHostToDevice, h->hs));
+  HC(hipStreamSynchronize(h->hs));  // the host staging vectors go out of scope
+  const int32_t *p = gd.pre;
+  g.ninst = na;
+  g.p_primal = p;
+  g.p_dual = p + c1;
+  g.p_rows = p + 2 * c1;
+  g.p_cols = p + 3 * c1;
+  g.p_lrows = p + 4 * c1;
+  g.p_lcols = p + 5 * c1;
+  g.n_primal = pre[na];
+  g.n_dual = pre[c1 + na];
+  g.n_rows = pre[2 * c1 + na];
+  g.n_cols = pre[3 * c1 + na];
+  g.n_lrows = pre[4 * c1 + na];
+  g.n_lcols = pre[5 * c1 + na];
+  return PDHG_OK;
+}
+
+int read_states(pdhg_handle *h, GroupDev &gd, int na, bool fp32) {
+  if (fp32)
+    launch_gather_states<float>(gd.d32, na, gd.dstates, h->hs);
+  else
+    launch_gather_states<double>(gd.d64, na, gd.dstates, h->hs);
+  HK();
+  HC(hipMemcpyAsync(gd.hstates, gd.dstates, sizeof(CtlState) * na, hipMemcpyDeviceToHost, h->hs));
+  HC(hipStreamSynchronize(h->hs));
+  return PDHG_OK;
+}
+
+// Record one block (period attempts + evaluation) as a graph.  `version`
+// identifies the group tables the graph was taken with.
+template <typename T>
+int capture(pdhg_handle *h, GraphSlot &gs, const Inst<T> *dI, const Groups &g, int period,
+            double tol, int64_t max_iter, int version) {
+  if (gs.exec && gs.period == period && gs.tol == tol && gs.max_iter == max_iter &&
+      gs.version == version)
+    return PDHG_OK;
+  if (gs.exec) {
+    HC(hipGraphExecDestroy(gs.exec));
+    gs.exec = nullptr;
+  }
+  hipGraph_t graph;
+  HC(hipStreamBeginCapture(h->hs, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < period; i++) launch_attempt<T>(dI, g, h->hs);
+  launch_evaluate<T>(dI, g, tol, max_iter, h->hs);
+  HC(hipStreamEndCapture(h->hs, &graph));
+  HK();
+  HC(hipGraphInstantiate(&gs.exec, graph, nullptr, nullptr, 0));
+  HC(hipGraphDestroy(graph));
+  gs.period = period;
+  gs.tol = tol;
+  gs.max_iter = max_iter;
+  gs.version = version;
+  return PDHG_OK;
+}
+
+// Drive a group of instances in blocks of `period` attempts plus an
+// evaluation until every instance is done.  `active` lists the instances
+// (indices into `all`, start points already initialised).  On return
+// status[i] holds each one's status, 0 for an instance stopped because its
+// relative KKT error had not dropped below 0.9 of its best value for
+// `stall_evals` evaluations (0 disables that test).  With reuse_graph the
+// slot's graph is kept if it was taken with the same tables.
+template <typename T>
+int run_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
+              std::vector<int> active, double tol, int64_t max_iter, double t_start,
+              int stall_evals, GraphSlot &gs, bool reuse_graph, std::vector<int> &status,
+              std::vector<CtlState> &final_state) {
+  const int P = h->o.eval_period;
+  const bool fp32 = sizeof(T) == 4;
+  std::vector<double> best(all.size(), INFINITY);
+  std::vector<int> since(all.size(), 0);
+  Groups g{};
+  int version = reuse_graph ? gs.version : gs.version + 1;
+  RC(upload_group<T>(h, gd, all, active, g));
+  const Inst<T> *dI = dev_insts<T>(gd);
+  launch_evaluate<T>(dI, g, tol, max_iter, h->hs);
+  HK();
+  for (;;) {
+    RC(read_states(h, gd, (int)active.size(), fp32));
+    std::vector<int> still;
+    bool timeout = now_s() - t_start > h->o.time_limit_s;
+    int64_t kmin = INT64_MAX;
+    for (size_t q = 0; q < active.size(); q++) {
+      int i = active[q];
+      const CtlState &s = gd.hstates[q];
+      final_state[i] = s;
+      if (h->o.verbose && active.size() == 1)
+        fprintf(stderr,
+                "pdhg k=%lld kkt=%.3e (p %.2e d %.2e g %.2e) obj=%.10g eta=%.3e omega=%.3e "
+                "restarts=%lld\n",
+                s.k, s.rel_kkt, s.rel_p, s.rel_d, s.rel_gap, s.pobj, s.eta, s.omega, s.restarts);
+      if (s.done) {
+        status[i] = s.status;
+        continue;
+      }
+      if (timeout) {
+        status[i] = PDHG_TIME_LIMIT;
+        continue;
+      }
+      if (s.rel_kkt < 0.9 * best[i]) {
+        best[i] = s.rel_kkt;
+        since[i] = 0;
+      } else if (stall_evals > 0 && ++since[i] >= stall_evals) {
+        status[i] = 0;
+        continue;
+      }
+      still.push_back(i);
+      kmin = std::min<int64_t>(kmin, s.k);
+    }
+    if (still.empty()) break;
+    if (still.size() != active.size()) {
+      active.swap(still);
+      RC(upload_group<T>(h, gd, all, active, g));
+      version++;
+    }
+    int64_t nb = std::min<int64_t>(P, max_iter - kmin);
+    if (nb < 1) nb = 1;
+    if (nb == P && h->o.use_graph) {
+      RC(capture<T>(h, gs, dI, g, P, tol, max_iter, version));
+      HC(hipGraphLaunch(gs.exec, h->hs));
+    } else {
+      for (int64_t i = 0; i < nb; i++) launch_attempt<T>(dI, g, h->hs);
+      launch_evaluate<T>(dI, g, tol, max_iter, h->hs);
+      HK();
+    }
+  }
+  return PDHG_OK;
+}
+
+void fill_info(pdhg_info *info, const CtlState &s, int status, int64_t attempts_fp32,
+               double setup_s, double solve_s) {
+  memset(info, 0, sizeof *info);
+  info->status = status;
+  info->which = s.which;
+  info->attempts = s.k;
+  info->attempts_fp32 = attempts_fp32;
+  info->accepted = s.accepted;
+  info->restarts = s.restarts;
+  info->primal_obj = s.pobj;
+  info->dual_obj = s.dobj;
+  info->rel_primal = s.rel_p;
+  info->rel_dual = s.rel_d;
+  info->rel_gap = s.rel_gap;
+  info->rel_kkt = s.rel_kkt;
+  info->eta = s.eta;
+  info->omega = s.omega;
+  info->setup_s = setup_s;
+  info->solve_s = solve_s;
+}
+
+// Solve a group of prepared instances (start points and result pointers set)
+// with the precision of handle h's options.
+int solve_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
+                std::vector<Inst<float>> &i32, GraphSlot *gslots, bool reuse, double t0,
+                std::vector<int> &status, std::vector<CtlState> &fin,
+                std::vector<int64_t> &att32, std::vector<int> &final_fp32) {
+  const int B = (int)i64.size();
+  std::vector<int> all(B);
+  for (int i = 0; i < B; i++) all[i] = i;
+  status.assign(B, 0);
+  fin.assign(B, CtlState{});
+  att32.assign(B, 0);
+  final_fp32.assign(B, 0);
+  Groups g{};
+  if (h->o.precision == PDHG_FP64) {
+    RC(upload_group<double>(h, gd, i64, all, g));
+    launch_init_point<double>(gd.d64, g, h->hs);
+    HK();
+    return run_group<double>(h, gd, i64, all, h->o.tol, h->o.max_iter, t0, 0, gslots[0], reuse,
+                             status, fin);
+  }
+  // FP32 phase: FP32 matrix, iterates and SpMVs; FP64 evaluation and control
+  double tol32 = h->o.polish_tol > h->o.tol ? h->o.polish_tol : h->o.tol;
+  RC(upload_group<float>(h, gd, i32, all, g));
+  launch_init_point<float>(gd.d32, g, h->hs);
+  HK();
+  RC(run_group<float>(h, gd, i32, all, tol32, h->o.max_iter, t0, 300, gslots[1], reuse, status,
+                      fin));
+  std::vector<int> polish;
+  for (int i = 0; i < B; i++) {
+    att32[i] = fin[i].k;
+    final_fp32[i] = 1;
+    if (status[i] == 0 || (status[i] == PDHG_OPTIMAL && tol32 > h->o.tol)) polish.push_back(i);
+  }
+  if (polish.empty()) return PDHG_OK;
+  // FP64 refinement from the FP32 iterates (both tables describe the same instances)
+  RC(upload_group<float>(h, gd, i32, polish, g));
+  Groups g64{};
+  RC(upload_group<double>(h, gd, i64, polish, g64));
+  launch_switch_to_fp64(gd.d32, gd.d64, g64, h->hs);
+  HK();
+  std::vector<int> st2(B, 0);
+  std::vector<CtlState> fin2(B);
+  RC(run_group<double>(h, gd, i64, polish, h->o.tol, h->o.max_iter, t0, 0, gslots[0],
+                       reuse && B == 1, st2, fin2));
+  for (int i : polish) {
+    status[i] = st2[i];
+    fin[i] = fin2[i];
+    final_fp32[i] = 0;
+  }
+  return PDHG_OK;
+}
+
+// Unscale every instance's result from the precision its solve ended in.
+int unscale_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
+                  std::vector<Inst<float>> &i32, const std::vector<int> &final_fp32) {
+  std::vector<int> a64, a32;
+  for (int i = 0; i < (int)i64.size(); i++) (final_fp32[i] ? a32 : a64).push_back(i);
+  Groups g{};
+  if (!a64.empty()) {
+    RC(upload_group<double>(h, gd, i64, a64, g));
+    launch_unscale<double>(gd.d64, g, h->hs);
+    HK();
+  }
+  if (!a32.empty()) {
+    RC(upload_group<float>(h, gd, i32, a32, g));
+    launch_unscale<float>(gd.d32, g, h->hs);
+    HK();
+  }
   return PDHG_OK;
 }
 
@@ -488,6 +693,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->polish_tol = 0.0;
   o->pw_update = 1;
   o->pw_theta = 0.5;
+  o->tiles_per_block = 0;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -534,25 +740,13 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
   h->on_device = lp->on_device;
   h->user = (hipStream_t)stream;
   layout(h, (void *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255));
-  h->nblk_rows = (int)nblk(h->m);
-  h->nblk_cols = (int)nblk(h->n);
-  auto cleanup = [&](int code) {
-    pdhg_destroy(h);
-    return code;
-  };
-#define SC(call)                                                                            \
-  do {                                                                                      \
-    int r_ = (call);                                                                        \
-    if (r_) return cleanup(r_);                                                             \
-  } while (0)
   auto setup_body = [&]() -> int {
     HC(hipStreamCreateWithFlags(&h->hs, hipStreamNonBlocking));
     HC(hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
-    HC(hipHostMalloc((void **)&h->host_st, sizeof(CtlState), hipHostMallocDefault));
-    int r = enter(h);
-    if (r) return r;
+    HC(hipHostMalloc((void **)&h->grp.hstates, sizeof(CtlState), hipHostMallocDefault));
+    RC(enter(h));
     int64_t m = h->m, n = h->n, nnz = h->nnz;
-    hipMemcpyKind kd = in_kind(h);
+    hipMemcpyKind kd = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HC(hipMemcpyAsync(h->rp, lp->row_ptr, sizeof(int32_t) * (m + 1), kd, h->hs));
     if (nnz) {
       HC(hipMemcpyAsync(h->ci, lp->col_idx, sizeof(int32_t) * nnz, kd, h->hs));
@@ -580,13 +774,13 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
     launch_transpose(h->rp, h->ci, h->v, m, n, nnz, h->cp, h->ri, h->vt, h->tmp_next, h->scan_tmp,
                      h->hs);
     HK();
-    // scaling: rs in YA (m), cs in XA (n)
+    // scaling: row factors in YA (m), column factors in XA (n)
     launch_fill(h->Dr, 1.0, m, h->hs);
     launch_fill(h->Dc, 1.0, n, h->hs);
     int passes = h->o.scaling_iters + (h->o.pock_chambolle ? 1 : 0);
     for (int it = 0; it < passes; it++)
       launch_scale_pass(h->rp, h->ci, h->v, h->cp, h->ri, h->vt, m, n,
-                        it == h->o.scaling_iters ? 1 : 0, h->YA, h->XA, h->Dr, h->Dc, h->hs);
+                        it == h->o.scaling_iters ? 1 : 0, h->it.YA, h->it.XA, h->Dr, h->Dc, h->hs);
     launch_scale_vectors(h->b0, h->c0, h->l0, h->u0, h->Dr, h->Dc, m, n, h->b, h->c, h->l, h->u,
                          h->hs);
     HK();
@@ -603,21 +797,14 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
       if (hp[j + 1] - hp[j] > PDHG_LONG_SEG) lc.push_back((int32_t)j);
     h->n_long_rows = (int)lr.size();
     h->n_long_cols = (int)lc.size();
-    h->tpb_rows = h->o.tiles_per_block > 0
-                      ? h->o.tiles_per_block
-                      : std::max(1, (h->nblk_rows + PDHG_TARGET_GROUPS - 1) / PDHG_TARGET_GROUPS);
-    h->tpb_cols = h->o.tiles_per_block > 0
-                      ? h->o.tiles_per_block
-                      : std::max(1, (h->nblk_cols + PDHG_TARGET_GROUPS - 1) / PDHG_TARGET_GROUPS);
-    h->grid_rows = h->n_long_rows + (h->nblk_rows + h->tpb_rows - 1) / h->tpb_rows;
-    h->grid_cols = h->n_long_cols + (h->nblk_cols + h->tpb_cols - 1) / h->tpb_cols;
+    set_grids(h);
     if (!lr.empty())
       HC(hipMemcpyAsync(h->long_rows, lr.data(), sizeof(int32_t) * lr.size(), hipMemcpyHostToDevice,
                         h->hs));
     if (!lc.empty())
       HC(hipMemcpyAsync(h->long_cols, lc.data(), sizeof(int32_t) * lc.size(), hipMemcpyHostToDevice,
                         h->hs));
-    launch_init_ctl(h->v, nnz, h->b, h->c, h->b0, h->c0, m, n, h->scratch, h->nscratch, h->st,
+    launch_init_ctl(h->v, nnz, h->b, h->c, h->b0, h->c0, m, n, h->scratch, h->nscratch, h->it.st,
                     h->o.step_mode, h->o.step_mode == 1 ? h->o.fixed_eta : 0.0, h->o.fixed_omega,
                     h->hs);
     if (h->o.precision == PDHG_MIXED) {
@@ -630,12 +817,13 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
     }
     HK();
     HC(hipStreamSynchronize(h->hs));
-    r = leave(h);
-    if (r) return r;
-    return PDHG_OK;
+    return leave(h);
   };
-  SC(setup_body());
-#undef SC
+  rc = setup_body();
+  if (rc) {
+    pdhg_destroy(h);
+    return rc;
+  }
   h->setup_s = now_s() - t0;
   *out = h;
   return PDHG_OK;
@@ -644,92 +832,278 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
 int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, double *y,
                pdhg_info *info) {
   if (!h || !x || !y || !info) return fail(PDHG_ERR_ARG, "null argument");
-  int rc = enter(h);
-  if (rc) return rc;
+  RC(enter(h));
   double t0 = now_s();
-  memset(info, 0, sizeof *info);
-  // stage host start vectors in the average buffers (free before the first evaluation)
+  // host start vectors are staged in the average buffers (free until the first evaluation)
   const double *dx0 = x0, *dy0 = y0;
   if (!h->on_device) {
     if (x0) {
-      HC(hipMemcpyAsync(h->XA, x0, sizeof(double) * h->n, hipMemcpyHostToDevice, h->hs));
-      dx0 = h->XA;
+      HC(hipMemcpyAsync(h->it.XA, x0, sizeof(double) * h->n, hipMemcpyHostToDevice, h->hs));
+      dx0 = h->it.XA;
     }
     if (y0) {
-      HC(hipMemcpyAsync(h->YA, y0, sizeof(double) * h->m, hipMemcpyHostToDevice, h->hs));
-      dy0 = h->YA;
+      HC(hipMemcpyAsync(h->it.YA, y0, sizeof(double) * h->m, hipMemcpyHostToDevice, h->hs));
+      dy0 = h->it.YA;
     }
   }
-  int status = 0;
-  bool final_fp32 = false;
-  int64_t attempts_fp32 = 0;
-  EvalView<double> e = eval_view<double>(h);
-  if (h->o.precision == PDHG_FP64) {
-    launch_init_point<double>(e, h->long_rows, h->n_long_rows, dx0, dy0, h->st, h->AXA, h->hs);
-    HK();
-    rc = run_blocks<double>(h, h->o.tol, h->o.max_iter, t0, &status);
-    if (rc) return rc;
-  } else {
-    // FP32 phase: FP32 matrix, iterates and SpMVs; FP64 evaluation and control
-    EvalView<float> ef = eval_view<float>(h);
-    double tol32 = h->o.polish_tol > h->o.tol ? h->o.polish_tol : h->o.tol;
-    launch_init_point<float>(ef, h->long_rows, h->n_long_rows, dx0, dy0, h->st, h->AXA, h->hs);
-    HK();
-    rc = run_blocks<float>(h, tol32, h->o.max_iter, t0, &status, 300);
-    if (rc) return rc;
-    attempts_fp32 = h->host_st->k;
-    final_fp32 = true;
-    bool polish = (status == 0) || (status == PDHG_OPTIMAL && tol32 > h->o.tol);
-    if (polish) {
-      // FP64 refinement from the FP32 iterate
-      launch_switch_to_fp64(ef, e, h->long_rows, h->n_long_rows, h->st, h->hs);
-      HK();
-      rc = run_blocks<double>(h, h->o.tol, h->o.max_iter, t0, &status);
-      if (rc) return rc;
-      final_fp32 = false;
-    }
+  InstData d = base_data(h);
+  std::vector<Inst<double>> i64{make_inst<double>(h, d, h->it)};
+  std::vector<Inst<float>> i32{make_inst<float>(h, d, h->it)};
+  double *xo = h->on_device ? x : h->it.ATYA;
+  double *yo = h->on_device ? y : h->it.AXA;
+  i64[0].x0 = i32[0].x0 = dx0;
+  i64[0].y0 = i32[0].y0 = dy0;
+  i64[0].xout = i32[0].xout = xo;
+  i64[0].yout = i32[0].yout = yo;
+  std::vector<int> status, final_fp32;
+  std::vector<CtlState> fin;
+  std::vector<int64_t> att32;
+  RC(solve_group(h, h->grp, i64, i32, h->graph, true, t0, status, fin, att32, final_fp32));
+  RC(unscale_group(h, h->grp, i64, i32, final_fp32));
+  if (!h->on_device) {
+    HC(hipMemcpyAsync(x, xo, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->hs));
+    HC(hipMemcpyAsync(y, yo, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->hs));
   }
-  // unscale into the caller's arrays
-  if (h->on_device) {
-    if (final_fp32)
-      launch_unscale<float>(eval_view<float>(h), h->st, x, y, h->hs);
-    else
-      launch_unscale<double>(e, h->st, x, y, h->hs);
-    HK();
-  } else {
-    if (final_fp32)
-      launch_unscale<float>(eval_view<float>(h), h->st, h->ATYA, h->AXA, h->hs);
-    else
-      launch_unscale<double>(e, h->st, h->ATYA, h->AXA, h->hs);
-    HK();
-    HC(hipMemcpyAsync(x, h->ATYA, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->hs));
-    HC(hipMemcpyAsync(y, h->AXA, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->hs));
-  }
-  rc = read_state(h);
-  if (rc) return rc;
-  const CtlState *s = h->host_st;
-  info->status = status;
-  info->which = s->which;
-  info->attempts = s->k;
-  info->attempts_fp32 = attempts_fp32;
-  info->accepted = s->accepted;
-  info->restarts = s->restarts;
-  info->primal_obj = s->pobj;
-  info->dual_obj = s->dobj;
-  info->rel_primal = s->rel_p;
-  info->rel_dual = s->rel_d;
-  info->rel_gap = s->rel_gap;
-  info->rel_kkt = s->rel_kkt;
-  info->eta = s->eta;
-  info->omega = s->omega;
-  info->setup_s = h->setup_s;
-  info->solve_s = now_s() - t0;
+  HC(hipStreamSynchronize(h->hs));
+  fill_info(info, fin[0], status[0], h->o.precision == PDHG_MIXED ? att32[0] : 0, h->setup_s,
+            now_s() - t0);
   return leave(h);
 }
 
-int pdhg_solve_batch(pdhg_handle *const *, int, const pdhg_instance *, int, double *const *,
-                     double *const *, pdhg_info *) {
-  return fail(PDHG_ERR_STATE, "batched solve not available in this build");
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched solve
+
+namespace {
+
+struct BatchPlan {
+  std::vector<IterBufs> it;
+  // per-instance problem vectors that differ from the base (nullptr: shared)
+  std::vector<double *> b0, c0, l0, u0, b, c, l, u;
+  std::vector<float *> bf, cf, lf, uf;
+  std::vector<uint8_t *> vk;
+  std::vector<int32_t *> fix_idx;
+  std::vector<double *> fix_val;
+  std::vector<double *> xo, yo;  // staging for host results
+  GroupDev gd;
+};
+
+size_t batch_layout(pdhg_handle *const *hs, const pdhg_instance *inst, int batch, void *base,
+                    BatchPlan &P) {
+  Carver cv(base);
+  P.it.assign(batch, IterBufs{});
+  std::vector<double *> nd(batch, nullptr);
+  std::vector<float *> nf(batch, nullptr);
+  P.b0 = P.c0 = P.l0 = P.u0 = P.b = P.c = P.l = P.u = nd;
+  P.bf = P.cf = P.lf = P.uf = nf;
+  P.vk.assign(batch, nullptr);
+  P.fix_idx.assign(batch, nullptr);
+  P.fix_val.assign(batch, nullptr);
+  P.xo = P.yo = nd;
+  for (int k = 0; k < batch; k++) {
+    const pdhg_handle *h = hs[inst[k].base];
+    int64_t m = h->m, n = h->n;
+    bool mixed = h->o.precision == PDHG_MIXED;
+    carve_iter(cv, P.it[k], m, n, h->grid_rows, h->grid_cols, mixed);
+    if (inst[k].b) {
+      P.b0[k] = cv.take<double>(m);
+      P.b[k] = cv.take<double>(m);
+      if (mixed) P.bf[k] = cv.take<float>(m);
+    }
+    if (inst[k].c) {
+      P.c0[k] = cv.take<double>(n);
+      P.c[k] = cv.take<double>(n);
+      if (mixed) P.cf[k] = cv.take<float>(n);
+    }
+    if (inst[k].l || inst[k].u || inst[k].n_fix > 0) {
+      P.l0[k] = cv.take<double>(n);
+      P.u0[k] = cv.take<double>(n);
+      P.l[k] = cv.take<double>(n);
+      P.u[k] = cv.take<double>(n);
+      P.vk[k] = cv.take<uint8_t>(n);
+      if (mixed) {
+        P.lf[k] = cv.take<float>(n);
+        P.uf[k] = cv.take<float>(n);
+      }
+    }
+    if (inst[k].n_fix > 0) {
+      P.fix_idx[k] = cv.take<int32_t>(inst[k].n_fix);
+      P.fix_val[k] = cv.take<double>(inst[k].n_fix);
+    }
+    if (!h->on_device) {
+      P.xo[k] = cv.take<double>(n);
+      P.yo[k] = cv.take<double>(m);
+    }
+  }
+  carve_group(cv, P.gd, batch);
+  return cv.off + 256;
+}
+
+int check_batch(pdhg_handle *const *handles, int n_handles, const pdhg_instance *inst, int batch) {
+  if (!handles || n_handles < 1 || !inst || batch < 1)
+    return fail(PDHG_ERR_ARG, "empty batch or null arguments");
+  for (int i = 0; i < n_handles; i++) {
+    if (!handles[i]) return fail(PDHG_ERR_ARG, "null handle %d", i);
+    if (handles[i]->o.precision != handles[0]->o.precision)
+      return fail(PDHG_ERR_ARG, "all handles of a batch must use the same precision");
+  }
+  for (int k = 0; k < batch; k++) {
+    if (inst[k].base < 0 || inst[k].base >= n_handles)
+      return fail(PDHG_ERR_ARG, "instance %d: base %d out of range", k, inst[k].base);
+    if (inst[k].n_fix < 0 || (inst[k].n_fix > 0 && (!inst[k].fix_idx || !inst[k].fix_val)))
+      return fail(PDHG_ERR_ARG, "instance %d: bad fixings", k);
+    const pdhg_handle *h = handles[inst[k].base];
+    if (!h->on_device)
+      for (int64_t q = 0; q < inst[k].n_fix; q++)
+        if (inst[k].fix_idx[q] < 0 || inst[k].fix_idx[q] >= h->n || !isfinite(inst[k].fix_val[q]))
+          return fail(PDHG_ERR_ARG, "instance %d: fixing %lld out of range or not finite", k,
+                      (long long)q);
+  }
+  return PDHG_OK;
+}
+
+struct PinnedStates {
+  CtlState *p = nullptr;
+  ~PinnedStates() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int pdhg_batch_workspace_bytes(pdhg_handle *const *handles, int n_handles,
+                               const pdhg_instance *inst, int batch, size_t *bytes) {
+  int rc = check_batch(handles, n_handles, inst, batch);
+  if (rc) return rc;
+  if (!bytes) return fail(PDHG_ERR_ARG, "null argument");
+  BatchPlan P;
+  *bytes = batch_layout(handles, inst, batch, nullptr, P);
+  return PDHG_OK;
+}
+
+int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_instance *inst,
+                     int batch, void *workspace, size_t ws_bytes, double *const *x,
+                     double *const *y, pdhg_info *infos) {
+  int rc = check_batch(handles, n_handles, inst, batch);
+  if (rc) return rc;
+  if (!x || !y || !infos) return fail(PDHG_ERR_ARG, "null output arrays");
+  for (int k = 0; k < batch; k++)
+    if (!x[k] || !y[k]) return fail(PDHG_ERR_ARG, "instance %d: null output", k);
+  BatchPlan P;
+  size_t need = batch_layout(handles, inst, batch, nullptr, P);
+  if (!workspace || ws_bytes < need)
+    return fail(PDHG_ERR_OOM, "batch workspace of %zu bytes, need %zu", ws_bytes, need);
+  batch_layout(handles, inst, batch, (void *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255), P);
+  pdhg_handle *h = handles[0];  // the batch runs on this handle's stream
+  for (int i = 0; i < n_handles; i++) RC(enter(handles[i]));
+  for (int i = 1; i < n_handles; i++) {
+    pdhg_handle *hi = handles[i];
+    if (hipStreamSynchronize(hi->hs) != hipSuccess) return fail(PDHG_ERR_HIP, "stream sync failed");
+  }
+  double t0 = now_s();
+  PinnedStates pin;
+  HC(hipHostMalloc((void **)&pin.p, sizeof(CtlState) * batch, hipHostMallocDefault));
+  P.gd.hstates = pin.p;
+  std::vector<Inst<double>> i64(batch);
+  std::vector<Inst<float>> i32(batch);
+  const bool mixed = h->o.precision == PDHG_MIXED;
+  for (int k = 0; k < batch; k++) {
+    const pdhg_instance &q = inst[k];
+    pdhg_handle *hb = handles[q.base];
+    int64_t m = hb->m, n = hb->n;
+    hipMemcpyKind kd = hb->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    IterBufs &ib = P.it[k];
+    InstData d = base_data(hb);
+    if (q.b) {  // b^ = Dr b
+      HC(hipMemcpyAsync(P.b0[k], q.b, sizeof(double) * m, kd, h->hs));
+      launch_scale_vectors(P.b0[k], nullptr, nullptr, nullptr, hb->Dr, hb->Dc, m, 0, P.b[k], nullptr,
+                           nullptr, nullptr, h->hs);
+      d.b = P.b[k];
+      if (mixed) {
+        launch_cast_f32(P.b[k], P.bf[k], m, h->hs);
+        d.bf = P.bf[k];
+      }
+    }
+    const double *l0 = hb->l0, *u0 = hb->u0;
+    if (P.l0[k]) {  // bounds: overrides, then fixings l = u = value
+      HC(hipMemcpyAsync(P.l0[k], q.l ? q.l : hb->l0, sizeof(double) * n,
+                        q.l ? kd : hipMemcpyDeviceToDevice, h->hs));
+      HC(hipMemcpyAsync(P.u0[k], q.u ? q.u : hb->u0, sizeof(double) * n,
+                        q.u ? kd : hipMemcpyDeviceToDevice, h->hs));
+      if (q.n_fix > 0) {
+        HC(hipMemcpyAsync(P.fix_idx[k], q.fix_idx, sizeof(int32_t) * q.n_fix, kd, h->hs));
+        HC(hipMemcpyAsync(P.fix_val[k], q.fix_val, sizeof(double) * q.n_fix, kd, h->hs));
+        launch_fix_bounds(P.l0[k], P.u0[k], P.fix_idx[k], P.fix_val[k], q.n_fix, h->hs);
+      }
+      launch_var_kind(P.l0[k], P.u0[k], n, P.vk[k], h->hs);
+      l0 = P.l0[k];
+      u0 = P.u0[k];
+    }
+    if (q.c) HC(hipMemcpyAsync(P.c0[k], q.c, sizeof(double) * n, kd, h->hs));
+    if (q.c || P.l0[k]) {
+      // c^ = Dc c, l^ = l / Dc, u^ = u / Dc; untouched outputs go to free buffers
+      launch_scale_vectors(nullptr, q.c ? P.c0[k] : hb->c0, l0, u0, hb->Dr, hb->Dc, 0, n, nullptr,
+                           q.c ? P.c[k] : ib.XA, P.l0[k] ? P.l[k] : ib.XL,
+                           P.l0[k] ? P.u[k] : ib.ATY, h->hs);
+      if (q.c) {
+        d.c = P.c[k];
+        if (mixed) {
+          launch_cast_f32(P.c[k], P.cf[k], n, h->hs);
+          d.cf = P.cf[k];
+        }
+      }
+      if (P.l0[k]) {
+        d.l = P.l[k];
+        d.u = P.u[k];
+        d.vk = P.vk[k];
+        if (mixed) {
+          launch_cast_f32(P.l[k], P.lf[k], n, h->hs);
+          launch_cast_f32(P.u[k], P.uf[k], n, h->hs);
+          d.lf = P.lf[k];
+          d.uf = P.uf[k];
+        }
+      }
+    }
+    HK();
+    // initial step size, primal weight and the norms of this instance's b and c
+    launch_init_ctl(hb->v, hb->nnz, d.b, d.c, q.b ? P.b0[k] : hb->b0, q.c ? P.c0[k] : hb->c0, m, n,
+                    hb->scratch, hb->nscratch, ib.st, hb->o.step_mode,
+                    hb->o.step_mode == 1 ? hb->o.fixed_eta : 0.0, hb->o.fixed_omega, h->hs);
+    HK();
+    HC(hipStreamSynchronize(h->hs));  // the base's scratch is reused by the next instance
+    i64[k] = make_inst<double>(hb, d, ib);
+    i32[k] = make_inst<float>(hb, d, ib);
+    double *xo = hb->on_device ? x[k] : P.xo[k];
+    double *yo = hb->on_device ? y[k] : P.yo[k];
+    i64[k].xout = i32[k].xout = xo;
+    i64[k].yout = i32[k].yout = yo;
+  }
+  std::vector<int> status, final_fp32;
+  std::vector<CtlState> fin;
+  std::vector<int64_t> att32;
+  GraphSlot gs[2];
+  rc = solve_group(h, P.gd, i64, i32, gs, false, t0, status, fin, att32, final_fp32);
+  for (auto &g : gs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (rc) return rc;
+  RC(unscale_group(h, P.gd, i64, i32, final_fp32));
+  for (int k = 0; k < batch; k++) {
+    pdhg_handle *hb = handles[inst[k].base];
+    if (!hb->on_device) {
+      HC(hipMemcpyAsync(x[k], P.xo[k], sizeof(double) * hb->n, hipMemcpyDeviceToHost, h->hs));
+      HC(hipMemcpyAsync(y[k], P.yo[k], sizeof(double) * hb->m, hipMemcpyDeviceToHost, h->hs));
+    }
+  }
+  HC(hipStreamSynchronize(h->hs));
+  double dt = now_s() - t0;
+  for (int k = 0; k < batch; k++)
+    fill_info(&infos[k], fin[k], status[k], mixed ? att32[k] : 0, handles[inst[k].base]->setup_s,
+              dt);
+  for (int i = 0; i < n_handles; i++) RC(leave(handles[i]));
+  return PDHG_OK;
 }
 
 int pdhg_backward(pdhg_handle *, double, double *, double *) {
@@ -745,37 +1119,35 @@ void pdhg_destroy(pdhg_handle *h) {
     (void)hipStreamDestroy(h->hs);
   }
   if (h->ev) (void)hipEventDestroy(h->ev);
-  if (h->host_st) (void)hipHostFree(h->host_st);
+  if (h->grp.hstates) (void)hipHostFree(h->grp.hstates);
   delete h;
 }
 
 int pdhg_export_setup(pdhg_handle *h, uint8_t *var_kind, int32_t *colptr, int32_t *rowidx,
                       double *valT, double *val_s, double *Dr, double *Dc) {
   if (!h) return fail(PDHG_ERR_ARG, "null handle");
-  int rc = enter(h);
-  if (rc) return rc;
+  RC(enter(h));
   auto d2h = [&](void *dst, const void *src, size_t bytes) -> int {
     if (dst) HC(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->hs));
     return PDHG_OK;
   };
-  if ((rc = d2h(var_kind, h->vk, h->n))) return rc;
-  if ((rc = d2h(colptr, h->cp, sizeof(int32_t) * (h->n + 1)))) return rc;
-  if ((rc = d2h(rowidx, h->ri, sizeof(int32_t) * h->nnz))) return rc;
-  if ((rc = d2h(valT, h->vt, sizeof(double) * h->nnz))) return rc;
-  if ((rc = d2h(val_s, h->v, sizeof(double) * h->nnz))) return rc;
-  if ((rc = d2h(Dr, h->Dr, sizeof(double) * h->m))) return rc;
-  if ((rc = d2h(Dc, h->Dc, sizeof(double) * h->n))) return rc;
+  RC(d2h(var_kind, h->vk, h->n));
+  RC(d2h(colptr, h->cp, sizeof(int32_t) * (h->n + 1)));
+  RC(d2h(rowidx, h->ri, sizeof(int32_t) * h->nnz));
+  RC(d2h(valT, h->vt, sizeof(double) * h->nnz));
+  RC(d2h(val_s, h->v, sizeof(double) * h->nnz));
+  RC(d2h(Dr, h->Dr, sizeof(double) * h->m));
+  RC(d2h(Dc, h->Dc, sizeof(double) * h->n));
   HC(hipStreamSynchronize(h->hs));
   return leave(h);
 }
 
 int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out) {
   if (!h || !x || !out) return fail(PDHG_ERR_ARG, "null argument");
-  int rc = enter(h);
-  if (rc) return rc;
+  RC(enter(h));
   int64_t nin = transpose ? h->m : h->n, nout = transpose ? h->n : h->m;
-  double *din = transpose ? h->YA : h->XA;
-  double *dout = transpose ? h->ATYA : h->AXA;
+  double *din = transpose ? h->it.YA : h->it.XA;
+  double *dout = transpose ? h->it.ATYA : h->it.AXA;
   HC(hipMemcpyAsync(din, x, sizeof(double) * nin, hipMemcpyHostToDevice, h->hs));
   if (transpose)
     launch_spmv(h->cp, h->ri, h->vt, h->n, din, dout, h->hs);
@@ -792,17 +1164,22 @@ int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out) {
 namespace {
 template <typename T>
 int time_kernels(pdhg_handle *h, int attempts, double *ms) {
-  IterView<T> w = iter_view<T>(h);
+  InstData d = base_data(h);
+  std::vector<Inst<T>> one{make_inst<T>(h, d, h->it)};
+  std::vector<int> act{0};
+  Groups g{};
+  RC(upload_group<T>(h, h->grp, one, act, g));
+  const Inst<T> *dI = dev_insts<T>(h->grp);
   hipEvent_t ev[4];
   for (auto &e : ev) HC(hipEventCreate(&e));
   double acc[4] = {0, 0, 0, 0};
   for (int a = 0; a < attempts; a++) {
     HC(hipEventRecord(ev[0], h->hs));
-    launch_primal<T>(w, h->st, h->hs);
+    launch_primal<T>(dI, g, h->hs);
     HC(hipEventRecord(ev[1], h->hs));
-    launch_dual<T>(w, h->st, h->hs);
+    launch_dual<T>(dI, g, h->hs);
     HC(hipEventRecord(ev[2], h->hs));
-    launch_control<T>(w, h->st, h->hs);
+    launch_control<T>(dI, g, h->hs);
     HC(hipEventRecord(ev[3], h->hs));
     HK();
     HC(hipEventSynchronize(ev[3]));
@@ -822,10 +1199,9 @@ int time_kernels(pdhg_handle *h, int attempts, double *ms) {
 
 extern "C" int pdhg_time_kernels(pdhg_handle *h, int attempts, double *ms_out) {
   if (!h || !ms_out || attempts < 1) return fail(PDHG_ERR_ARG, "bad argument");
-  int rc = enter(h);
-  if (rc) return rc;
-  rc = h->o.precision == PDHG_MIXED ? time_kernels<float>(h, attempts, ms_out)
-                                    : time_kernels<double>(h, attempts, ms_out);
+  RC(enter(h));
+  int rc = h->o.precision == PDHG_MIXED ? time_kernels<float>(h, attempts, ms_out)
+                                        : time_kernels<double>(h, attempts, ms_out);
   if (rc) return rc;
   return leave(h);
 }

@@ -100,33 +100,54 @@ void launch_scale_vectors(const double *b0, const double *c0, const double *l0,
                           int64_t m, int64_t n, double *b, double *c, double *l,
                           double *u, hipStream_t s);
 void launch_fill(double *p, double v, int64_t n, hipStream_t s);
+void launch_fix_bounds(double *l, double *u, const int32_t *idx, const double *val, int64_t nfix,
+                       hipStream_t s);
 void launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
 void launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 
+// One instance of a (possibly batched) solve: views of its problem data and
+// iterates, its control state, start point and result buffers.
+template <typename T>
+struct Inst {
+  IterView<T> w;
+  EvalView<T> e;
+  CtlState *st;
+  const double *x0, *y0;  // start point, original space (device) or null
+  double *xout, *yout;    // unscaled result (device)
+};
+
+// Block-to-instance maps of a grouped launch: exclusive prefix sums of each
+// instance's block count for every kernel shape (device memory, ninst + 1
+// entries); the totals are the grid sizes.
+struct Groups {
+  int ninst;
+  const int32_t *p_primal, *p_dual;  // attempt kernels
+  const int32_t *p_rows, *p_cols;    // one block per 256 rows / columns
+  const int32_t *p_lrows, *p_lcols;  // one block per long row / column
+  int n_primal, n_dual, n_rows, n_cols, n_lrows, n_lcols;
+};
+
 // ---------------------------------------------------------------------------
-// launchers (iterate.hip)
+// launchers (iterate.hip); every launch covers all instances of the group
 template <typename T>
-void launch_attempt(const IterView<T> &w, CtlState *st, int64_t max_iter, hipStream_t s);
+void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s);
 template <typename T>
-void launch_primal(const IterView<T> &w, CtlState *st, hipStream_t s);
+void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s);
 template <typename T>
-void launch_dual(const IterView<T> &w, CtlState *st, hipStream_t s);
+void launch_control(const Inst<T> *I, const Groups &g, hipStream_t s);
 template <typename T>
-void launch_control(const IterView<T> &w, CtlState *st, hipStream_t s);
+void launch_attempt(const Inst<T> *I, const Groups &g, hipStream_t s);
 template <typename T>
-void launch_evaluate_ll(const EvalView<T> &e, const int32_t *long_rows, int n_long_rows,
-                        const int32_t *long_cols, int n_long_cols, CtlState *st, double tol,
-                        int64_t max_iter, hipStream_t s);
+void launch_evaluate(const Inst<T> *I, const Groups &g, double tol, int64_t max_iter,
+                     hipStream_t s);
 template <typename T>
-void launch_init_point(const EvalView<T> &e, const int32_t *long_rows, int n_long_rows,
-                       const double *x0, const double *y0, CtlState *st, double *ax_tmp,
-                       hipStream_t s);
-void launch_switch_to_fp64(const EvalView<float> &ef, const EvalView<double> &ed,
-                           const int32_t *long_rows, int n_long_rows, CtlState *st,
+void launch_init_point(const Inst<T> *I, const Groups &g, hipStream_t s);
+void launch_switch_to_fp64(const Inst<float> *If, const Inst<double> *Id, const Groups &g,
                            hipStream_t s);
 template <typename T>
-void launch_unscale(const EvalView<T> &e, const CtlState *st, double *x, double *y,
-                    hipStream_t s);
+void launch_unscale(const Inst<T> *I, const Groups &g, hipStream_t s);
+template <typename T>
+void launch_gather_states(const Inst<T> *I, int n, CtlState *out, hipStream_t s);
 void launch_init_ctl(const double *v, int64_t nnz, const double *b, const double *c,
                      const double *b0, const double *c0, int64_t m, int64_t n,
                      double *scratch, int nscratch, CtlState *st, int step_mode,

@@ -9,12 +9,18 @@
 // current and the averaged iterate, decides termination and restarts.
 // All control state lives in device memory so that a block of attempts can be
 // replayed as one HIP graph; the host reads the state only between blocks.
+//
+// Every kernel is grouped: one launch serves all instances of a batch.  A
+// workgroup finds its instance by a binary search of the launch's prefix
+// table, after the XCD remapping, so each XCD walks contiguous blocks of one
+// instance.  A single solve is a group of one.
 #include "internal.h"
 
 #include <math.h>
 
 namespace {
 
+inline unsigned grid_of(int n) { return (unsigned)(n > 0 ? n : 1); }
 inline unsigned grid_for(int64_t n) {
   int64_t g = (n + PDHG_BLOCK - 1) / PDHG_BLOCK;
   return (unsigned)(g > 0 ? g : 1);
@@ -29,6 +35,19 @@ __device__ inline int xcd_remap(int b, int nb) {
   return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
+// Instance owning logical block b: the largest i with pre[i] <= b.
+__device__ inline int find_inst(const int32_t *pre, int ninst, int b) {
+  int lo = 0, hi = ninst;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (pre[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 template <typename T>
 __device__ inline T clamp_box(T x, T lo, T hi) {
   // explicit comparisons keep NaN visible (fmin/fmax would drop it)
@@ -36,7 +55,7 @@ __device__ inline T clamp_box(T x, T lo, T hi) {
 }
 
 // Deterministic block reduction of NQ doubles (fixed shuffle tree, then the
-// four waves in order).  Bit q of maxmask selects max instead of sum.
+// waves in order).  Bit q of maxmask selects max instead of sum.
 template <int NQ, int BS = PDHG_BLOCK>
 __device__ inline void block_reduce(double (&v)[NQ], unsigned maxmask, double *out) {
   __shared__ double lds[BS / 64][NQ];
@@ -98,8 +117,8 @@ __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t str
 // with the gathered vector into LDS, and each lane then sums its own row from
 // LDS in CSR order.  Tiles whose nonzeros do not fit the LDS buffer fall back
 // to one lane per row.  Rows longer than PDHG_LONG_SEG get a workgroup each
-// (the first blocks of the grid).  Each workgroup covers `tpb` consecutive
-// tiles and writes one partial per reduced quantity.
+// (the first blocks of the instance).  Each workgroup covers `tpb`
+// consecutive tiles and writes one partial per reduced quantity.
 
 #define TILE_CAP 2048
 
@@ -110,8 +129,8 @@ __device__ inline T ld_stream(const T *p) {
   return __builtin_nontemporal_load(p);
 }
 
-// Row dot products of one 256-row tile: s = sum_k v[k] x[idx[k]] over row
-// r0 + threadIdx.x.  rs/re are the row's bounds (already loaded).
+// Row dot product of row r0 + threadIdx.x in one 256-row tile:
+// sum_k v[k] x[idx[k]].  rs/re are the row's bounds (already loaded).
 template <typename T>
 __device__ inline T tile_rowdot(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                 const T *__restrict__ v, const T *__restrict__ x, int64_t nrows,
@@ -144,9 +163,13 @@ __device__ inline void primal_finish(const IterView<T> &w, int64_t j, T t, T tau
 }
 
 template <typename T>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_primal(IterView<T> w, const CtlState *st) {
+__global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ T lds[TILE_CAP];
-  int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = find_inst(g.p_primal, g.ninst, b);
+  const int lb = b - g.p_primal[inst];
+  const IterView<T> &w = I[inst].w;
+  const CtlState *st = I[inst].st;
   const int cur = st->cur;
   const T tau = (T)(st->eta / st->omega);
   const double pend = st->pending;
@@ -212,9 +235,13 @@ __device__ inline void dual_finish(const IterView<T> &w, int64_t i, T s, T sigma
 }
 
 template <typename T>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_dual(IterView<T> w, const CtlState *st) {
+__global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ T lds[TILE_CAP];
-  int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = find_inst(g.p_dual, g.ninst, b);
+  const int lb = b - g.p_dual[inst];
+  const IterView<T> &w = I[inst].w;
+  const CtlState *st = I[inst].st;
   const int cur = st->cur;
   const T sigma = (T)(st->eta * st->omega);
   const double pend = st->pending;
@@ -223,7 +250,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(IterView<T> w, const CtlSta
   const T *__restrict__ xn = w.X[cur ^ 1];
   const T *__restrict__ y = w.Y[cur];
   const T *__restrict__ ax = w.AX[cur];
-  const int64_t G = gridDim.x;
+  const int64_t G = w.grid_rows;
   if (lb < w.n_long_rows) {
     int64_t i = w.long_rows[lb];
     int s = w.rp[i], e = w.rp[i + 1];
@@ -271,15 +298,17 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(IterView<T> w, const CtlSta
   }
 }
 
-// Step-size control of one attempt (PDLP adaptive rule):
+// Step-size control of one attempt (PDLP adaptive rule), one workgroup per
+// instance:
 //   ebar = ||dz||_omega^2 / (2 |dy' A dx|),  accept iff eta <= ebar,
 //   eta <- min((1 - (k+1)^-0.3) ebar, (1 + (k+1)^-0.6) eta),  k = attempts so far.
-__global__ __launch_bounds__(CTL_BLOCK) void k_control(const double *part_dx2, int64_t ncols_p,
-                                                        const double *part_dy, int64_t nrows_p,
-                                                        int adaptive, CtlState *st) {
+template <typename T>
+__global__ __launch_bounds__(CTL_BLOCK) void k_control(const Inst<T> *__restrict__ I) {
   __shared__ double r[3];
-  reduce_partials<1>(part_dx2, ncols_p, 0, 0u, &r[0]);
-  reduce_partials<2>(part_dy, nrows_p, nrows_p, 0u, &r[1]);
+  const IterView<T> &w = I[blockIdx.x].w;
+  CtlState *st = I[blockIdx.x].st;
+  reduce_partials<1>(w.part_dx2, w.grid_cols, 0, 0u, &r[0]);
+  reduce_partials<2>(w.part_dy, w.grid_rows, w.grid_rows, 0u, &r[1]);
   if (threadIdx.x != 0) return;
   double dx2 = r[0], dy2 = r[1], inter = r[2];
   double eta = st->eta, omega = st->omega;
@@ -288,7 +317,7 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_control(const double *part_dx2, i
   st->pending = 0.0;
   int accept = 1;
   double eta_new = eta;
-  if (adaptive) {
+  if (w.adaptive) {
     double nz = omega * dx2 + dy2 / omega;
     double ebar = (inter != 0.0) ? nz / (2.0 * fabs(inter)) : INFINITY;
     double kk = (double)(k + 1);
@@ -317,10 +346,21 @@ __device__ inline bool have_avg(const CtlState *st, int use_average) {
   return use_average && st->wsum > 0.0;
 }
 
+// instance, its local block and its views for a launch over 256-row blocks
+#define GROUP_BLOCK(pre)                                    \
+  const int b = xcd_remap(blockIdx.x, gridDim.x);           \
+  const int inst = find_inst(g.pre, g.ninst, b);            \
+  const int lb = b - g.pre[inst];                           \
+  const EvalView<T> &e = I[inst].e;                         \
+  const CtlState *st = I[inst].st;                          \
+  (void)st;                                                 \
+  (void)lb;
+
 template <typename T>
-__global__ void k_avg_cols(EvalView<T> e, const CtlState *st) {
+__global__ __launch_bounds__(PDHG_BLOCK) void k_avg_cols(const Inst<T> *__restrict__ I, Groups g) {
+  GROUP_BLOCK(p_cols)
   if (!have_avg(st, e.use_average)) return;
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (j >= e.n) return;
   double pend = st->pending;
   T xs = e.XS[j];
@@ -332,9 +372,10 @@ __global__ void k_avg_cols(EvalView<T> e, const CtlState *st) {
 }
 
 template <typename T>
-__global__ void k_avg_rows(EvalView<T> e, const CtlState *st) {
+__global__ __launch_bounds__(PDHG_BLOCK) void k_avg_rows(const Inst<T> *__restrict__ I, Groups g) {
+  GROUP_BLOCK(p_rows)
   if (!have_avg(st, e.use_average)) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (i >= e.m) return;
   double pend = st->pending;
   T ys = e.YS[i];
@@ -345,54 +386,91 @@ __global__ void k_avg_rows(EvalView<T> e, const CtlState *st) {
   e.YA[i] = (double)ys / st->wsum;
 }
 
-// out = M x for a CSR M (FP64 values).  x is x0/x1 picked by the current
-// buffer index (sel_cur) or x0; gate_avg skips the product when there is no
-// average.  Rows longer than PDHG_LONG_SEG are left to k_spmv_long.
-template <typename TX>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_spmv_sel(const int32_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ ci,
-                                                         const double *__restrict__ v,
-                                                         int64_t rows, const TX *x0,
-                                                         const TX *x1, const CtlState *st,
-                                                         int sel_cur, int gate_avg,
-                                                         double *__restrict__ out) {
-  if (gate_avg && !have_avg(st, gate_avg)) return;
-  int lb = xcd_remap(blockIdx.x, gridDim.x);
-  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
-  if (i >= rows) return;
-  const TX *__restrict__ x = (sel_cur && st->cur) ? x1 : x0;
-  int s = rp[i], e = rp[i + 1];
-  if (e - s > PDHG_LONG_SEG) return;
-  double acc = 0.0;
-  for (int k = s; k < e; k++) acc += v[k] * (double)x[ci[k]];
-  out[i] = acc;
+// FP64 products of the evaluation (and of the start point):
+//   SP_ATY   ATY  = A' y_cur   (columns)
+//   SP_AXA   AXA  = A x_avg    (rows, skipped without an average)
+//   SP_ATYA  ATYA = A' y_avg   (columns, skipped without an average)
+//   SP_AX0   AXA  = A x_0      (rows; start point in buffer 0 of the iterate type)
+enum { SP_ATY = 0, SP_AXA = 1, SP_ATYA = 2, SP_AX0 = 3 };
+
+template <typename T>
+struct SpmvSel {
+  const int32_t *ptr, *idx;
+  const double *v;
+  int64_t rows;
+  const T *xt;       // iterate-typed input or null
+  const double *xd;  // FP64 input or null
+  double *out;
+  bool skip;
+};
+
+template <typename T>
+__device__ inline SpmvSel<T> spmv_sel(const EvalView<T> &e, const CtlState *st, int mode) {
+  SpmvSel<T> s;
+  bool rowsA = (mode == SP_AXA || mode == SP_AX0);
+  s.ptr = rowsA ? e.rp : e.cp;
+  s.idx = rowsA ? e.ci : e.ri;
+  s.v = rowsA ? e.v : e.vt;
+  s.rows = rowsA ? e.m : e.n;
+  s.xt = mode == SP_ATY ? e.Y[st->cur] : (mode == SP_AX0 ? e.X[0] : nullptr);
+  s.xd = mode == SP_AXA ? e.XA : (mode == SP_ATYA ? e.YA : nullptr);
+  s.out = mode == SP_ATY ? e.ATY : (mode == SP_ATYA ? e.ATYA : e.AXA);
+  s.skip = (mode == SP_AXA || mode == SP_ATYA) && !have_avg(st, e.use_average);
+  return s;
 }
 
-template <typename TX>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_spmv_sel_long(const int32_t *__restrict__ rp,
-                                                              const int32_t *__restrict__ ci,
-                                                              const double *__restrict__ v,
-                                                              const int32_t *long_rows,
-                                                              const TX *x0, const TX *x1,
-                                                              const CtlState *st, int sel_cur,
-                                                              int gate_avg, double *out) {
-  if (gate_avg && !have_avg(st, gate_avg)) return;
-  int64_t i = long_rows[blockIdx.x];
-  const TX *__restrict__ x = (sel_cur && st->cur) ? x1 : x0;
-  int s = rp[i], e = rp[i + 1];
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_spmv(const Inst<T> *__restrict__ I, Groups g,
+                                                          int mode) {
+  const bool rowsA = (mode == SP_AXA || mode == SP_AX0);
+  const int32_t *pre = rowsA ? g.p_rows : g.p_cols;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = find_inst(pre, g.ninst, b);
+  const int lb = b - pre[inst];
+  SpmvSel<T> s = spmv_sel(I[inst].e, I[inst].st, mode);
+  if (s.skip) return;
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  if (i >= s.rows) return;
+  int a = s.ptr[i], z = s.ptr[i + 1];
+  if (z - a > PDHG_LONG_SEG) return;
+  double acc = 0.0;
+  if (s.xt)
+    for (int k = a; k < z; k++) acc += s.v[k] * (double)s.xt[s.idx[k]];
+  else
+    for (int k = a; k < z; k++) acc += s.v[k] * s.xd[s.idx[k]];
+  s.out[i] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_spmv_long(const Inst<T> *__restrict__ I,
+                                                               Groups g, int mode) {
+  const bool rowsA = (mode == SP_AXA || mode == SP_AX0);
+  const int32_t *pre = rowsA ? g.p_lrows : g.p_lcols;
+  const int b = blockIdx.x;
+  const int inst = find_inst(pre, g.ninst, b);
+  const int lb = b - pre[inst];
+  const IterView<T> &w = I[inst].w;
+  SpmvSel<T> s = spmv_sel(I[inst].e, I[inst].st, mode);
+  if (s.skip) return;
+  int64_t i = rowsA ? w.long_rows[lb] : w.long_cols[lb];
+  int a = s.ptr[i], z = s.ptr[i + 1];
   double acc[1] = {0.0};
-  for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += v[k] * (double)x[ci[k]];
+  if (s.xt)
+    for (int k = a + threadIdx.x; k < z; k += PDHG_BLOCK) acc[0] += s.v[k] * (double)s.xt[s.idx[k]];
+  else
+    for (int k = a + threadIdx.x; k < z; k += PDHG_BLOCK) acc[0] += s.v[k] * s.xd[s.idx[k]];
   double tot[1];
   block_reduce<1>(acc, 0u, tot);
-  if (threadIdx.x == 0) out[i] = tot[0];
+  if (threadIdx.x == 0) s.out[i] = tot[0];
 }
 
 // Row-space KKT pieces for the current point and the average:
 // [0] ||r_p||^2 scaled [1] ||r_p||^2 unscaled [2] ||r_p||_inf unscaled
 // [3] b'y [4] ||y - y_last||^2, then the same five for the average.
 template <typename T>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(EvalView<T> e, const CtlState *st) {
-  int64_t i = (int64_t)blockIdx.x * PDHG_BLOCK + threadIdx.x;
+__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(const Inst<T> *__restrict__ I, Groups g) {
+  GROUP_BLOCK(p_rows)
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   bool avg = have_avg(st, e.use_average);
   double q[EV_ROWQ];
 #pragma unroll
@@ -417,7 +495,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(EvalView<T> e, const C
   double out[EV_ROWQ];
   block_reduce<EV_ROWQ>(q, (1u << 2) | (1u << 7), out);
   if (threadIdx.x == 0)
-    for (int t = 0; t < EV_ROWQ; t++) e.part_rows[(int64_t)t * e.nblk_rows + blockIdx.x] = out[t];
+    for (int t = 0; t < EV_ROWQ; t++) e.part_rows[(int64_t)t * e.nblk_rows + lb] = out[t];
 }
 
 __device__ inline double proj_lambda(uint8_t vk, double lam) {
@@ -438,8 +516,9 @@ __device__ inline double bound_term(uint8_t vk, double lam, double l, double u) 
 // [2] ||r_d||_inf unscaled [3] bound part of the dual objective [4] c'x
 // [5] ||x - x_last||^2, then the same six for the average.
 template <typename T>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(EvalView<T> e, const CtlState *st) {
-  int64_t j = (int64_t)blockIdx.x * PDHG_BLOCK + threadIdx.x;
+__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(const Inst<T> *__restrict__ I, Groups g) {
+  GROUP_BLOCK(p_cols)
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   bool avg = have_avg(st, e.use_average);
   double q[EV_COLQ];
 #pragma unroll
@@ -466,7 +545,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(EvalView<T> e, const C
   double out[EV_COLQ];
   block_reduce<EV_COLQ>(q, (1u << 2) | (1u << 8), out);
   if (threadIdx.x == 0)
-    for (int t = 0; t < EV_COLQ; t++) e.part_cols[(int64_t)t * e.nblk_cols + blockIdx.x] = out[t];
+    for (int t = 0; t < EV_COLQ; t++) e.part_cols[(int64_t)t * e.nblk_cols + lb] = out[t];
 }
 
 struct PointKKT {
@@ -498,17 +577,17 @@ __device__ inline PointKKT point_kkt(const double *rq, const double *cq, double 
 // the scaled KKT_omega (restart at the better of current and average when it
 // fell to 0.2 of the last restart's, or to 0.8 with no progress since the
 // previous evaluation, or after 0.36 of all attempts), primal-weight update.
-__global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const double *part_rows,
-                                                             int64_t nbr, const double *part_cols,
-                                                             int64_t nbc, int use_average,
-                                                             int restart, double pw_theta,
-                                                             double tol, long long max_iter,
-                                                             CtlState *st) {
+// One workgroup per instance.
+template <typename T>
+__global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const Inst<T> *__restrict__ I,
+                                                            double tol, long long max_iter) {
   __shared__ double rq[EV_ROWQ], cq[EV_COLQ];
-  reduce_partials<EV_ROWQ>(part_rows, nbr, nbr, (1u << 2) | (1u << 7), rq);
-  reduce_partials<EV_COLQ>(part_cols, nbc, nbc, (1u << 2) | (1u << 8), cq);
+  const EvalView<T> &e = I[blockIdx.x].e;
+  CtlState *st = I[blockIdx.x].st;
+  reduce_partials<EV_ROWQ>(e.part_rows, e.nblk_rows, e.nblk_rows, (1u << 2) | (1u << 7), rq);
+  reduce_partials<EV_COLQ>(e.part_cols, e.nblk_cols, e.nblk_cols, (1u << 2) | (1u << 8), cq);
   if (threadIdx.x != 0) return;
-  bool avg = use_average && st->wsum > 0.0;
+  bool avg = e.use_average && st->wsum > 0.0;
   double omega = st->omega;
   PointKKT pc = point_kkt(rq, cq, omega, st->nb, st->nc);
   PointKKT pa = pc;
@@ -538,7 +617,7 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const double *part_r
   } else if (k >= max_iter) {
     st->done = 1;
     st->status = 2;
-  } else if (restart && k > 0) {
+  } else if (e.restart && k > 0) {
     bool cand_avg = avg && pa.komega < pc.komega;
     const PointKKT *cd = cand_avg ? &pa : &pc;
     double kc = cd->komega;
@@ -549,8 +628,9 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const double *part_r
     if (do_restart) {
       st->restart_flag = cand_avg ? 2 : 1;
       double dx = cd->dl_x, dy = cd->dl_y;
-      if (pw_theta > 0.0 && dx > 1e-10 && dy > 1e-10)
-        omega = exp(pw_theta * log(dy / dx) + (1.0 - pw_theta) * log(omega));
+      double th = e.pw_theta;
+      if (th > 0.0 && dx > 1e-10 && dy > 1e-10)
+        omega = exp(th * log(dy / dx) + (1.0 - th) * log(omega));
       st->omega = omega;
       st->kkt_last = sqrt(omega * cd->sp2 + cd->sd2 / omega + cd->gap * cd->gap);
       st->kkt_prev = INFINITY;
@@ -571,10 +651,12 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const double *part_r
 }
 
 template <typename T>
-__global__ void k_restart_cols(EvalView<T> e, const CtlState *st) {
+__global__ __launch_bounds__(PDHG_BLOCK) void k_restart_cols(const Inst<T> *__restrict__ I,
+                                                             Groups g) {
+  GROUP_BLOCK(p_cols)
   int f = st->restart_flag;
   if (f == 0) return;
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (j >= e.n) return;
   T *x = e.X[st->cur];
   if (f == 2) x[j] = (T)e.XA[j];
@@ -582,10 +664,12 @@ __global__ void k_restart_cols(EvalView<T> e, const CtlState *st) {
 }
 
 template <typename T>
-__global__ void k_restart_rows(EvalView<T> e, const CtlState *st) {
+__global__ __launch_bounds__(PDHG_BLOCK) void k_restart_rows(const Inst<T> *__restrict__ I,
+                                                             Groups g) {
+  GROUP_BLOCK(p_rows)
   int f = st->restart_flag;
   if (f == 0) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (i >= e.m) return;
   T *y = e.Y[st->cur];
   if (f == 2) {
@@ -597,9 +681,11 @@ __global__ void k_restart_rows(EvalView<T> e, const CtlState *st) {
 
 // Start point: x = proj_[l,u](x0 / Dc) (0 if no x0), y = proj_Y(y0 / Dr).
 template <typename T>
-__global__ void k_init_cols(EvalView<T> e, const double *x0) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(PDHG_BLOCK) void k_init_cols(const Inst<T> *__restrict__ I, Groups g) {
+  GROUP_BLOCK(p_cols)
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (j >= e.n) return;
+  const double *x0 = I[inst].x0;
   double xv = x0 ? x0[j] / e.Dc[j] : 0.0;
   xv = clamp_box<double>(xv, e.l[j], e.u[j]);
   e.X[0][j] = (T)xv;
@@ -607,9 +693,11 @@ __global__ void k_init_cols(EvalView<T> e, const double *x0) {
 }
 
 template <typename T>
-__global__ void k_init_rows(EvalView<T> e, const double *y0) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(PDHG_BLOCK) void k_init_rows(const Inst<T> *__restrict__ I, Groups g) {
+  GROUP_BLOCK(p_rows)
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (i >= e.m) return;
+  const double *y0 = I[inst].y0;
   double yv = y0 ? y0[i] / e.Dr[i] : 0.0;
   if (e.kind[i] == 1 && yv < 0.0) yv = 0.0;
   e.Y[0][i] = (T)yv;
@@ -617,12 +705,15 @@ __global__ void k_init_rows(EvalView<T> e, const double *y0) {
 }
 
 template <typename T>
-__global__ void k_ax_to_iter(EvalView<T> e, const double *ax) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < e.m) e.AX[0][i] = (T)ax[i];
+__global__ __launch_bounds__(PDHG_BLOCK) void k_ax_to_iter(const Inst<T> *__restrict__ I, Groups g) {
+  GROUP_BLOCK(p_rows)
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  if (i < e.m) e.AX[0][i] = (T)e.AXA[i];
 }
 
-__global__ void k_init_state(CtlState *st) {
+template <typename T>
+__global__ void k_init_state(const Inst<T> *__restrict__ I) {
+  CtlState *st = I[blockIdx.x].st;
   st->cur = 0;
   st->fresh = 1;
   st->pending = 0.0;
@@ -647,23 +738,32 @@ __global__ void k_init_state(CtlState *st) {
 // current iterate becomes the FP64 start point; attempts, accepted steps,
 // restarts, the step size and the primal weight carry over, the average and
 // the restart reference start afresh.
-__global__ void k_switch_cols(EvalView<float> ef, EvalView<double> ed, const CtlState *st) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ed.n) return;
-  double xv = (double)ef.X[st->cur][j];
-  ed.X[0][j] = xv;
-  ed.XL[j] = xv;
+__global__ __launch_bounds__(PDHG_BLOCK) void k_switch_cols(const Inst<float> *__restrict__ If,
+                                                            const Inst<double> *__restrict__ I,
+                                                            Groups g) {
+  typedef double T;
+  GROUP_BLOCK(p_cols)
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  if (j >= e.n) return;
+  double xv = (double)If[inst].e.X[st->cur][j];
+  e.X[0][j] = xv;
+  e.XL[j] = xv;
 }
 
-__global__ void k_switch_rows(EvalView<float> ef, EvalView<double> ed, const CtlState *st) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ed.m) return;
-  double yv = (double)ef.Y[st->cur][i];
-  ed.Y[0][i] = yv;
-  ed.YL[i] = yv;
+__global__ __launch_bounds__(PDHG_BLOCK) void k_switch_rows(const Inst<float> *__restrict__ If,
+                                                            const Inst<double> *__restrict__ I,
+                                                            Groups g) {
+  typedef double T;
+  GROUP_BLOCK(p_rows)
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  if (i >= e.m) return;
+  double yv = (double)If[inst].e.Y[st->cur][i];
+  e.Y[0][i] = yv;
+  e.YL[i] = yv;
 }
 
-__global__ void k_switch_state(CtlState *st) {
+__global__ void k_switch_state(const Inst<double> *__restrict__ I) {
+  CtlState *st = I[blockIdx.x].st;
   st->cur = 0;
   st->fresh = 1;
   st->pending = 0.0;
@@ -678,19 +778,23 @@ __global__ void k_switch_state(CtlState *st) {
 }
 
 template <typename T>
-__global__ void k_unscale_cols(EvalView<T> e, const CtlState *st, double *x) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(PDHG_BLOCK) void k_unscale_cols(const Inst<T> *__restrict__ I,
+                                                             Groups g) {
+  GROUP_BLOCK(p_cols)
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (j >= e.n) return;
   double xv = st->which ? e.XA[j] : (double)e.X[st->cur][j];
-  x[j] = e.Dc[j] * xv;
+  I[inst].xout[j] = e.Dc[j] * xv;
 }
 
 template <typename T>
-__global__ void k_unscale_rows(EvalView<T> e, const CtlState *st, double *y) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(PDHG_BLOCK) void k_unscale_rows(const Inst<T> *__restrict__ I,
+                                                             Groups g) {
+  GROUP_BLOCK(p_rows)
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (i >= e.m) return;
   double yv = st->which ? e.YA[i] : (double)e.Y[st->cur][i];
-  y[i] = e.Dr[i] * yv;
+  I[inst].yout[i] = e.Dr[i] * yv;
 }
 
 // ---------------------------------------------------------------------------
@@ -721,8 +825,8 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_norm_partials(const double *v, i
 }
 
 __global__ __launch_bounds__(CTL_BLOCK) void k_init_ctl(const double *part, int nparts,
-                                                         int step_mode, double fixed_eta,
-                                                         double fixed_omega, CtlState *st) {
+                                                        double fixed_eta, double fixed_omega,
+                                                        CtlState *st) {
   __shared__ double r[5];
   reduce_partials<5>(part, nparts, nparts, 1u, r);
   if (threadIdx.x != 0) return;
@@ -734,7 +838,12 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_init_ctl(const double *part, int 
     st->omega0 = fixed_omega;
   else
     st->omega0 = (ncs > 1e-10 && nbs > 1e-10) ? ncs / nbs : 1.0;
-  (void)step_mode;
+}
+
+template <typename T>
+__global__ void k_gather_states(const Inst<T> *__restrict__ I, int n, CtlState *out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = *I[i].st;
 }
 
 __global__ void k_spmv_plain(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -753,108 +862,72 @@ __global__ void k_spmv_plain(const int32_t *__restrict__ rp, const int32_t *__re
 // launchers
 
 template <typename T>
-void launch_primal(const IterView<T> &w, CtlState *st, hipStream_t s) {
-  k_primal<T><<<w.grid_cols, PDHG_BLOCK, 0, s>>>(w, st);
+void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s) {
+  k_primal<T><<<grid_of(g.n_primal), PDHG_BLOCK, 0, s>>>(I, g);
 }
 
 template <typename T>
-void launch_dual(const IterView<T> &w, CtlState *st, hipStream_t s) {
-  k_dual<T><<<w.grid_rows, PDHG_BLOCK, 0, s>>>(w, st);
+void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s) {
+  k_dual<T><<<grid_of(g.n_dual), PDHG_BLOCK, 0, s>>>(I, g);
 }
 
 template <typename T>
-void launch_control(const IterView<T> &w, CtlState *st, hipStream_t s) {
-  k_control<<<1, CTL_BLOCK, 0, s>>>(w.part_dx2, w.grid_cols, w.part_dy, w.grid_rows, w.adaptive,
-                                     st);
+void launch_control(const Inst<T> *I, const Groups &g, hipStream_t s) {
+  k_control<T><<<grid_of(g.ninst), CTL_BLOCK, 0, s>>>(I);
 }
 
 template <typename T>
-void launch_attempt(const IterView<T> &w, CtlState *st, int64_t, hipStream_t s) {
-  launch_primal<T>(w, st, s);
-  launch_dual<T>(w, st, s);
-  launch_control<T>(w, st, s);
-}
-
-// The evaluation needs the long-row lists too; they are passed through the
-// IterView that shares the matrix pointers.
-struct LongLists {
-  const int32_t *rows, *cols;
-  int nrows, ncols;
-};
-
-template <typename T>
-void launch_evaluate_impl(const EvalView<T> &e, const LongLists &ll, CtlState *st, double tol,
-                          int64_t max_iter, hipStream_t s) {
-  k_avg_cols<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e, st);
-  k_avg_rows<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, st);
-  // A'y of the current point, A x_avg, A'y_avg
-  k_spmv_sel<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e.cp, e.ri, e.vt, e.n, e.Y[0], e.Y[1], st,
-                                                      1, 0, e.ATY);
-  if (ll.ncols)
-    k_spmv_sel_long<T><<<ll.ncols, PDHG_BLOCK, 0, s>>>(e.cp, e.ri, e.vt, ll.cols, e.Y[0], e.Y[1],
-                                                        st, 1, 0, e.ATY);
-  k_spmv_sel<double><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e.rp, e.ci, e.v, e.m, e.XA, e.XA, st,
-                                                           0, e.use_average, e.AXA);
-  if (ll.nrows)
-    k_spmv_sel_long<double><<<ll.nrows, PDHG_BLOCK, 0, s>>>(e.rp, e.ci, e.v, ll.rows, e.XA, e.XA,
-                                                             st, 0, e.use_average, e.AXA);
-  k_spmv_sel<double><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e.cp, e.ri, e.vt, e.n, e.YA, e.YA, st,
-                                                           0, e.use_average, e.ATYA);
-  if (ll.ncols)
-    k_spmv_sel_long<double><<<ll.ncols, PDHG_BLOCK, 0, s>>>(e.cp, e.ri, e.vt, ll.cols, e.YA,
-                                                             e.YA, st, 0, e.use_average, e.ATYA);
-  k_eval_rows<T><<<e.nblk_rows, PDHG_BLOCK, 0, s>>>(e, st);
-  k_eval_cols<T><<<e.nblk_cols, PDHG_BLOCK, 0, s>>>(e, st);
-  k_eval_control<<<1, CTL_BLOCK, 0, s>>>(e.part_rows, e.nblk_rows, e.part_cols, e.nblk_cols,
-                                          e.use_average, e.restart, e.pw_theta, tol,
-                                          (long long)max_iter, st);
-  k_restart_cols<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e, st);
-  k_restart_rows<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, st);
+void launch_attempt(const Inst<T> *I, const Groups &g, hipStream_t s) {
+  launch_primal<T>(I, g, s);
+  launch_dual<T>(I, g, s);
+  launch_control<T>(I, g, s);
 }
 
 template <typename T>
-void launch_evaluate_ll(const EvalView<T> &e, const int32_t *long_rows, int n_long_rows,
-                        const int32_t *long_cols, int n_long_cols, CtlState *st, double tol,
-                        int64_t max_iter, hipStream_t s) {
-  LongLists ll{long_rows, long_cols, n_long_rows, n_long_cols};
-  launch_evaluate_impl<T>(e, ll, st, tol, max_iter, s);
+static void launch_products(const Inst<T> *I, const Groups &g, int mode, hipStream_t s) {
+  bool rowsA = (mode == SP_AXA || mode == SP_AX0);
+  k_eval_spmv<T><<<grid_of(rowsA ? g.n_rows : g.n_cols), PDHG_BLOCK, 0, s>>>(I, g, mode);
+  int nl = rowsA ? g.n_lrows : g.n_lcols;
+  if (nl) k_eval_spmv_long<T><<<grid_of(nl), PDHG_BLOCK, 0, s>>>(I, g, mode);
 }
 
 template <typename T>
-void launch_init_point(const EvalView<T> &e, const int32_t *long_rows, int n_long_rows,
-                       const double *x0, const double *y0, CtlState *st, double *ax_tmp,
-                       hipStream_t s) {
-  k_init_state<<<1, 1, 0, s>>>(st);
-  k_init_cols<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e, x0);
-  k_init_rows<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, y0);
-  // A x of the start point (FP64 matrix, then cast to the iterate type)
-  k_spmv_sel<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e.rp, e.ci, e.v, e.m, e.X[0], e.X[0], st, 0,
-                                                      0, ax_tmp);
-  if (n_long_rows)
-    k_spmv_sel_long<T><<<n_long_rows, PDHG_BLOCK, 0, s>>>(e.rp, e.ci, e.v, long_rows, e.X[0],
-                                                           e.X[0], st, 0, 0, ax_tmp);
-  k_ax_to_iter<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, ax_tmp);
+void launch_evaluate(const Inst<T> *I, const Groups &g, double tol, int64_t max_iter,
+                     hipStream_t s) {
+  k_avg_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
+  k_avg_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
+  launch_products<T>(I, g, SP_ATY, s);
+  launch_products<T>(I, g, SP_AXA, s);
+  launch_products<T>(I, g, SP_ATYA, s);
+  k_eval_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
+  k_eval_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
+  k_eval_control<T><<<grid_of(g.ninst), CTL_BLOCK, 0, s>>>(I, tol, (long long)max_iter);
+  k_restart_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
+  k_restart_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
 }
 
-void launch_switch_to_fp64(const EvalView<float> &ef, const EvalView<double> &ed,
-                           const int32_t *long_rows, int n_long_rows, CtlState *st,
+template <typename T>
+void launch_init_point(const Inst<T> *I, const Groups &g, hipStream_t s) {
+  k_init_state<T><<<grid_of(g.ninst), 1, 0, s>>>(I);
+  k_init_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
+  k_init_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
+  launch_products<T>(I, g, SP_AX0, s);
+  k_ax_to_iter<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
+}
+
+void launch_switch_to_fp64(const Inst<float> *If, const Inst<double> *Id, const Groups &g,
                            hipStream_t s) {
-  k_switch_cols<<<grid_for(ed.n), PDHG_BLOCK, 0, s>>>(ef, ed, st);
-  k_switch_rows<<<grid_for(ed.m), PDHG_BLOCK, 0, s>>>(ef, ed, st);
-  k_switch_state<<<1, 1, 0, s>>>(st);
-  k_spmv_sel<double><<<grid_for(ed.m), PDHG_BLOCK, 0, s>>>(ed.rp, ed.ci, ed.v, ed.m, ed.X[0],
-                                                            ed.X[0], st, 0, 0, ed.AX[0]);
-  if (n_long_rows)
-    k_spmv_sel_long<double><<<n_long_rows, PDHG_BLOCK, 0, s>>>(ed.rp, ed.ci, ed.v, long_rows,
-                                                                ed.X[0], ed.X[0], st, 0, 0,
-                                                                ed.AX[0]);
+  k_switch_cols<<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(If, Id, g);
+  k_switch_rows<<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(If, Id, g);
+  k_switch_state<<<grid_of(g.ninst), 1, 0, s>>>(Id);
+  launch_products<double>(Id, g, SP_AX0, s);
+  k_ax_to_iter<double><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(Id, g);
 }
 
 template <typename T>
-void launch_unscale(const EvalView<T> &e, const CtlState *st, double *x, double *y,
-                    hipStream_t s) {
-  k_unscale_cols<T><<<grid_for(e.n), PDHG_BLOCK, 0, s>>>(e, st, x);
-  k_unscale_rows<T><<<grid_for(e.m), PDHG_BLOCK, 0, s>>>(e, st, y);
+void launch_unscale(const Inst<T> *I, const Groups &g, hipStream_t s) {
+  k_unscale_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
+  k_unscale_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
 }
 
 void launch_init_ctl(const double *v, int64_t nnz, const double *b, const double *c,
@@ -863,8 +936,14 @@ void launch_init_ctl(const double *v, int64_t nnz, const double *b, const double
                      double fixed_omega, hipStream_t s) {
   int np = nscratch / 5;
   if (np > 1024) np = 1024;
+  (void)step_mode;
   k_norm_partials<<<np, PDHG_BLOCK, 0, s>>>(v, nnz, b, c, b0, c0, m, n, scratch, np);
-  k_init_ctl<<<1, CTL_BLOCK, 0, s>>>(scratch, np, step_mode, fixed_eta, fixed_omega, st);
+  k_init_ctl<<<1, CTL_BLOCK, 0, s>>>(scratch, np, fixed_eta, fixed_omega, st);
+}
+
+template <typename T>
+void launch_gather_states(const Inst<T> *I, int n, CtlState *out, hipStream_t s) {
+  k_gather_states<T><<<(n + 63) / 64, 64, 0, s>>>(I, n, out);
 }
 
 void launch_spmv(const int32_t *rp, const int32_t *ci, const double *v, int64_t rows,
@@ -872,18 +951,15 @@ void launch_spmv(const int32_t *rp, const int32_t *ci, const double *v, int64_t 
   k_spmv_plain<<<grid_for(rows), PDHG_BLOCK, 0, s>>>(rp, ci, v, rows, x, y);
 }
 
-#define INST(T)                                                                               \
-  template void launch_attempt<T>(const IterView<T> &, CtlState *, int64_t, hipStream_t);    \
-  template void launch_primal<T>(const IterView<T> &, CtlState *, hipStream_t);              \
-  template void launch_dual<T>(const IterView<T> &, CtlState *, hipStream_t);                \
-  template void launch_control<T>(const IterView<T> &, CtlState *, hipStream_t);             \
-  template void launch_evaluate_ll<T>(const EvalView<T> &, const int32_t *, int,              \
-                                      const int32_t *, int, CtlState *, double, int64_t,      \
-                                      hipStream_t);                                           \
-  template void launch_init_point<T>(const EvalView<T> &, const int32_t *, int,              \
-                                     const double *, const double *, CtlState *, double *,    \
-                                     hipStream_t);                                            \
-  template void launch_unscale<T>(const EvalView<T> &, const CtlState *, double *, double *, \
-                                  hipStream_t);
+#define INST(T)                                                                            \
+  template void launch_primal<T>(const Inst<T> *, const Groups &, hipStream_t);            \
+  template void launch_dual<T>(const Inst<T> *, const Groups &, hipStream_t);              \
+  template void launch_control<T>(const Inst<T> *, const Groups &, hipStream_t);           \
+  template void launch_attempt<T>(const Inst<T> *, const Groups &, hipStream_t);           \
+  template void launch_evaluate<T>(const Inst<T> *, const Groups &, double, int64_t,       \
+                                   hipStream_t);                                           \
+  template void launch_init_point<T>(const Inst<T> *, const Groups &, hipStream_t);        \
+  template void launch_unscale<T>(const Inst<T> *, const Groups &, hipStream_t);            \
+  template void launch_gather_states<T>(const Inst<T> *, int, CtlState *, hipStream_t);
 INST(double)
 INST(float)

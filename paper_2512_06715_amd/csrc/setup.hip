@@ -296,10 +296,23 @@ __global__ void k_scale_cols_vec(const double *__restrict__ c0, const double *__
   u[j] = u0[j] / d;
 }
 
+__global__ void k_fix_bounds(double *l, double *u, const int32_t *__restrict__ idx,
+                             const double *__restrict__ val, int64_t nfix) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nfix) return;
+  l[idx[k]] = val[k];
+  u[idx[k]] = val[k];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers
+
+void launch_fix_bounds(double *l, double *u, const int32_t *idx, const double *val, int64_t nfix,
+                       hipStream_t s) {
+  if (nfix > 0) k_fix_bounds<<<grid_for(nfix), PDHG_BLOCK, 0, s>>>(l, u, idx, val, nfix);
+}
 
 void launch_validate(const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *kind,
                      const double *b, const double *c, const double *l, const double *u,

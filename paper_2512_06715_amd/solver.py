@@ -142,3 +142,58 @@ def solve(lp, x0=None, y0=None, **opts):
         return p.solve(x0, y0)
     finally:
         p.close()
+
+
+def solve_batch(problems, instances, stream=None):
+    """Solve many instances in one batched run.
+
+    problems: list of Problem (the bases; same precision).
+    instances: list of dicts with key 'base' (index into problems) and optional
+    'b', 'c', 'l', 'u' (original-space overrides) and 'fix_idx', 'fix_val'
+    (variables fixed to a value).  Host problems take numpy arrays, device
+    problems torch CUDA tensors.  Returns a list of (x, y, info dict).
+    """
+    import torch
+    lib = L.load()
+    H = (ctypes.c_void_p * len(problems))(*[p.handle for p in problems])
+    keep = []
+    arr = (L.PdhgInstance * len(instances))()
+    outs = []
+    for k, d in enumerate(instances):
+        bi = int(d["base"])
+        # an out-of-range base is passed through so the library rejects it
+        base = problems[bi] if 0 <= bi < len(problems) else problems[0]
+
+        def conv(a, dt):
+            if a is None:
+                return None
+            if base.device:
+                return a
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a
+        fi = conv(d.get("fix_idx"), np.int32)
+        fv = conv(d.get("fix_val"), np.float64)
+        nfix = 0 if fi is None else int(fi.numel() if base.device else len(fi))
+        arr[k] = L.PdhgInstance(bi, _ptr(conv(d.get("b"), np.float64)),
+                                _ptr(conv(d.get("c"), np.float64)),
+                                _ptr(conv(d.get("l"), np.float64)),
+                                _ptr(conv(d.get("u"), np.float64)), _ptr(fi), _ptr(fv), nfix)
+        if base.device:
+            x = torch.empty(base.n, dtype=torch.float64, device="cuda")
+            y = torch.empty(base.m, dtype=torch.float64, device="cuda")
+        else:
+            x = np.zeros(base.n)
+            y = np.zeros(base.m)
+        outs.append((x, y))
+    nb = ctypes.c_size_t()
+    L.check(lib.pdhg_batch_workspace_bytes(H, len(problems), arr, len(instances),
+                                           ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    X = (ctypes.c_void_p * len(instances))(*[_ptr(o[0]).value for o in outs])
+    Y = (ctypes.c_void_p * len(instances))(*[_ptr(o[1]).value for o in outs])
+    infos = (L.PdhgInfo * len(instances))()
+    L.check(lib.pdhg_solve_batch(H, len(problems), arr, len(instances),
+                                 ctypes.c_void_p(ws.data_ptr()), int(nb.value), X, Y, infos))
+    del ws
+    return [(outs[k][0], outs[k][1], infos[k].as_dict()) for k in range(len(instances))]

@@ -1,0 +1,60 @@
+"""Batched solves: grouped launches over instances with per-instance state."""
+import numpy as np
+import pytest
+
+from paper_2512_06715_amd import ucgen
+
+pytestmark = pytest.mark.gpu
+
+
+def node_variants(lp, count, seed0):
+    out = []
+    for k in range(count):
+        v = ucgen.fix_commitments(lp, seed=[seed0, k])
+        out.append(v)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_matches_standalone(gpu, oracle_mod, precision):
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    base_a = ucgen.random_uc(14, 5, 20, 6, 1.0, seed=21)
+    base_b = ucgen.random_uc(10, 4, 14, 4, 1.0, seed=24)
+    nodes = node_variants(base_a, 5, 3)
+    print("case batch", precision, flush=True)
+    opts = dict(tol=1e-6, max_iter=300000, precision=precision)
+    pa, pb = Problem(base_a, **opts), Problem(base_b, **opts)
+    insts = [dict(base=0)] + [dict(base=0, fix_idx=v.meta["fix_idx"], fix_val=v.meta["fix_val"])
+                              for v in nodes] + [dict(base=1), dict(base=1, b=base_b.b * 1.05)]
+    res = solve_batch([pa, pb], insts)
+    pa.close()
+    pb.close()
+    lps = [base_a] + nodes + [base_b, base_b.copy()]
+    lps[-1].b = base_b.b * 1.05
+    for k, (x, y, info) in enumerate(res):
+        lp = lps[k]
+        assert info["status"] == 1, (k, info)
+        kk = oracle_mod.kkt(lp, x, y)
+        assert kk["rel_kkt"] <= 1.001e-6, (k, kk)
+        # the same instance as a standalone problem: identical partition and
+        # reduction order, so the FP64 path reproduces it bit for bit
+        p = Problem(lp, **opts)
+        xs, ys, info_s = p.solve()
+        p.close()
+        assert info_s["attempts"] == info["attempts"], k
+        if precision == "fp64":
+            assert np.array_equal(xs, x) and np.array_equal(ys, y), k
+        else:
+            np.testing.assert_allclose(x, xs, rtol=0, atol=1e-9 * (1 + np.abs(xs).max()))
+
+
+def test_batch_rejects_bad_instances(gpu):
+    from paper_2512_06715_amd import _lib
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    base = ucgen.random_uc(6, 3, 8, 4, 1.0, seed=5)
+    p = Problem(base)
+    with pytest.raises(_lib.PdhgError):
+        solve_batch([p], [dict(base=1)])
+    with pytest.raises(_lib.PdhgError):
+        solve_batch([p], [dict(base=0, fix_idx=np.array([base.n + 5]), fix_val=np.array([1.0]))])
+    p.close()
