@@ -162,10 +162,28 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles,
                      size_t workspace_bytes, double *const *x, double *const *y,
                      pdhg_info *infos);
 
-/* After a pdhg_solve in unrolled mode (opts.unroll_iters > 0), the gradient
- * of V = c'x_K with respect to b and c (original space), scaled by
- * grad_value.  grad_b[m], grad_c[n]: same memory kind as the LP. */
+/* Unrolled mode (opts.unroll_iters = K > 0, FP64): pdhg_solve runs exactly K
+ * fixed-step iterations from x = proj(x0 or 0), y = proj(y0 or 0), with
+ * eta = opts.fixed_eta (or 0.9/||A^||_2 by 50 power iterations), the primal
+ * weight of the usual rule (or opts.fixed_omega), no restarts and no
+ * average, and keeps (x, y, Ax) every opts.checkpoint_every steps.  It returns
+ * x_K, y_K with status PDHG_ITER_LIMIT; info.primal_obj is V = c'x_K.
+ *
+ * pdhg_backward then gives the gradient of V with respect to b and c
+ * (original space), times grad_value, by the exact transpose of the unrolled
+ * map: segments are recomputed from their checkpoints with bit-packed
+ * projection masks, then swept backwards with one A' and one A product per
+ * step.  At a point where a pre-projection value sits exactly on a bound the
+ * mask counts it as projected (the one-sided derivative of the clamp from
+ * inside the active side).  grad_b[m], grad_c[n]: same memory kind as the LP.
+ * Returns PDHG_ERR_STATE without a preceding unrolled solve. */
 int pdhg_backward(pdhg_handle *h, double grad_value, double *grad_b, double *grad_c);
+
+/* Replace b and/or c (original space, nullable, same memory kind as the
+ * LP) of a set-up problem: rescales them with the stored diagonals and resets
+ * the step size and primal weight rules.  Invalidates a previous unrolled
+ * solve for pdhg_backward. */
+int pdhg_update(pdhg_handle *h, const double *b, const double *c);
 
 void pdhg_destroy(pdhg_handle *h);
 

@@ -69,6 +69,7 @@ SIGNATURES = {
                                  c_int, vp, ctypes.c_size_t, ctypes.POINTER(vp),
                                  ctypes.POINTER(vp), ctypes.POINTER(PdhgInfo)]),
     "pdhg_backward": (c_int, [vp, c_dbl, vp, vp]),
+    "pdhg_update": (c_int, [vp, vp, vp]),
     "pdhg_destroy": (None, [vp]),
     "pdhg_last_error": (ctypes.c_char_p, []),
     "pdhg_export_setup": (c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),

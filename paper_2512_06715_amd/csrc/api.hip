@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <stddef.h>
+
 #include <algorithm>
 #include <chrono>
 #include <string>
@@ -134,6 +136,15 @@ struct pdhg_handle {
   int n_long_rows = 0, n_long_cols = 0, nblk_rows = 0, nblk_cols = 0;
   int tpb_rows = 1, tpb_cols = 1, grid_rows = 1, grid_cols = 1;
 
+  // unrolled mode: checkpoints (x, y, Ax) every ur_C steps, masks of one
+  // segment, adjoint vectors, and the forward's step sizes
+  double *ckpt = nullptr, *XB = nullptr, *YB = nullptr, *H = nullptr, *BB = nullptr,
+         *CB = nullptr, *XK = nullptr;
+  uint64_t *mask_x = nullptr, *mask_y = nullptr;
+  int64_t ur_K = 0, ur_C = 0;
+  double ur_eta = 0, ur_omega = 0;
+  bool ur_valid = false;
+
   // the handle's own instance (pdhg_solve) and its cached block graphs
   IterBufs it{};
   GroupDev grp{};
@@ -209,6 +220,22 @@ size_t layout(pdhg_handle *h, void *base) {
   int gc = (int)std::min<int64_t>(n + h->nblk_cols, 0x7fffffff);
   carve_iter(cv, h->it, m, n, gr, gc, mixed);
   carve_group(cv, h->grp, 1);
+  if (h->o.unroll_iters > 0) {
+    int64_t K = h->o.unroll_iters;
+    int64_t C = h->o.checkpoint_every > 0 ? std::min<int64_t>(h->o.checkpoint_every, K) : K;
+    int64_t S = (K + C - 1) / C;
+    h->ur_K = K;
+    h->ur_C = C;
+    h->ckpt = cv.take<double>(S * (n + 2 * m));
+    h->mask_x = cv.take<uint64_t>(C * ((n + 63) / 64));
+    h->mask_y = cv.take<uint64_t>(C * ((m + 63) / 64));
+    h->XB = cv.take<double>(n);
+    h->YB = cv.take<double>(m);
+    h->H = cv.take<double>(n);
+    h->BB = cv.take<double>(m);
+    h->CB = cv.take<double>(n);
+    h->XK = cv.take<double>(n);
+  }
   return cv.off + 256;
 }
 
@@ -223,6 +250,10 @@ int check_opts(const pdhg_opts *o) {
   if (o->unroll_iters < 0) return fail(PDHG_ERR_ARG, "unroll_iters must be >= 0");
   if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return fail(PDHG_ERR_ARG, "pw_theta must be in [0, 1]");
   if (o->tiles_per_block < 0) return fail(PDHG_ERR_ARG, "tiles_per_block must be >= 0");
+  if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
+    return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
+  if (o->unroll_iters > 0 && o->checkpoint_every < 0)
+    return fail(PDHG_ERR_ARG, "checkpoint_every must be >= 0");
   return PDHG_OK;
 }
 
@@ -829,6 +860,187 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
   return PDHG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// ||A^||_2 by power iteration on A'A from the all-ones direction (the same
+// iteration as the reference definition of the unrolled step size).
+int power_norm(pdhg_handle *h, int iters, double *est) {
+  int64_t m = h->m, n = h->n;
+  double *z = h->it.XA, *w = h->it.YA, *q = h->it.ATYA;
+  launch_fill(z, 1.0 / sqrt((double)n), n, h->hs);
+  HK();
+  *est = 0.0;
+  for (int it = 0; it < iters; it++) {
+    launch_spmv(h->rp, h->ci, h->v, m, z, w, h->hs);
+    launch_spmv(h->cp, h->ri, h->vt, n, w, q, h->hs);
+    double *dn = launch_sumsq(q, n, h->scratch, h->nscratch, h->hs);
+    HK();
+    double qn2 = 0.0;
+    HC(hipMemcpyAsync(&qn2, dn, sizeof(double), hipMemcpyDeviceToHost, h->hs));
+    HC(hipStreamSynchronize(h->hs));
+    double qn = sqrt(qn2);
+    *est = sqrt(qn);
+    if (qn == 0.0) break;
+    launch_axpby(z, q, 1.0 / qn, 0.0, n, h->hs);
+    HK();
+  }
+  return PDHG_OK;
+}
+
+template <typename F>
+int write_state_field(pdhg_handle *h, size_t offset, const F &value) {
+  HC(hipMemcpyAsync((char *)h->it.st + offset, &value, sizeof(F), hipMemcpyHostToDevice, h->hs));
+  HC(hipStreamSynchronize(h->hs));
+  return PDHG_OK;
+}
+
+// The instance of the unrolled mode: fixed steps, no restarts, no average.
+Inst<double> unrolled_inst(pdhg_handle *h) {
+  Inst<double> I = make_inst<double>(h, base_data(h), h->it);
+  I.w.adaptive = 0;
+  I.e.restart = 0;
+  I.e.use_average = 0;
+  return I;
+}
+
+int solve_unrolled(pdhg_handle *h, const double *dx0, const double *dy0, double *xo, double *yo,
+                   pdhg_info *info, double t0) {
+  const int64_t K = h->ur_K, C = h->ur_C, m = h->m, n = h->n;
+  double eta = h->o.fixed_eta;
+  if (!(eta > 0.0)) {
+    double nrm = 0.0;
+    RC(power_norm(h, 50, &nrm));
+    eta = nrm > 0.0 ? 0.9 / nrm : 1.0;
+  }
+  RC(write_state_field(h, offsetof(CtlState, eta0), eta));
+  std::vector<Inst<double>> one{unrolled_inst(h)};
+  one[0].x0 = dx0;
+  one[0].y0 = dy0;
+  one[0].xout = xo;
+  one[0].yout = yo;
+  std::vector<int> act{0};
+  Groups g{};
+  RC(upload_group<double>(h, h->grp, one, act, g));
+  const Inst<double> *dI = h->grp.d64;
+  launch_init_point<double>(dI, g, h->hs);
+  HK();
+  const int64_t S = (K + C - 1) / C;
+  hipGraphExec_t exec = nullptr;
+  for (int64_t s = 0; s < S; s++) {
+    double *ck = h->ckpt + s * (n + 2 * m);
+    launch_checkpoint<double>(dI, g, ck, ck + n, ck + n + m, 0, h->hs);
+    int64_t steps = std::min<int64_t>(C, K - s * C);
+    if (steps == C && h->o.use_graph) {
+      if (!exec) {
+        hipGraph_t graph;
+        HC(hipStreamBeginCapture(h->hs, hipStreamCaptureModeThreadLocal));
+        for (int64_t i = 0; i < C; i++) launch_attempt<double>(dI, g, h->hs);
+        HC(hipStreamEndCapture(h->hs, &graph));
+        HK();
+        HC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HC(hipGraphDestroy(graph));
+      }
+      HC(hipGraphLaunch(exec, h->hs));
+    } else {
+      for (int64_t i = 0; i < steps; i++) launch_attempt<double>(dI, g, h->hs);
+      HK();
+    }
+  }
+  if (exec) HC(hipGraphExecDestroy(exec));
+  // x_K for the adjoint's seed; the y and Ax copies land in scratch
+  launch_checkpoint<double>(dI, g, h->XK, h->YB, h->BB, 0, h->hs);
+  launch_evaluate<double>(dI, g, 0.0, K, h->hs);
+  launch_unscale<double>(dI, g, h->hs);
+  HK();
+  RC(read_states(h, h->grp, 1, false));
+  const CtlState &st = h->grp.hstates[0];
+  h->ur_eta = st.eta;
+  h->ur_omega = st.omega;
+  h->ur_valid = true;
+  fill_info(info, st, PDHG_ITER_LIMIT, 0, h->setup_s, now_s() - t0);
+  return PDHG_OK;
+}
+
+int backward_unrolled(pdhg_handle *h, double gv, double *grad_b, double *grad_c) {
+  const int64_t K = h->ur_K, C = h->ur_C, m = h->m, n = h->n;
+  const int64_t wx = (n + 63) / 64, wy = (m + 63) / 64, S = (K + C - 1) / C;
+  // seed: dV/dx_K = c^, dV/dc^ (direct) = x_K
+  launch_copy_f64(h->XB, h->c, n, h->hs);
+  launch_fill(h->YB, 0.0, m, h->hs);
+  launch_fill(h->BB, 0.0, m, h->hs);
+  launch_copy_f64(h->CB, h->XK, n, h->hs);
+  HK();
+  AdjView a{};
+  a.m = m;
+  a.n = n;
+  a.rp = h->rp;
+  a.ci = h->ci;
+  a.cp = h->cp;
+  a.ri = h->ri;
+  a.v = h->v;
+  a.vt = h->vt;
+  a.long_rows = h->long_rows;
+  a.long_cols = h->long_cols;
+  a.n_long_rows = h->n_long_rows;
+  a.n_long_cols = h->n_long_cols;
+  a.nblk_rows = h->nblk_rows;
+  a.nblk_cols = h->nblk_cols;
+  a.XB = h->XB;
+  a.YB = h->YB;
+  a.H = h->H;
+  a.BB = h->BB;
+  a.CB = h->CB;
+  a.tau = h->ur_eta / h->ur_omega;
+  a.sigma = h->ur_eta * h->ur_omega;
+  std::vector<int> act{0};
+  for (int64_t s = S - 1; s >= 0; s--) {
+    int64_t steps = std::min<int64_t>(C, K - s * C);
+    // recompute the segment from its checkpoint, recording the masks
+    launch_fill_u64(h->mask_x, steps * wx, h->hs);
+    launch_fill_u64(h->mask_y, steps * wy, h->hs);
+    std::vector<Inst<double>> one{unrolled_inst(h)};
+    one[0].w.mask_x = h->mask_x;
+    one[0].w.mask_y = h->mask_y;
+    one[0].w.mask_k0 = s * C;
+    Groups g{};
+    RC(upload_group<double>(h, h->grp, one, act, g));
+    const Inst<double> *dI = h->grp.d64;
+    double *ck = h->ckpt + s * (n + 2 * m);
+    launch_checkpoint<double>(dI, g, ck, ck + n, ck + n + m, 1, h->hs);
+    HK();
+    RC(write_state_field(h, offsetof(CtlState, k), (long long)(s * C)));
+    for (int64_t i = 0; i < steps; i++) launch_attempt<double>(dI, g, h->hs);
+    HK();
+    // reverse sweep over the segment
+    for (int64_t k = steps - 1; k >= 0; k--) {
+      a.mask_x = h->mask_x + k * wx;
+      a.mask_y = h->mask_y + k * wy;
+      launch_adjoint_step(a, h->hs);
+    }
+    HK();
+  }
+  // back to the original space: dV/db = Dr b-bar, dV/dc = Dc c-bar
+  double *ob = h->on_device ? grad_b : h->it.AXA;
+  double *oc = h->on_device ? grad_c : h->it.ATYA;
+  launch_scale_vectors(h->BB, h->CB, h->CB, h->CB, h->Dr, h->Dc, m, n, ob, oc, h->H, h->XB,
+                       h->hs);
+  launch_axpby(ob, ob, gv, 0.0, m, h->hs);
+  launch_axpby(oc, oc, gv, 0.0, n, h->hs);
+  HK();
+  if (!h->on_device) {
+    HC(hipMemcpyAsync(grad_b, ob, sizeof(double) * m, hipMemcpyDeviceToHost, h->hs));
+    HC(hipMemcpyAsync(grad_c, oc, sizeof(double) * n, hipMemcpyDeviceToHost, h->hs));
+  }
+  HC(hipStreamSynchronize(h->hs));
+  return PDHG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, double *y,
                pdhg_info *info) {
   if (!h || !x || !y || !info) return fail(PDHG_ERR_ARG, "null argument");
@@ -846,11 +1058,21 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, do
       dy0 = h->it.YA;
     }
   }
+  double *xo = h->on_device ? x : h->it.ATYA;
+  double *yo = h->on_device ? y : h->it.AXA;
+  if (h->ur_K > 0) {
+    RC(solve_unrolled(h, dx0, dy0, xo, yo, info, t0));
+    if (!h->on_device) {
+      HC(hipMemcpyAsync(x, xo, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->hs));
+      HC(hipMemcpyAsync(y, yo, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->hs));
+    }
+    HC(hipStreamSynchronize(h->hs));
+    info->solve_s = now_s() - t0;
+    return leave(h);
+  }
   InstData d = base_data(h);
   std::vector<Inst<double>> i64{make_inst<double>(h, d, h->it)};
   std::vector<Inst<float>> i32{make_inst<float>(h, d, h->it)};
-  double *xo = h->on_device ? x : h->it.ATYA;
-  double *yo = h->on_device ? y : h->it.AXA;
   i64[0].x0 = i32[0].x0 = dx0;
   i64[0].y0 = i32[0].y0 = dy0;
   i64[0].xout = i32[0].xout = xo;
@@ -1106,8 +1328,40 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
   return PDHG_OK;
 }
 
-int pdhg_backward(pdhg_handle *, double, double *, double *) {
-  return fail(PDHG_ERR_STATE, "backward not available in this build");
+int pdhg_backward(pdhg_handle *h, double grad_value, double *grad_b, double *grad_c) {
+  if (!h || !grad_b || !grad_c) return fail(PDHG_ERR_ARG, "null argument");
+  if (!h->ur_valid)
+    return fail(PDHG_ERR_STATE, "backward needs a preceding unrolled solve (opts.unroll_iters > 0)");
+  RC(enter(h));
+  RC(backward_unrolled(h, grad_value, grad_b, grad_c));
+  return leave(h);
+}
+
+int pdhg_update(pdhg_handle *h, const double *b, const double *c) {
+  if (!h) return fail(PDHG_ERR_ARG, "null handle");
+  if (!h->on_device) {
+    for (int64_t i = 0; b && i < h->m; i++)
+      if (!isfinite(b[i])) return fail(PDHG_ERR_NONFINITE, "non-finite b[%lld]", (long long)i);
+    for (int64_t j = 0; c && j < h->n; j++)
+      if (!isfinite(c[j])) return fail(PDHG_ERR_NONFINITE, "non-finite c[%lld]", (long long)j);
+  }
+  RC(enter(h));
+  hipMemcpyKind kd = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (b) HC(hipMemcpyAsync(h->b0, b, sizeof(double) * h->m, kd, h->hs));
+  if (c) HC(hipMemcpyAsync(h->c0, c, sizeof(double) * h->n, kd, h->hs));
+  launch_scale_vectors(h->b0, h->c0, h->l0, h->u0, h->Dr, h->Dc, h->m, h->n, h->b, h->c, h->l,
+                       h->u, h->hs);
+  launch_init_ctl(h->v, h->nnz, h->b, h->c, h->b0, h->c0, h->m, h->n, h->scratch, h->nscratch,
+                  h->it.st, h->o.step_mode, h->o.step_mode == 1 ? h->o.fixed_eta : 0.0,
+                  h->o.fixed_omega, h->hs);
+  if (h->o.precision == PDHG_MIXED) {
+    launch_cast_f32(h->b, h->bf, h->m, h->hs);
+    launch_cast_f32(h->c, h->cf, h->n, h->hs);
+  }
+  HK();
+  HC(hipStreamSynchronize(h->hs));
+  h->ur_valid = false;
+  return leave(h);
 }
 
 void pdhg_destroy(pdhg_handle *h) {

@@ -57,6 +57,11 @@ struct IterView {
   double *part_dx2;              // [grid_cols]
   double *part_dy;               // [2 * grid_rows]
   int adaptive;
+  // unrolled-mode recording: when non-null, attempt k - mask_k0 writes its
+  // projection masks (bit j: pre-clamp x strictly inside the box; bit i:
+  // equality row or pre-projection y > 0) into words [(k - mask_k0) * words]
+  uint64_t *mask_x, *mask_y;
+  int64_t mask_k0;
 };
 
 // FP64 evaluation view (always FP64 matrix); iterates of type T.
@@ -146,6 +151,29 @@ void launch_switch_to_fp64(const Inst<float> *If, const Inst<double> *Id, const 
                            hipStream_t s);
 template <typename T>
 void launch_unscale(const Inst<T> *I, const Groups &g, hipStream_t s);
+// Adjoint of unrolled PDHG (FP64): one reverse step with the masks of the
+// forward step it undoes.
+struct AdjView {
+  int64_t m, n;
+  const int32_t *rp, *ci, *cp, *ri;
+  const double *v, *vt;
+  const int32_t *long_rows, *long_cols;
+  int n_long_rows, n_long_cols;
+  int nblk_rows, nblk_cols;
+  const uint64_t *mask_x, *mask_y;  // this step's masks
+  double *XB, *YB, *H, *BB, *CB;     // x-bar, y-bar, h, b-bar, c-bar
+  double tau, sigma;
+};
+void launch_adjoint_step(const AdjView &a, hipStream_t s);
+void launch_fill_u64(uint64_t *p, int64_t n, hipStream_t s);
+void launch_copy_f64(double *dst, const double *src, int64_t n, hipStream_t s);
+void launch_axpby(double *y, const double *x, double alpha, double beta, int64_t n,
+                  hipStream_t s);
+double *launch_sumsq(const double *x, int64_t n, double *scratch, int nscratch, hipStream_t s);
+template <typename T>
+void launch_checkpoint(const Inst<T> *I, const Groups &g, double *cx, double *cy, double *cax,
+                       int restore, hipStream_t s);
+
 template <typename T>
 void launch_gather_states(const Inst<T> *I, int n, CtlState *out, hipStream_t s);
 void launch_init_ctl(const double *v, int64_t nnz, const double *b, const double *c,

@@ -152,14 +152,29 @@ __device__ inline T tile_rowdot(const int32_t *__restrict__ ptr, const int32_t *
   return acc;
 }
 
+// Returns whether the pre-clamp value lies strictly inside the box.
 template <typename T>
-__device__ inline void primal_finish(const IterView<T> &w, int64_t j, T t, T tau, T xj, T cj, T lj,
+__device__ inline bool primal_finish(const IterView<T> &w, int64_t j, T t, T tau, T xj, T cj, T lj,
                                      T uj, T xsj, T *xn, double pend, int fresh, double &d2) {
-  T xv = clamp_box<T>(xj - tau * (cj - t), lj, uj);
+  T xt = xj - tau * (cj - t);
+  T xv = clamp_box<T>(xt, lj, uj);
   xn[j] = xv;
   double d = (double)xv - (double)xj;
   d2 += d * d;
   if (pend > 0.0) w.XS[j] = (fresh ? (T)0 : xsj) + (T)pend * xj;
+  return xt > lj && xt < uj;
+}
+
+// Bit-packed mask of one wave's 64 consecutive rows (tile rows are
+// 64-aligned); bits are OR-ed in, so long rows can add theirs separately.
+__device__ inline void record_mask(uint64_t *mask, int64_t row0_of_wave, bool bit) {
+  uint64_t bits = __ballot(bit);
+  if ((threadIdx.x & 63) == 0 && bits) atomicOr((unsigned long long *)&mask[row0_of_wave >> 6],
+                                                 (unsigned long long)bits);
+}
+
+__device__ inline void record_bit(uint64_t *mask, int64_t row) {
+  atomicOr((unsigned long long *)&mask[row >> 6], 1ull << (row & 63));
 }
 
 template <typename T>
@@ -188,9 +203,11 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict
     block_reduce<1>(acc, 0u, tot);
     if (threadIdx.x == 0) {
       double dd = 0.0;
-      primal_finish(w, j, (T)tot[0], tau, x[j], w.c[j], w.l[j], w.u[j], fold_read ? w.XS[j] : (T)0,
-                    xn, pend, fresh, dd);
+      bool in = primal_finish(w, j, (T)tot[0], tau, x[j], w.c[j], w.l[j], w.u[j],
+                              fold_read ? w.XS[j] : (T)0, xn, pend, fresh, dd);
       w.part_dx2[lb] = dd;
+      if (w.mask_x && in)
+        record_bit(w.mask_x + (st->k - w.mask_k0) * ((w.n + 63) >> 6), j);
     }
     return;
   }
@@ -213,18 +230,23 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict
     }
     bool mine = valid && (re - rs <= PDHG_LONG_SEG);
     T s = tile_rowdot<T>(w.cp, w.ri, w.vt, y, w.n, t * PDHG_BLOCK, rs, re, mine, lds);
-    if (mine) primal_finish(w, j, s, tau, xj, cj, lj, uj, xsj, xn, pend, fresh, d2[0]);
+    bool in = false;
+    if (mine) in = primal_finish(w, j, s, tau, xj, cj, lj, uj, xsj, xn, pend, fresh, d2[0]);
+    if (w.mask_x)
+      record_mask(w.mask_x + (st->k - w.mask_k0) * ((w.n + 63) >> 6), j & ~(int64_t)63, in);
   }
   double out[1];
   block_reduce<1>(d2, 0u, out);
   if (threadIdx.x == 0) w.part_dx2[lb] = out[0];
 }
 
+// Returns whether the row's dual is unprojected (equality row or value > 0).
 template <typename T>
-__device__ inline void dual_finish(const IterView<T> &w, int64_t i, T s, T sigma, int cur, T yi,
+__device__ inline bool dual_finish(const IterView<T> &w, int64_t i, T s, T sigma, int cur, T yi,
                                    T axi, T bi, uint8_t ki, T ysi, double pend, int fresh,
                                    double &dy2, double &inter) {
   T yv = yi + sigma * (bi - (s + s - axi));
+  bool in = (ki == 0) || (yv > (T)0);
   if (ki == 1 && yv < (T)0) yv = (T)0;
   w.Y[cur ^ 1][i] = yv;
   w.AX[cur ^ 1][i] = s;
@@ -232,6 +254,7 @@ __device__ inline void dual_finish(const IterView<T> &w, int64_t i, T s, T sigma
   dy2 += dy * dy;
   inter += dy * ((double)s - (double)axi);
   if (pend > 0.0) w.YS[i] = (fresh ? (T)0 : ysi) + (T)pend * yi;
+  return in;
 }
 
 template <typename T>
@@ -260,10 +283,12 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__
     block_reduce<1>(acc, 0u, tot);
     if (threadIdx.x == 0) {
       double dy2 = 0.0, inter = 0.0;
-      dual_finish(w, i, (T)tot[0], sigma, cur, y[i], ax[i], w.b[i], w.kind[i],
-                  fold_read ? w.YS[i] : (T)0, pend, fresh, dy2, inter);
+      bool in = dual_finish(w, i, (T)tot[0], sigma, cur, y[i], ax[i], w.b[i], w.kind[i],
+                            fold_read ? w.YS[i] : (T)0, pend, fresh, dy2, inter);
       w.part_dy[lb] = dy2;
       w.part_dy[G + lb] = inter;
+      if (w.mask_y && in)
+        record_bit(w.mask_y + (st->k - w.mask_k0) * ((w.m + 63) >> 6), i);
     }
     return;
   }
@@ -288,7 +313,10 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__
     }
     bool mine = valid && (re - rs <= PDHG_LONG_SEG);
     T s = tile_rowdot<T>(w.rp, w.ci, w.v, xn, w.m, t * PDHG_BLOCK, rs, re, mine, lds);
-    if (mine) dual_finish(w, i, s, sigma, cur, yi, axi, bi, ki, ysi, pend, fresh, v[0], v[1]);
+    bool in = false;
+    if (mine) in = dual_finish(w, i, s, sigma, cur, yi, axi, bi, ki, ysi, pend, fresh, v[0], v[1]);
+    if (w.mask_y)
+      record_mask(w.mask_y + (st->k - w.mask_k0) * ((w.m + 63) >> 6), i & ~(int64_t)63, in);
   }
   double out[2];
   block_reduce<2>(v, 0u, out);
@@ -798,6 +826,153 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_unscale_rows(const Inst<T> *__re
 }
 
 // ---------------------------------------------------------------------------
+// adjoint of unrolled PDHG
+//
+// Forward step k (fixed tau, sigma; masks Mx, My of that step):
+//   x' = P(x - tau c + tau A'y),  y' = P(y + sigma b - sigma A (2x' - x)).
+// Its transpose, applied to the adjoints (xb, yb) of (x', y'):
+//   g  = My .* yb                      (rows)
+//   t  = A' g,  xb' = xb - 2 sigma t,  h = Mx .* xb'
+//   xb <- sigma t + h,  cb -= tau h    (columns)
+//   yb <- g + tau A h,  bb += sigma g  (rows)
+// Two kernels per step: the column kernel gathers g = My .* yb on the fly.
+
+__device__ inline bool mask_bit(const uint64_t *mask, int64_t i) {
+  return (mask[i >> 6] >> (i & 63)) & 1ull;
+}
+
+__device__ inline void adj_col(const AdjView &a, int64_t j, double t) {
+  double xb = a.XB[j] - 2.0 * a.sigma * t;
+  double h = mask_bit(a.mask_x, j) ? xb : 0.0;
+  a.XB[j] = a.sigma * t + h;
+  a.CB[j] -= a.tau * h;
+  a.H[j] = h;
+}
+
+__global__ __launch_bounds__(PDHG_BLOCK) void k_adj_cols(AdjView a) {
+  int b = blockIdx.x;
+  if (b < a.n_long_cols) {
+    int64_t j = a.long_cols[b];
+    double acc[1] = {0.0};
+    for (int k = a.cp[j] + threadIdx.x; k < a.cp[j + 1]; k += PDHG_BLOCK) {
+      int64_t i = a.ri[k];
+      if (mask_bit(a.mask_y, i)) acc[0] += a.vt[k] * a.YB[i];
+    }
+    double tot[1];
+    block_reduce<1>(acc, 0u, tot);
+    if (threadIdx.x == 0) adj_col(a, j, tot[0]);
+    return;
+  }
+  int64_t j = (int64_t)(b - a.n_long_cols) * PDHG_BLOCK + threadIdx.x;
+  if (j >= a.n) return;
+  int s = a.cp[j], e = a.cp[j + 1];
+  if (e - s > PDHG_LONG_SEG) return;
+  double t = 0.0;
+  for (int k = s; k < e; k++) {
+    int64_t i = a.ri[k];
+    if (mask_bit(a.mask_y, i)) t += a.vt[k] * a.YB[i];
+  }
+  adj_col(a, j, t);
+}
+
+__device__ inline void adj_row(const AdjView &a, int64_t i, double s) {
+  double g = mask_bit(a.mask_y, i) ? a.YB[i] : 0.0;
+  a.YB[i] = g + a.tau * s;
+  a.BB[i] += a.sigma * g;
+}
+
+__global__ __launch_bounds__(PDHG_BLOCK) void k_adj_rows(AdjView a) {
+  int b = blockIdx.x;
+  if (b < a.n_long_rows) {
+    int64_t i = a.long_rows[b];
+    double acc[1] = {0.0};
+    for (int k = a.rp[i] + threadIdx.x; k < a.rp[i + 1]; k += PDHG_BLOCK) acc[0] += a.v[k] * a.H[a.ci[k]];
+    double tot[1];
+    block_reduce<1>(acc, 0u, tot);
+    if (threadIdx.x == 0) adj_row(a, i, tot[0]);
+    return;
+  }
+  int64_t i = (int64_t)(b - a.n_long_rows) * PDHG_BLOCK + threadIdx.x;
+  if (i >= a.m) return;
+  int s = a.rp[i], e = a.rp[i + 1];
+  if (e - s > PDHG_LONG_SEG) return;
+  double acc = 0.0;
+  for (int k = s; k < e; k++) acc += a.v[k] * a.H[a.ci[k]];
+  adj_row(a, i, acc);
+}
+
+__global__ void k_fill_u64(uint64_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+__global__ void k_copy_f64(double *__restrict__ d, const double *__restrict__ s, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+// y = alpha x + beta y
+__global__ void k_axpby(double *y, const double *x, double alpha, double beta, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = alpha * x[i] + beta * y[i];
+}
+
+__global__ __launch_bounds__(PDHG_BLOCK) void k_sumsq_partials(const double *x, int64_t n,
+                                                               double *part) {
+  double q[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * PDHG_BLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * PDHG_BLOCK)
+    q[0] += x[i] * x[i];
+  double out[1];
+  block_reduce<1>(q, 0u, out);
+  if (threadIdx.x == 0) part[blockIdx.x] = out[0];
+}
+
+__global__ __launch_bounds__(CTL_BLOCK) void k_sumsq_finish(double *part, int np, double *out) {
+  __shared__ double r[1];
+  reduce_partials<1>(part, np, 0, 0u, r);
+  if (threadIdx.x == 0) *out = r[0];
+}
+
+// Save (restore = 0) the current iterate x, y, Ax of each instance, or put a
+// saved one back as the current iterate (restore = 1).
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_checkpoint_cols(const Inst<T> *__restrict__ I,
+                                                                Groups g, double *cx,
+                                                                int restore) {
+  GROUP_BLOCK(p_cols)
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  if (j >= e.n) return;
+  if (restore)
+    e.X[0][j] = (T)cx[j];
+  else
+    cx[j] = (double)e.X[st->cur][j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_checkpoint_rows(const Inst<T> *__restrict__ I,
+                                                                Groups g, double *cy, double *cax,
+                                                                int restore) {
+  GROUP_BLOCK(p_rows)
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  if (i >= e.m) return;
+  if (restore) {
+    e.Y[0][i] = (T)cy[i];
+    e.AX[0][i] = (T)cax[i];
+  } else {
+    cy[i] = (double)e.Y[st->cur][i];
+    cax[i] = (double)e.AX[st->cur][i];
+  }
+}
+
+template <typename T>
+__global__ void k_restore_state(const Inst<T> *__restrict__ I) {
+  CtlState *st = I[blockIdx.x].st;
+  st->cur = 0;
+  st->pending = 0.0;
+}
+
+// ---------------------------------------------------------------------------
 // setup reductions for the initial step size and primal weight
 
 __global__ __launch_bounds__(PDHG_BLOCK) void k_norm_partials(const double *v, int64_t nnz,
@@ -941,6 +1116,40 @@ void launch_init_ctl(const double *v, int64_t nnz, const double *b, const double
   k_init_ctl<<<1, CTL_BLOCK, 0, s>>>(scratch, np, fixed_eta, fixed_omega, st);
 }
 
+void launch_adjoint_step(const AdjView &a, hipStream_t s) {
+  k_adj_cols<<<grid_of(a.n_long_cols + a.nblk_cols), PDHG_BLOCK, 0, s>>>(a);
+  k_adj_rows<<<grid_of(a.n_long_rows + a.nblk_rows), PDHG_BLOCK, 0, s>>>(a);
+}
+
+void launch_fill_u64(uint64_t *p, int64_t n, hipStream_t s) {
+  k_fill_u64<<<grid_for(n), PDHG_BLOCK, 0, s>>>(p, n);
+}
+
+void launch_copy_f64(double *dst, const double *src, int64_t n, hipStream_t s) {
+  k_copy_f64<<<grid_for(n), PDHG_BLOCK, 0, s>>>(dst, src, n);
+}
+
+void launch_axpby(double *y, const double *x, double alpha, double beta, int64_t n,
+                  hipStream_t s) {
+  k_axpby<<<grid_for(n), PDHG_BLOCK, 0, s>>>(y, x, alpha, beta, n);
+}
+
+// ||x||^2 into scratch[nscratch - 1] (device); partials use the rest.
+double *launch_sumsq(const double *x, int64_t n, double *scratch, int nscratch, hipStream_t s) {
+  int np = nscratch - 1 < 1024 ? nscratch - 1 : 1024;
+  k_sumsq_partials<<<np, PDHG_BLOCK, 0, s>>>(x, n, scratch);
+  k_sumsq_finish<<<1, CTL_BLOCK, 0, s>>>(scratch, np, scratch + nscratch - 1);
+  return scratch + nscratch - 1;
+}
+
+template <typename T>
+void launch_checkpoint(const Inst<T> *I, const Groups &g, double *cx, double *cy, double *cax,
+                       int restore, hipStream_t s) {
+  k_checkpoint_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g, cx, restore);
+  k_checkpoint_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g, cy, cax, restore);
+  if (restore) k_restore_state<T><<<grid_of(g.ninst), 1, 0, s>>>(I);
+}
+
 template <typename T>
 void launch_gather_states(const Inst<T> *I, int n, CtlState *out, hipStream_t s) {
   k_gather_states<T><<<(n + 63) / 64, 64, 0, s>>>(I, n, out);
@@ -960,6 +1169,8 @@ void launch_spmv(const int32_t *rp, const int32_t *ci, const double *v, int64_t 
                                    hipStream_t);                                           \
   template void launch_init_point<T>(const Inst<T> *, const Groups &, hipStream_t);        \
   template void launch_unscale<T>(const Inst<T> *, const Groups &, hipStream_t);            \
-  template void launch_gather_states<T>(const Inst<T> *, int, CtlState *, hipStream_t);
+  template void launch_gather_states<T>(const Inst<T> *, int, CtlState *, hipStream_t);        \
+  template void launch_checkpoint<T>(const Inst<T> *, const Groups &, double *, double *,    \
+                                     double *, int, hipStream_t);
 INST(double)
 INST(float)

@@ -117,6 +117,26 @@ class Problem:
         L.check(lib.pdhg_spmv(self.handle, 1 if transpose else 0, _ptr(x), _ptr(out)))
         return out
 
+    def update(self, b=None, c=None):
+        """Replace b and/or c (original space) of the set-up problem."""
+        lib = L.load()
+        if not self.device:
+            b = None if b is None else _host(b, np.float64)
+            c = None if c is None else _host(c, np.float64)
+        L.check(lib.pdhg_update(self.handle, _ptr(b), _ptr(c)))
+
+    def backward(self, grad_value: float = 1.0):
+        """Gradient of c'x_K of the last unrolled solve w.r.t. (b, c), times grad_value."""
+        lib = L.load()
+        if self.device:
+            import torch
+            gb = torch.empty(self.m, dtype=torch.float64, device="cuda")
+            gc = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        else:
+            gb, gc = np.zeros(self.m), np.zeros(self.n)
+        L.check(lib.pdhg_backward(self.handle, float(grad_value), _ptr(gb), _ptr(gc)))
+        return gb, gc
+
     def time_kernels(self, attempts: int = 200) -> dict:
         """Average ms per launch of the attempt kernels, timed with HIP events."""
         lib = L.load()
