@@ -2,13 +2,18 @@
 
 One step = one full pdhg_solve from a cold start to relative KKT 1e-4 on the
 seeded synthetic 6717-bus, 96-period UC LP (3.22M variables, 2.03M rows,
-7.19M nonzeros), with the problem already resident in HBM.  value = PDHG
-attempts per second over the timed solves (one attempt = one A'y and one Ax
-product); ms_per_step = time to 1e-4.
+7.19M nonzeros), with the problem already resident in HBM, in the mixed
+precision of that workload (FP32 SpMVs and iterates, FP64 reductions,
+restarts, step control and polish).  value = PDHG attempts per second over
+the timed solves (one attempt = one A'y and one Ax product); ms_per_step =
+time to 1e-4.
 
-Also reported: a live HIP-event timing of the dominant kernel against its
-algorithmic bytes (roofline), and the FP64 CPU oracle timed on a bounded
-sample of the same workload on the host cores.
+Also reported on the same line: the plain FP64 solve of the same LP (time to
+1e-4 and the mixed-precision speedup), batched LPs/s against the same
+instances solved one at a time, the unrolled solve and adjoint of the
+2000-bus differentiable case, a live HIP-event timing of the dominant kernel
+against its algorithmic bytes (roofline), and the FP64 CPU oracle timed on a
+bounded sample of the workload on the host cores.
 """
 from __future__ import annotations
 
@@ -80,13 +85,87 @@ def cpu_baseline(lp, sample_lo: int, sample_hi: int):
                        f"same LP, single thread; {t2 - t0:.1f}s of CPU work")
 
 
+def fp64_compare(lp, args):
+    """One cold FP64 solve of the same LP on the device (for the speedup)."""
+    import torch
+    from paper_2512_06715_amd.solver import Problem
+    p = Problem(lp, tol=args.tol, max_iter=args.max_iter, precision="fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = p.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    p.close()
+    return dict(fp64_time_to_tol_s=round(dt, 3), fp64_attempts=info["attempts"],
+                fp64_attempts_per_s=round(info["attempts"] / dt, 1),
+                fp64_rel_kkt=info["rel_kkt"], fp64_status=info["status_name"])
+
+
+def batch_run(args):
+    """Batched LPs/s on small instances of the batched workload (500-2000 buses,
+    24 periods, mixed precision, KKT 1e-4 each) against the same instances
+    solved one at a time with pdhg_solve (setup excluded from both)."""
+    import torch
+    from paper_2512_06715_amd import ucgen
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    lps = [ucgen.small_batch_instance(j) for j in range(args.batch_small)]
+    probs = [Problem(lp, tol=args.tol, precision="mixed", max_iter=args.max_iter) for lp in lps]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = solve_batch(probs, [dict(base=k) for k in range(len(lps))])
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    ok = sum(1 for r in res if r[2]["status"] == 1)
+    ts = 0.0
+    for p in probs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.solve()
+        torch.cuda.synchronize()
+        ts += time.perf_counter() - t0
+        p.close()
+    n = len(lps)
+    return dict(batch=dict(instances=n, solved=ok, lps_per_s=round(n / tb, 4),
+                           sequential_lps_per_s=round(n / ts, 4), speedup=round(ts / tb, 3),
+                           batch_s=round(tb, 3), sequential_s=round(ts, 3),
+                           workload="small instances 0..%d of the batched workload "
+                                    "(N ~ U{500..2000}, T=24), mixed, KKT 1e-4" % (n - 1)))
+
+
+def adjoint_run():
+    """Unrolled solve (1000 steps, checkpoints every 50) and its adjoint on the
+    2000-bus, 24-period differentiable case."""
+    import torch
+    from paper_2512_06715_amd import ucgen
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc2000_t24")
+    p = Problem(lp, unroll_iters=1000, checkpoint_every=50)
+    p.solve()
+    p.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info = p.solve()
+    t1 = time.perf_counter()
+    p.backward()
+    t2 = time.perf_counter()
+    p.close()
+    return dict(adjoint=dict(workload="uc2000_t24 (2000 buses, 300 units, 2700 lines, 24 periods)",
+                             unroll_iters=1000, checkpoint_every=50,
+                             forward_ms=round(1e3 * (t1 - t0), 2),
+                             backward_ms=round(1e3 * (t2 - t1), 2)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="uc6717_t96")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--no-compare-fp64", action="store_true")
+    ap.add_argument("--batch-small", type=int, default=8,
+                    help="small instances of the batched workload (0 skips the batch run)")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
     ap.add_argument("--kernel-attempts", type=int, default=200)
@@ -164,13 +243,26 @@ def main():
     nbytes = kernel_bytes(dom, lp.m, lp.n, lp.nnz, vb)
     achieved = nbytes / (kt[dom] * 1e-3) / 1e9
     kname = f"k_{dom}"
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+    roofline_kernel = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=load_traffic(kname, args.workload, args.precision),
                     kernel=kname, ms_per_launch=round(kt[dom], 5),
                     algorithmic_bytes_per_launch=nbytes,
                     kernel_ms=dict((k, round(v, 5)) for k, v in kt.items()))
+    roofline = roofline_kernel
     prob.close()
+    del DevLP
+
+    extra = {}
+    if not args.no_compare_fp64 and args.precision == "mixed":
+        print("[bench] plain FP64 solve of the same LP ...", file=sys.stderr, flush=True)
+        extra.update(fp64_compare(lp, args))
+    if args.batch_small > 0:
+        print("[bench] batched solve ...", file=sys.stderr, flush=True)
+        extra.update(batch_run(args))
+    if not args.no_adjoint:
+        print("[bench] unrolled solve + adjoint ...", file=sys.stderr, flush=True)
+        extra.update(adjoint_run())
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -178,6 +270,8 @@ def main():
         print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(lp, lo, hi)
 
+    if "fp64_time_to_tol_s" in extra:
+        extra["mixed_speedup_vs_fp64"] = round(extra["fp64_time_to_tol_s"] / (elapsed / args.steps), 3)
     last = infos[-1]
     out = dict(
         metric=METRIC,
@@ -201,6 +295,7 @@ def main():
         rel_kkt=last["rel_kkt"],
         primal_obj=last["primal_obj"],
         setup_s=round(setup_s, 3),
+        **extra,
         roofline=roofline,
         cpu_baseline=cpu,
     )

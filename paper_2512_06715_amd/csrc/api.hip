@@ -134,7 +134,8 @@ struct pdhg_handle {
   int nscratch = 0;
   int *err;
   int n_long_rows = 0, n_long_cols = 0, nblk_rows = 0, nblk_cols = 0;
-  int tpb_rows = 1, tpb_cols = 1, grid_rows = 1, grid_cols = 1;
+  int tpb_rows = 1, tpb_cols = 1;
+  int grid_rows[2] = {1, 1}, grid_cols[2] = {1, 1};  // attempt grids: [FP64, FP32]
 
   // unrolled mode: checkpoints (x, y, Ax) every ur_C steps, masks of one
   // segment, adjoint vectors, and the forward's step sizes
@@ -173,8 +174,13 @@ void partition(pdhg_handle *h) {
 }
 
 void set_grids(pdhg_handle *h) {
-  h->grid_rows = h->n_long_rows + (h->nblk_rows + h->tpb_rows - 1) / h->tpb_rows;
-  h->grid_cols = h->n_long_cols + (h->nblk_cols + h->tpb_cols - 1) / h->tpb_cols;
+  const int rpt[2] = {PDHG_RPT_F64, PDHG_RPT_F32};
+  for (int q = 0; q < 2; q++) {
+    int64_t tile = (int64_t)rpt[q] * PDHG_BLOCK;
+    int tr = (int)((h->m + tile - 1) / tile), tc = (int)((h->n + tile - 1) / tile);
+    h->grid_rows[q] = h->n_long_rows + (tr + h->tpb_rows - 1) / h->tpb_rows;
+    h->grid_cols[q] = h->n_long_cols + (tc + h->tpb_cols - 1) / h->tpb_cols;
+  }
 }
 
 size_t layout(pdhg_handle *h, void *base) {
@@ -371,8 +377,8 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   w.n_long_cols = h->n_long_cols;
   w.tpb_rows = h->tpb_rows;
   w.tpb_cols = h->tpb_cols;
-  w.grid_rows = h->grid_rows;
-  w.grid_cols = h->grid_cols;
+  w.grid_rows = h->grid_rows[sizeof(T) == 4];
+  w.grid_cols = h->grid_cols[sizeof(T) == 4];
   w.part_dx2 = b.part_dx2;
   w.part_dy = b.part_dy;
   w.adaptive = h->o.step_mode == 0;
@@ -1127,7 +1133,8 @@ size_t batch_layout(pdhg_handle *const *hs, const pdhg_instance *inst, int batch
     const pdhg_handle *h = hs[inst[k].base];
     int64_t m = h->m, n = h->n;
     bool mixed = h->o.precision == PDHG_MIXED;
-    carve_iter(cv, P.it[k], m, n, h->grid_rows, h->grid_cols, mixed);
+    carve_iter(cv, P.it[k], m, n, std::max(h->grid_rows[0], h->grid_rows[1]),
+               std::max(h->grid_cols[0], h->grid_cols[1]), mixed);
     if (inst[k].b) {
       P.b0[k] = cv.take<double>(m);
       P.b[k] = cv.take<double>(m);

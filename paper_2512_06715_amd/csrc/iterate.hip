@@ -120,7 +120,13 @@ __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t str
 // (the first blocks of the instance).  Each workgroup covers `tpb`
 // consecutive tiles and writes one partial per reduced quantity.
 
-#define TILE_CAP 2048
+// Rows per lane of the attempt kernels: a tile is RPT * 256 rows.  Two rows
+// per lane keep twice the bytes in flight for the 4-byte FP32 path.
+template <typename T>
+struct Rpt {
+  static constexpr int value = sizeof(T) == 4 ? PDHG_RPT_F32 : PDHG_RPT_F64;
+};
+#define TILE_CAP_PER_ROWS 2048
 
 // Streams read exactly once per launch bypass the cache hierarchy's reuse
 // policy so that L2 keeps the gathered vector windows.
@@ -129,27 +135,33 @@ __device__ inline T ld_stream(const T *p) {
   return __builtin_nontemporal_load(p);
 }
 
-// Row dot product of row r0 + threadIdx.x in one 256-row tile:
-// sum_k v[k] x[idx[k]].  rs/re are the row's bounds (already loaded).
-template <typename T>
-__device__ inline T tile_rowdot(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                const T *__restrict__ v, const T *__restrict__ x, int64_t nrows,
-                                int64_t r0, int rs, int re, bool mine, T *lds) {
-  int64_t rend = r0 + PDHG_BLOCK < nrows ? r0 + PDHG_BLOCK : nrows;
+// Row dot products of the RPT rows r0 + threadIdx.x + q * 256 of one tile:
+// s[q] = sum_k v[k] x[idx[k]].  rs/re are the rows' bounds (already loaded).
+template <typename T, int RPT>
+__device__ inline void tile_rowdot(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                   const T *__restrict__ v, const T *__restrict__ x, int64_t nrows,
+                                   int64_t r0, const int (&rs)[RPT], const int (&re)[RPT],
+                                   const bool (&mine)[RPT], T *lds, T (&s)[RPT]) {
+  int64_t rend = r0 + RPT * PDHG_BLOCK < nrows ? r0 + RPT * PDHG_BLOCK : nrows;
   int base = ptr[r0], top = ptr[rend];
   int cnt = top - base;
-  T acc = 0;
-  if (cnt <= TILE_CAP) {
+#pragma unroll
+  for (int q = 0; q < RPT; q++) s[q] = 0;
+  if (cnt <= RPT * TILE_CAP_PER_ROWS) {
     for (int k = threadIdx.x; k < cnt; k += PDHG_BLOCK)
       lds[k] = ld_stream(v + base + k) * x[ld_stream(idx + base + k)];
     __syncthreads();
-    if (mine)
-      for (int k = rs - base; k < re - base; k++) acc += lds[k];
+#pragma unroll
+    for (int q = 0; q < RPT; q++)
+      if (mine[q])
+        for (int k = rs[q] - base; k < re[q] - base; k++) s[q] += lds[k];
     __syncthreads();
-  } else if (mine) {
-    for (int k = rs; k < re; k++) acc += v[k] * x[idx[k]];
+  } else {
+#pragma unroll
+    for (int q = 0; q < RPT; q++)
+      if (mine[q])
+        for (int k = rs[q]; k < re[q]; k++) s[q] += v[k] * x[idx[k]];
   }
-  return acc;
 }
 
 // Returns whether the pre-clamp value lies strictly inside the box.
@@ -179,7 +191,8 @@ __device__ inline void record_bit(uint64_t *mask, int64_t row) {
 
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
-  __shared__ T lds[TILE_CAP];
+  constexpr int RPT = Rpt<T>::value;
+  __shared__ T lds[RPT * TILE_CAP_PER_ROWS];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = find_inst(g.p_primal, g.ninst, b);
   const int lb = b - g.p_primal[inst];
@@ -212,28 +225,40 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict
     return;
   }
   int64_t t0 = (int64_t)(lb - w.n_long_cols) * w.tpb_cols;
-  int64_t ntiles = (w.n + PDHG_BLOCK - 1) / PDHG_BLOCK;
+  int64_t ntiles = (w.n + RPT * PDHG_BLOCK - 1) / (RPT * PDHG_BLOCK);
   int64_t t1 = t0 + w.tpb_cols < ntiles ? t0 + w.tpb_cols : ntiles;
   for (int64_t t = t0; t < t1; t++) {
-    int64_t j = t * PDHG_BLOCK + threadIdx.x;
-    bool valid = j < w.n;
-    int rs = 0, re = 0;
-    T xj = 0, cj = 0, lj = 0, uj = 0, xsj = 0;
-    if (valid) {  // issue the column's own loads before the SpMV phase
-      rs = w.cp[j];
-      re = w.cp[j + 1];
-      xj = x[j];
-      cj = ld_stream(w.c + j);
-      lj = ld_stream(w.l + j);
-      uj = ld_stream(w.u + j);
-      if (fold_read) xsj = w.XS[j];
+    int64_t r0 = t * RPT * PDHG_BLOCK;
+    int rs[RPT], re[RPT];
+    bool mine[RPT];
+    T xj[RPT], cj[RPT], lj[RPT], uj[RPT], xsj[RPT], s[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; q++) {  // issue the columns' own loads before the SpMV phase
+      int64_t j = r0 + q * PDHG_BLOCK + threadIdx.x;
+      rs[q] = re[q] = 0;
+      xj[q] = cj[q] = lj[q] = uj[q] = xsj[q] = 0;
+      if (j < w.n) {
+        rs[q] = w.cp[j];
+        re[q] = w.cp[j + 1];
+        xj[q] = x[j];
+        cj[q] = ld_stream(w.c + j);
+        lj[q] = ld_stream(w.l + j);
+        uj[q] = ld_stream(w.u + j);
+        if (fold_read) xsj[q] = w.XS[j];
+      }
+      mine[q] = j < w.n && (re[q] - rs[q] <= PDHG_LONG_SEG);
     }
-    bool mine = valid && (re - rs <= PDHG_LONG_SEG);
-    T s = tile_rowdot<T>(w.cp, w.ri, w.vt, y, w.n, t * PDHG_BLOCK, rs, re, mine, lds);
-    bool in = false;
-    if (mine) in = primal_finish(w, j, s, tau, xj, cj, lj, uj, xsj, xn, pend, fresh, d2[0]);
-    if (w.mask_x)
-      record_mask(w.mask_x + (st->k - w.mask_k0) * ((w.n + 63) >> 6), j & ~(int64_t)63, in);
+    tile_rowdot<T, RPT>(w.cp, w.ri, w.vt, y, w.n, r0, rs, re, mine, lds, s);
+#pragma unroll
+    for (int q = 0; q < RPT; q++) {
+      int64_t j = r0 + q * PDHG_BLOCK + threadIdx.x;
+      bool in = false;
+      if (mine[q])
+        in = primal_finish(w, j, s[q], tau, xj[q], cj[q], lj[q], uj[q], xsj[q], xn, pend, fresh,
+                           d2[0]);
+      if (w.mask_x)
+        record_mask(w.mask_x + (st->k - w.mask_k0) * ((w.n + 63) >> 6), j & ~(int64_t)63, in);
+    }
   }
   double out[1];
   block_reduce<1>(d2, 0u, out);
@@ -259,7 +284,8 @@ __device__ inline bool dual_finish(const IterView<T> &w, int64_t i, T s, T sigma
 
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
-  __shared__ T lds[TILE_CAP];
+  constexpr int RPT = Rpt<T>::value;
+  __shared__ T lds[RPT * TILE_CAP_PER_ROWS];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = find_inst(g.p_dual, g.ninst, b);
   const int lb = b - g.p_dual[inst];
@@ -294,29 +320,42 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__
   }
   double v[2] = {0.0, 0.0};
   int64_t t0 = (int64_t)(lb - w.n_long_rows) * w.tpb_rows;
-  int64_t ntiles = (w.m + PDHG_BLOCK - 1) / PDHG_BLOCK;
+  int64_t ntiles = (w.m + RPT * PDHG_BLOCK - 1) / (RPT * PDHG_BLOCK);
   int64_t t1 = t0 + w.tpb_rows < ntiles ? t0 + w.tpb_rows : ntiles;
   for (int64_t t = t0; t < t1; t++) {
-    int64_t i = t * PDHG_BLOCK + threadIdx.x;
-    bool valid = i < w.m;
-    int rs = 0, re = 0;
-    T yi = 0, axi = 0, bi = 0, ysi = 0;
-    uint8_t ki = 0;
-    if (valid) {  // issue the row's own loads before the SpMV phase
-      rs = w.rp[i];
-      re = w.rp[i + 1];
-      yi = y[i];
-      axi = ax[i];
-      bi = ld_stream(w.b + i);
-      ki = w.kind[i];
-      if (fold_read) ysi = w.YS[i];
+    int64_t r0 = t * RPT * PDHG_BLOCK;
+    int rs[RPT], re[RPT];
+    bool mine[RPT];
+    T yi[RPT], axi[RPT], bi[RPT], ysi[RPT], s[RPT];
+    uint8_t ki[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; q++) {  // issue the rows' own loads before the SpMV phase
+      int64_t i = r0 + q * PDHG_BLOCK + threadIdx.x;
+      rs[q] = re[q] = 0;
+      yi[q] = axi[q] = bi[q] = ysi[q] = 0;
+      ki[q] = 0;
+      if (i < w.m) {
+        rs[q] = w.rp[i];
+        re[q] = w.rp[i + 1];
+        yi[q] = y[i];
+        axi[q] = ax[i];
+        bi[q] = ld_stream(w.b + i);
+        ki[q] = w.kind[i];
+        if (fold_read) ysi[q] = w.YS[i];
+      }
+      mine[q] = i < w.m && (re[q] - rs[q] <= PDHG_LONG_SEG);
     }
-    bool mine = valid && (re - rs <= PDHG_LONG_SEG);
-    T s = tile_rowdot<T>(w.rp, w.ci, w.v, xn, w.m, t * PDHG_BLOCK, rs, re, mine, lds);
-    bool in = false;
-    if (mine) in = dual_finish(w, i, s, sigma, cur, yi, axi, bi, ki, ysi, pend, fresh, v[0], v[1]);
-    if (w.mask_y)
-      record_mask(w.mask_y + (st->k - w.mask_k0) * ((w.m + 63) >> 6), i & ~(int64_t)63, in);
+    tile_rowdot<T, RPT>(w.rp, w.ci, w.v, xn, w.m, r0, rs, re, mine, lds, s);
+#pragma unroll
+    for (int q = 0; q < RPT; q++) {
+      int64_t i = r0 + q * PDHG_BLOCK + threadIdx.x;
+      bool in = false;
+      if (mine[q])
+        in = dual_finish(w, i, s[q], sigma, cur, yi[q], axi[q], bi[q], ki[q], ysi[q], pend, fresh,
+                         v[0], v[1]);
+      if (w.mask_y)
+        record_mask(w.mask_y + (st->k - w.mask_k0) * ((w.m + 63) >> 6), i & ~(int64_t)63, in);
+    }
   }
   double out[2];
   block_reduce<2>(v, 0u, out);

@@ -95,5 +95,5 @@ def test_autograd_load_and_cost(gpu, oracle_mod):
     Vo, dVo = oracle_mod.unrolled(lp, K, eta, omega, b1 - b0, c1 - c0)
     lhs = float((load.grad.numpy() * dD).sum() + (cost.grad.numpy() * dcost).sum())
     assert abs(lhs - dVo) <= 1e-9 * (1 + abs(dVo))
-    assert abs(float(V) - Vo) <= 1e-10 * (1 + abs(Vo))
+    assert abs(float(V.detach()) - Vo) <= 1e-10 * (1 + abs(Vo))
     p.close()
