@@ -98,6 +98,11 @@ typedef struct {
   int pw_update;          /* 1 (default): primal weight updated at restarts; 0: kept */
   double pw_theta;        /* smoothing of the primal-weight update in log space (default 0.5) */
   int tiles_per_block;    /* SpMV partition: 256-row tiles per workgroup; 0 = automatic */
+  int autotune;           /* 1: pdhg_setup times candidate SpMV partitions (tiles per
+                             workgroup, LDS-staged or per-row loops, long-row threshold)
+                             and keeps the fastest; cached per matrix in the process */
+  int spmv_direct;        /* partition without autotune: 1 = per-row loops, 0 = LDS tiles */
+  int long_seg;           /* rows/columns longer than this get a workgroup; 0 = 64 */
 } pdhg_opts;
 
 typedef struct {
@@ -204,6 +209,11 @@ int pdhg_export_setup(pdhg_handle *h, uint8_t *var_kind, int32_t *colptr,
  * (transpose = 1, x[m], out[n]) with the solver's FP64 SpMV kernels; host
  * memory. */
 int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out);
+
+/* The SpMV partition in use: out[0] tiles per workgroup, out[1] 1 for per-row
+ * loops (0: LDS-staged tiles), out[2] long-segment threshold, out[3] number
+ * of long rows plus long columns. */
+int pdhg_get_partition(pdhg_handle *h, int *out);
 
 /* Run `attempts` more attempts from the handle's current iterate (the state
  * the last pdhg_solve left) with HIP events around each kernel on the

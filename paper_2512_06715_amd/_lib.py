@@ -33,7 +33,8 @@ class PdhgOpts(ctypes.Structure):
                 ("pock_chambolle", c_int), ("restart", c_int), ("use_average", c_int),
                 ("unroll_iters", c_i64), ("checkpoint_every", c_i64), ("use_graph", c_int),
                 ("verbose", c_int), ("polish_tol", c_dbl), ("pw_update", c_int),
-                ("pw_theta", c_dbl), ("tiles_per_block", c_int)]
+                ("pw_theta", c_dbl), ("tiles_per_block", c_int), ("autotune", c_int),
+                ("spmv_direct", c_int), ("long_seg", c_int)]
 
 
 class PdhgInfo(ctypes.Structure):
@@ -75,6 +76,7 @@ SIGNATURES = {
     "pdhg_export_setup": (c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
     "pdhg_spmv": (c_int, [vp, c_int, vp, vp]),
     "pdhg_time_kernels": (c_int, [vp, c_int, ctypes.POINTER(c_dbl)]),
+    "pdhg_get_partition": (c_int, [vp, ctypes.POINTER(c_int)]),
 }
 
 _lib = None

@@ -11,7 +11,10 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -136,6 +139,9 @@ struct pdhg_handle {
   int n_long_rows = 0, n_long_cols = 0, nblk_rows = 0, nblk_cols = 0;
   int tpb_rows = 1, tpb_cols = 1;
   int grid_rows[2] = {1, 1}, grid_cols[2] = {1, 1};  // attempt grids: [FP64, FP32]
+  int long_seg = PDHG_LONG_SEG;  // SpMV partition (chosen by the autotuner or the options)
+  int direct = 0;
+  std::vector<int32_t> hrp, hcp;  // host copies of the row / column pointers
 
   // unrolled mode: checkpoints (x, y, Ax) every ur_C steps, masks of one
   // segment, adjoint vectors, and the forward's step sizes
@@ -256,6 +262,7 @@ int check_opts(const pdhg_opts *o) {
   if (o->unroll_iters < 0) return fail(PDHG_ERR_ARG, "unroll_iters must be >= 0");
   if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return fail(PDHG_ERR_ARG, "pw_theta must be in [0, 1]");
   if (o->tiles_per_block < 0) return fail(PDHG_ERR_ARG, "tiles_per_block must be >= 0");
+  if (o->long_seg < 0) return fail(PDHG_ERR_ARG, "long_seg must be >= 0");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -330,6 +337,33 @@ int validate_host(const pdhg_lp *lp) {
     if (r_) return r_; \
   } while (0)
 
+// Rows and columns longer than the partition's threshold get a workgroup each.
+int build_long_lists(pdhg_handle *h) {
+  std::vector<int32_t> lr, lc;
+  for (int64_t i = 0; i < h->m; i++)
+    if (h->hrp[i + 1] - h->hrp[i] > h->long_seg) lr.push_back((int32_t)i);
+  for (int64_t j = 0; j < h->n; j++)
+    if (h->hcp[j + 1] - h->hcp[j] > h->long_seg) lc.push_back((int32_t)j);
+  h->n_long_rows = (int)lr.size();
+  h->n_long_cols = (int)lc.size();
+  if (!lr.empty())
+    HC(hipMemcpyAsync(h->long_rows, lr.data(), sizeof(int32_t) * lr.size(), hipMemcpyHostToDevice,
+                      h->hs));
+  if (!lc.empty())
+    HC(hipMemcpyAsync(h->long_cols, lc.data(), sizeof(int32_t) * lc.size(), hipMemcpyHostToDevice,
+                      h->hs));
+  HC(hipStreamSynchronize(h->hs));
+  set_grids(h);
+  return PDHG_OK;
+}
+
+int apply_partition(pdhg_handle *h, int tpb, int direct, int long_seg) {
+  h->tpb_rows = h->tpb_cols = tpb;
+  h->direct = direct;
+  h->long_seg = long_seg;
+  return build_long_lists(h);
+}
+
 int enter(pdhg_handle *h) {
   if (h->hip_failed) return fail(PDHG_ERR_HIP, "handle unusable after an earlier HIP error");
   HC(hipEventRecord(h->ev, h->user));
@@ -382,6 +416,8 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   w.part_dx2 = b.part_dx2;
   w.part_dy = b.part_dy;
   w.adaptive = h->o.step_mode == 0;
+  w.long_seg = e.long_seg = h->long_seg;
+  w.direct = h->direct;
   e.v = h->v;
   e.vt = h->vt;
   e.b = d.b;
@@ -704,6 +740,88 @@ int unscale_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// SpMV partition autotuner
+
+// Average time of one attempt (both SpMV-fused kernels and the step control)
+// under the handle's current partition, from its own start point.
+template <typename T>
+int time_attempts(pdhg_handle *h, int warm, int reps, double *ms) {
+  InstData d = base_data(h);
+  std::vector<Inst<T>> one{make_inst<T>(h, d, h->it)};
+  std::vector<int> act{0};
+  Groups g{};
+  RC(upload_group<T>(h, h->grp, one, act, g));
+  const Inst<T> *dI = dev_insts<T>(h->grp);
+  launch_init_point<T>(dI, g, h->hs);
+  for (int i = 0; i < warm; i++) launch_attempt<T>(dI, g, h->hs);
+  HK();
+  hipEvent_t e0, e1;
+  HC(hipEventCreate(&e0));
+  HC(hipEventCreate(&e1));
+  HC(hipEventRecord(e0, h->hs));
+  for (int i = 0; i < reps; i++) launch_attempt<T>(dI, g, h->hs);
+  HC(hipEventRecord(e1, h->hs));
+  HK();
+  HC(hipEventSynchronize(e1));
+  float t = 0.f;
+  HC(hipEventElapsedTime(&t, e0, e1));
+  HC(hipEventDestroy(e0));
+  HC(hipEventDestroy(e1));
+  *ms = t / reps;
+  return PDHG_OK;
+}
+
+struct Partition {
+  int tpb, direct, long_seg;
+};
+
+// Choices already made in this process, by matrix signature.
+std::mutex g_tune_mu;
+std::map<std::tuple<int64_t, int64_t, int64_t, int, uint64_t>, Partition> g_tune_cache;
+
+uint64_t pointer_checksum(const std::vector<int32_t> &p) {
+  uint64_t hsh = 1469598103934665603ull;
+  size_t step = std::max<size_t>(1, p.size() / 4096);
+  for (size_t i = 0; i < p.size(); i += step) hsh = (hsh ^ (uint64_t)(uint32_t)p[i]) * 1099511628211ull;
+  return hsh ^ (uint64_t)(uint32_t)p.back();
+}
+
+// Time every candidate partition for a few attempts and keep the fastest.
+int autotune(pdhg_handle *h) {
+  auto key = std::make_tuple(h->m, h->n, h->nnz, h->o.precision,
+                             pointer_checksum(h->hrp) ^ (pointer_checksum(h->hcp) << 1));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end())
+      return apply_partition(h, it->second.tpb, it->second.direct, it->second.long_seg);
+  }
+  const int tpbs[] = {1, 2, 4};
+  const int directs[] = {0, 1};
+  const int segs[] = {32, 64, 256};
+  Partition best{1, 0, PDHG_LONG_SEG};
+  double best_ms = INFINITY;
+  for (int tpb : tpbs)
+    for (int dr : directs)
+      for (int ls : segs) {
+        RC(apply_partition(h, tpb, dr, ls));
+        double ms = 0.0;
+        if (h->o.precision == PDHG_MIXED)
+          RC(time_attempts<float>(h, 3, 20, &ms));
+        else
+          RC(time_attempts<double>(h, 3, 20, &ms));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = Partition{tpb, dr, ls};
+        }
+      }
+  RC(apply_partition(h, best.tpb, best.direct, best.long_seg));
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best;
+  return PDHG_OK;
+}
+
 // ===========================================================================
 // C ABI
 
@@ -731,6 +849,9 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->pw_update = 1;
   o->pw_theta = 0.5;
   o->tiles_per_block = 0;
+  o->autotune = 0;
+  o->spmv_direct = 0;
+  o->long_seg = 0;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -822,25 +943,14 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
                          h->hs);
     HK();
     // long rows and columns (handled by a workgroup each in the iteration)
-    std::vector<int32_t> hp(std::max(m, n) + 1);
-    std::vector<int32_t> lr, lc;
-    HC(hipMemcpyAsync(hp.data(), h->rp, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost, h->hs));
+    h->hrp.resize(m + 1);
+    h->hcp.resize(n + 1);
+    HC(hipMemcpyAsync(h->hrp.data(), h->rp, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost, h->hs));
+    HC(hipMemcpyAsync(h->hcp.data(), h->cp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, h->hs));
     HC(hipStreamSynchronize(h->hs));
-    for (int64_t i = 0; i < m; i++)
-      if (hp[i + 1] - hp[i] > PDHG_LONG_SEG) lr.push_back((int32_t)i);
-    HC(hipMemcpyAsync(hp.data(), h->cp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, h->hs));
-    HC(hipStreamSynchronize(h->hs));
-    for (int64_t j = 0; j < n; j++)
-      if (hp[j + 1] - hp[j] > PDHG_LONG_SEG) lc.push_back((int32_t)j);
-    h->n_long_rows = (int)lr.size();
-    h->n_long_cols = (int)lc.size();
-    set_grids(h);
-    if (!lr.empty())
-      HC(hipMemcpyAsync(h->long_rows, lr.data(), sizeof(int32_t) * lr.size(), hipMemcpyHostToDevice,
-                        h->hs));
-    if (!lc.empty())
-      HC(hipMemcpyAsync(h->long_cols, lc.data(), sizeof(int32_t) * lc.size(), hipMemcpyHostToDevice,
-                        h->hs));
+    h->direct = h->o.spmv_direct;
+    h->long_seg = h->o.long_seg > 0 ? h->o.long_seg : PDHG_LONG_SEG;
+    RC(build_long_lists(h));
     launch_init_ctl(h->v, nnz, h->b, h->c, h->b0, h->c0, m, n, h->scratch, h->nscratch, h->it.st,
                     h->o.step_mode, h->o.step_mode == 1 ? h->o.fixed_eta : 0.0, h->o.fixed_omega,
                     h->hs);
@@ -854,6 +964,7 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
     }
     HK();
     HC(hipStreamSynchronize(h->hs));
+    if (h->o.autotune) RC(autotune(h));
     return leave(h);
   };
   rc = setup_body();
@@ -993,6 +1104,7 @@ int backward_unrolled(pdhg_handle *h, double gv, double *grad_b, double *grad_c)
   a.n_long_cols = h->n_long_cols;
   a.nblk_rows = h->nblk_rows;
   a.nblk_cols = h->nblk_cols;
+  a.long_seg = h->long_seg;
   a.XB = h->XB;
   a.YB = h->YB;
   a.H = h->H;
@@ -1457,6 +1569,15 @@ int time_kernels(pdhg_handle *h, int attempts, double *ms) {
   return PDHG_OK;
 }
 }  // namespace
+
+extern "C" int pdhg_get_partition(pdhg_handle *h, int *out) {
+  if (!h || !out) return fail(PDHG_ERR_ARG, "null argument");
+  out[0] = h->tpb_rows;
+  out[1] = h->direct;
+  out[2] = h->long_seg;
+  out[3] = h->n_long_rows + h->n_long_cols;
+  return PDHG_OK;
+}
 
 extern "C" int pdhg_time_kernels(pdhg_handle *h, int attempts, double *ms_out) {
   if (!h || !ms_out || attempts < 1) return fail(PDHG_ERR_ARG, "bad argument");

@@ -4,7 +4,7 @@
 #include <stdint.h>
 
 #define PDHG_BLOCK 256
-// rows / columns longer than this are handled by a workgroup each
+// default length above which a row / column is handled by a workgroup
 #define PDHG_LONG_SEG 64
 // rows per lane of the attempt kernels (tile = rows_per_lane * 256 rows)
 #define PDHG_RPT_F64 1
@@ -60,6 +60,8 @@ struct IterView {
   double *part_dx2;              // [grid_cols]
   double *part_dy;               // [2 * grid_rows]
   int adaptive;
+  int long_seg;                  // rows longer than this get a workgroup each
+  int direct;                    // 1: per-row loops instead of LDS-staged tiles
   // unrolled-mode recording: when non-null, attempt k - mask_k0 writes its
   // projection masks (bit j: pre-clamp x strictly inside the box; bit i:
   // equality row or pre-projection y > 0) into words [(k - mask_k0) * words]
@@ -83,6 +85,7 @@ struct EvalView {
   double *part_cols;             // [nblk_cols * EV_COLQ]
   int use_average, restart;
   double pw_theta;               // 0 keeps the primal weight
+  int long_seg;
 };
 
 #define EV_ROWQ 10
@@ -163,6 +166,7 @@ struct AdjView {
   const int32_t *long_rows, *long_cols;
   int n_long_rows, n_long_cols;
   int nblk_rows, nblk_cols;
+  int long_seg;
   const uint64_t *mask_x, *mask_y;  // this step's masks
   double *XB, *YB, *H, *BB, *CB;     // x-bar, y-bar, h, b-bar, c-bar
   double tau, sigma;

@@ -116,7 +116,8 @@ __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t str
 // consecutive lanes on consecutive nonzeros (coalesced), forms the products
 // with the gathered vector into LDS, and each lane then sums its own row from
 // LDS in CSR order.  Tiles whose nonzeros do not fit the LDS buffer fall back
-// to one lane per row.  Rows longer than PDHG_LONG_SEG get a workgroup each
+// to one lane per row (as does the `direct` partition).  Rows longer than
+// `long_seg` get a workgroup each
 // (the first blocks of the instance).  Each workgroup covers `tpb`
 // consecutive tiles and writes one partial per reduced quantity.
 
@@ -141,13 +142,13 @@ template <typename T, int RPT>
 __device__ inline void tile_rowdot(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                    const T *__restrict__ v, const T *__restrict__ x, int64_t nrows,
                                    int64_t r0, const int (&rs)[RPT], const int (&re)[RPT],
-                                   const bool (&mine)[RPT], T *lds, T (&s)[RPT]) {
+                                   const bool (&mine)[RPT], T *lds, T (&s)[RPT], int direct) {
   int64_t rend = r0 + RPT * PDHG_BLOCK < nrows ? r0 + RPT * PDHG_BLOCK : nrows;
   int base = ptr[r0], top = ptr[rend];
   int cnt = top - base;
 #pragma unroll
   for (int q = 0; q < RPT; q++) s[q] = 0;
-  if (cnt <= RPT * TILE_CAP_PER_ROWS) {
+  if (!direct && cnt <= RPT * TILE_CAP_PER_ROWS) {
     for (int k = threadIdx.x; k < cnt; k += PDHG_BLOCK)
       lds[k] = ld_stream(v + base + k) * x[ld_stream(idx + base + k)];
     __syncthreads();
@@ -246,9 +247,9 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict
         uj[q] = ld_stream(w.u + j);
         if (fold_read) xsj[q] = w.XS[j];
       }
-      mine[q] = j < w.n && (re[q] - rs[q] <= PDHG_LONG_SEG);
+      mine[q] = j < w.n && (re[q] - rs[q] <= w.long_seg);
     }
-    tile_rowdot<T, RPT>(w.cp, w.ri, w.vt, y, w.n, r0, rs, re, mine, lds, s);
+    tile_rowdot<T, RPT>(w.cp, w.ri, w.vt, y, w.n, r0, rs, re, mine, lds, s, w.direct);
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
       int64_t j = r0 + q * PDHG_BLOCK + threadIdx.x;
@@ -343,9 +344,9 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__
         ki[q] = w.kind[i];
         if (fold_read) ysi[q] = w.YS[i];
       }
-      mine[q] = i < w.m && (re[q] - rs[q] <= PDHG_LONG_SEG);
+      mine[q] = i < w.m && (re[q] - rs[q] <= w.long_seg);
     }
-    tile_rowdot<T, RPT>(w.rp, w.ci, w.v, xn, w.m, r0, rs, re, mine, lds, s);
+    tile_rowdot<T, RPT>(w.rp, w.ci, w.v, xn, w.m, r0, rs, re, mine, lds, s, w.direct);
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
       int64_t i = r0 + q * PDHG_BLOCK + threadIdx.x;
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_spmv(const Inst<T> *__restr
   int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (i >= s.rows) return;
   int a = s.ptr[i], z = s.ptr[i + 1];
-  if (z - a > PDHG_LONG_SEG) return;
+  if (z - a > I[inst].e.long_seg) return;
   double acc = 0.0;
   if (s.xt)
     for (int k = a; k < z; k++) acc += s.v[k] * (double)s.xt[s.idx[k]];
@@ -905,7 +906,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_adj_cols(AdjView a) {
   int64_t j = (int64_t)(b - a.n_long_cols) * PDHG_BLOCK + threadIdx.x;
   if (j >= a.n) return;
   int s = a.cp[j], e = a.cp[j + 1];
-  if (e - s > PDHG_LONG_SEG) return;
+  if (e - s > a.long_seg) return;
   double t = 0.0;
   for (int k = s; k < e; k++) {
     int64_t i = a.ri[k];
@@ -934,7 +935,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_adj_rows(AdjView a) {
   int64_t i = (int64_t)(b - a.n_long_rows) * PDHG_BLOCK + threadIdx.x;
   if (i >= a.m) return;
   int s = a.rp[i], e = a.rp[i + 1];
-  if (e - s > PDHG_LONG_SEG) return;
+  if (e - s > a.long_seg) return;
   double acc = 0.0;
   for (int k = s; k < e; k++) acc += a.v[k] * a.H[a.ci[k]];
   adj_row(a, i, acc);

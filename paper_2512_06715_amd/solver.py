@@ -137,6 +137,12 @@ class Problem:
         L.check(lib.pdhg_backward(self.handle, float(grad_value), _ptr(gb), _ptr(gc)))
         return gb, gc
 
+    def partition(self) -> dict:
+        """The SpMV partition in use (chosen by the autotuner or the options)."""
+        out = (ctypes.c_int * 4)()
+        L.check(L.load().pdhg_get_partition(self.handle, out))
+        return dict(tiles_per_block=out[0], direct=out[1], long_seg=out[2], long_segments=out[3])
+
     def time_kernels(self, attempts: int = 200) -> dict:
         """Average ms per launch of the attempt kernels, timed with HIP events."""
         lib = L.load()

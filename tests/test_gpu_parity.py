@@ -90,3 +90,45 @@ def test_short_trajectory(gpu, oracle_mod, name, iters, bound):
     assert err <= bound * scale, err / scale
     k = oracle_mod.kkt(lp, x, y)
     assert abs(k["rel_kkt"] - info["rel_kkt"]) <= 1e-9 * max(1.0, k["rel_kkt"])
+
+
+@pytest.mark.parametrize("part", [dict(spmv_direct=1), dict(long_seg=8), dict(tiles_per_block=3),
+                                  dict(spmv_direct=1, long_seg=4, tiles_per_block=2)])
+def test_partitions_agree(gpu, oracle_mod, part):
+    """Every SpMV partition computes the same attempt (up to rounding) and
+    solves to the same optimum."""
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.random_uc(14, 5, 20, 24, 1.0, seed=11)
+    print("case partition", part, flush=True)
+    p = Problem(lp, max_iter=1, tol=1e-12, use_graph=0, **part)
+    x, y, info = p.solve()
+    got = p.partition()
+    p.close()
+    for k, v in part.items():
+        key = {"spmv_direct": "direct", "tiles_per_block": "tiles_per_block"}.get(k, k)
+        assert got[key] == v
+    xo, yo, io = oracle_mod.pdhg(lp, tol=1e-12, max_iter=1)
+    np.testing.assert_allclose(x, xo, rtol=1e-12, atol=1e-12 * (1 + np.abs(xo).max()))
+    np.testing.assert_allclose(y, yo, rtol=1e-12, atol=1e-12 * (1 + np.abs(yo).max()))
+    p = Problem(lp, tol=1e-7, max_iter=400000, **part)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 1
+    from oracle import exact
+    _, _, ref, _ = exact.highs(lp)
+    assert abs(info["primal_obj"] - ref) <= 1e-6 * abs(ref)
+
+
+def test_autotune_picks_a_candidate(gpu, oracle_mod):
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc1000_t48")
+    print("case autotune", flush=True)
+    p = Problem(lp, autotune=1, tol=1e-4, precision="mixed")
+    part = p.partition()
+    assert part["tiles_per_block"] in (1, 2, 4)
+    assert part["direct"] in (0, 1) and part["long_seg"] in (32, 64, 256)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 1
+    assert oracle_mod.kkt(lp, x, y)["rel_kkt"] <= 1.001e-4
+    print("autotuned partition", part, flush=True)
