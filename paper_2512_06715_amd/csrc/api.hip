@@ -180,9 +180,8 @@ void partition(pdhg_handle *h) {
 }
 
 void set_grids(pdhg_handle *h) {
-  const int rpt[2] = {PDHG_RPT_F64, PDHG_RPT_F32};
   for (int q = 0; q < 2; q++) {
-    int64_t tile = (int64_t)rpt[q] * PDHG_BLOCK;
+    int64_t tile = PDHG_BLOCK;
     int tr = (int)((h->m + tile - 1) / tile), tc = (int)((h->n + tile - 1) / tile);
     h->grid_rows[q] = h->n_long_rows + (tr + h->tpb_rows - 1) / h->tpb_rows;
     h->grid_cols[q] = h->n_long_cols + (tc + h->tpb_cols - 1) / h->tpb_cols;

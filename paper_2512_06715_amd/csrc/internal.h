@@ -6,9 +6,6 @@
 #define PDHG_BLOCK 256
 // default length above which a row / column is handled by a workgroup
 #define PDHG_LONG_SEG 64
-// rows per lane of the attempt kernels (tile = rows_per_lane * 256 rows)
-#define PDHG_RPT_F64 1
-#define PDHG_RPT_F32 1
 // tile groups per launch above which a workgroup takes several tiles
 #define PDHG_TARGET_GROUPS 65536
 // columns longer than this are sorted with a workgroup during the transpose

@@ -121,61 +121,137 @@ __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t str
 // (the first blocks of the instance).  Each workgroup covers `tpb`
 // consecutive tiles and writes one partial per reduced quantity.
 
-// Rows per lane of the attempt kernels: a tile is RPT * 256 rows.  Two rows
-// per lane keep twice the bytes in flight for the 4-byte FP32 path.
+// Address spaces.  Pointers read out of the instance tables are generic; the
+// attempt kernels cast them so that the compiler emits global (vector) and
+// scalar loads instead of flat ones, whose shared wait counter serialises
+// the otherwise independent load streams.  Instance tables, control states
+// and CSR pointers are not written while an attempt kernel runs, so their
+// uniform reads may go through the scalar path.
+#define AS_G __attribute__((address_space(1)))
+#define AS_C __attribute__((address_space(4)))
 template <typename T>
-struct Rpt {
-  static constexpr int value = sizeof(T) == 4 ? PDHG_RPT_F32 : PDHG_RPT_F64;
-};
-#define TILE_CAP_PER_ROWS 2048
+__device__ __forceinline__ const AS_G T *gin(const T *p) {
+  return (const AS_G T *)p;
+}
+template <typename T>
+__device__ __forceinline__ AS_G T *gout(T *p) {
+  return (AS_G T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const AS_C T *cin(const T *p) {
+  return (const AS_C T *)p;
+}
+
+// Instance owning logical block b (uniform): the largest i with pre[i] <= b.
+__device__ inline int find_inst_u(const int32_t *pre, int ninst, int b) {
+  const AS_C int32_t *p = cin(pre);
+  int lo = 0, hi = ninst;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (p[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+#define TILE_CAP 2048  // nonzeros of a tile staged in LDS
+#define TILE_U 4       // nonzeros per lane loaded before their gathers
 
 // Streams read exactly once per launch bypass the cache hierarchy's reuse
 // policy so that L2 keeps the gathered vector windows.
 template <typename T>
-__device__ inline T ld_stream(const T *p) {
+__device__ __forceinline__ T ld_stream(const AS_G T *p) {
   return __builtin_nontemporal_load(p);
 }
 
-// Row dot products of the RPT rows r0 + threadIdx.x + q * 256 of one tile:
-// s[q] = sum_k v[k] x[idx[k]].  rs/re are the rows' bounds (already loaded).
-template <typename T, int RPT>
-__device__ inline void tile_rowdot(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                   const T *__restrict__ v, const T *__restrict__ x, int64_t nrows,
-                                   int64_t r0, const int (&rs)[RPT], const int (&re)[RPT],
-                                   const bool (&mine)[RPT], T *lds, T (&s)[RPT], int direct) {
-  int64_t rend = r0 + RPT * PDHG_BLOCK < nrows ? r0 + RPT * PDHG_BLOCK : nrows;
-  int base = ptr[r0], top = ptr[rend];
-  int cnt = top - base;
+// Products are rounded on their own (never fused into the sum), so the
+// LDS-staged and the per-row paths give bit-identical row sums.
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+
+// Dot product s = sum_k v[k] x[idx[k]] of this lane's row i (rows r0 + lane of
+// a 256-row tile whose nonzeros are [base, top)), summed in CSR order.  The
+// row's bounds are loaded here, after the tile's index/value stream has been
+// issued, so the gathers wait only on that stream.  `mine` returns whether
+// the row is valid and short enough to be this tile's.  Every lane of the
+// workgroup must call it.
+template <typename T>
+__device__ __forceinline__ T tile_rowdot(const AS_G int32_t *ptr, const AS_G int32_t *idx,
+                                         const AS_G T *v, const AS_G T *x, int64_t i, bool valid,
+                                         int base, int top, int long_seg, T *lds, int direct,
+                                         bool &mine) {
+  const int cnt = top - base;
+  T s = 0;
+  int rs = 0, re = 0;
+  if (!direct && cnt <= TILE_CAP) {
+    for (int k0 = 0; k0 < cnt; k0 += TILE_U * PDHG_BLOCK) {
+      int id[TILE_U];
+      T vv[TILE_U];
 #pragma unroll
-  for (int q = 0; q < RPT; q++) s[q] = 0;
-  if (!direct && cnt <= RPT * TILE_CAP_PER_ROWS) {
-    for (int k = threadIdx.x; k < cnt; k += PDHG_BLOCK)
-      lds[k] = ld_stream(v + base + k) * x[ld_stream(idx + base + k)];
+      for (int q = 0; q < TILE_U; q++) {
+        int k = k0 + q * PDHG_BLOCK + (int)threadIdx.x;
+        int kc = base + (k < cnt ? k : cnt - 1);
+        id[q] = ld_stream(idx + kc);
+        vv[q] = ld_stream(v + kc);
+      }
+      if (k0 == 0 && valid) {
+        rs = ptr[i];
+        re = ptr[i + 1];
+      }
+#pragma unroll
+      for (int q = 0; q < TILE_U; q++) {
+        int k = k0 + q * PDHG_BLOCK + (int)threadIdx.x;
+        // lanes past the tile write a slot of their own past the staged range
+        lds[k < cnt ? k : TILE_CAP + (int)threadIdx.x] = mul_rn(vv[q], x[id[q]]);
+      }
+    }
+    if (cnt == 0 && valid) {
+      rs = ptr[i];
+      re = ptr[i + 1];
+    }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < RPT; q++)
-      if (mine[q])
-        for (int k = rs[q] - base; k < re[q] - base; k++) s[q] += lds[k];
+    mine = valid && (re - rs <= long_seg);
+    if (mine)
+      for (int k = rs - base; k < re - base; k++) s += lds[k];
     __syncthreads();
   } else {
+    if (valid) {
+      rs = ptr[i];
+      re = ptr[i + 1];
+    }
+    mine = valid && (re - rs <= long_seg);
+    if (mine) {
+      for (int k0 = rs; k0 < re; k0 += TILE_U) {
+        int id[TILE_U];
+        T vv[TILE_U];
 #pragma unroll
-    for (int q = 0; q < RPT; q++)
-      if (mine[q])
-        for (int k = rs[q]; k < re[q]; k++) s[q] += v[k] * x[idx[k]];
+        for (int q = 0; q < TILE_U; q++) {
+          int kc = k0 + q < re ? k0 + q : re - 1;
+          id[q] = idx[kc];
+          vv[q] = v[kc];
+        }
+#pragma unroll
+        for (int q = 0; q < TILE_U; q++) {
+          T p = mul_rn(vv[q], x[id[q]]);
+          if (k0 + q < re) s += p;
+        }
+      }
+    }
   }
+  return s;
 }
 
-// Returns whether the pre-clamp value lies strictly inside the box.
+// One long row (a workgroup of its own): FP64 sum of the products.
 template <typename T>
-__device__ inline bool primal_finish(const IterView<T> &w, int64_t j, T t, T tau, T xj, T cj, T lj,
-                                     T uj, T xsj, T *xn, double pend, int fresh, double &d2) {
-  T xt = xj - tau * (cj - t);
-  T xv = clamp_box<T>(xt, lj, uj);
-  xn[j] = xv;
-  double d = (double)xv - (double)xj;
-  d2 += d * d;
-  if (pend > 0.0) w.XS[j] = (fresh ? (T)0 : xsj) + (T)pend * xj;
-  return xt > lj && xt < uj;
+__device__ __forceinline__ double long_rowdot(const AS_G int32_t *idx, const AS_G T *v,
+                                              const AS_G T *x, int s, int e) {
+  double acc[1] = {0.0};
+  for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)mul_rn(v[k], x[idx[k]]);
+  double tot[1];
+  block_reduce<1>(acc, 0u, tot);
+  return tot[0];
 }
 
 // Bit-packed mask of one wave's 64 consecutive rows (tile rows are
@@ -190,179 +266,172 @@ __device__ inline void record_bit(uint64_t *mask, int64_t row) {
   atomicOr((unsigned long long *)&mask[row >> 6], 1ull << (row & 63));
 }
 
+// Primal update of column j from t = (A'y)_j; returns whether the pre-clamp
+// value lies strictly inside the box.  Folds the previous iterate into the
+// running sum when an accepted weight is pending.
+template <typename T>
+__device__ __forceinline__ bool primal_finish(int64_t j, T t, T tau, T xj, T cj, T lj, T uj,
+                                              T xsj, AS_G T *xn, AS_G T *xs, double pend,
+                                              int fresh, double &d2) {
+  T xt = xj - tau * (cj - t);
+  T xv = clamp_box<T>(xt, lj, uj);
+  xn[j] = xv;
+  double d = (double)xv - (double)xj;
+  d2 += d * d;
+  if (pend > 0.0) xs[j] = (fresh ? (T)0 : xsj) + (T)pend * xj;
+  return xt > lj && xt < uj;
+}
+
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
-  constexpr int RPT = Rpt<T>::value;
-  __shared__ T lds[RPT * TILE_CAP_PER_ROWS];
+  __shared__ T lds[TILE_CAP + PDHG_BLOCK];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int inst = find_inst(g.p_primal, g.ninst, b);
-  const int lb = b - g.p_primal[inst];
-  const IterView<T> &w = I[inst].w;
-  const CtlState *st = I[inst].st;
+  const int inst = find_inst_u(g.p_primal, g.ninst, b);
+  const int lb = b - cin(g.p_primal)[inst];
+  const AS_C IterView<T> &w = cin(I)[inst].w;
+  const AS_C CtlState *st = cin(cin(I)[inst].st);
   const int cur = st->cur;
   const T tau = (T)(st->eta / st->omega);
   const double pend = st->pending;
   const int fresh = st->fresh;
   const bool fold_read = pend > 0.0 && !fresh;
-  const T *__restrict__ x = w.X[cur];
-  T *__restrict__ xn = w.X[cur ^ 1];
-  const T *__restrict__ y = w.Y[cur];
+  const int64_t n = w.n;
+  const AS_G int32_t *cp = gin(w.cp), *ri = gin(w.ri);
+  const AS_G T *vt = gin(w.vt), *c = gin(w.c), *l = gin(w.l), *u = gin(w.u);
+  const AS_G T *x = gin((const T *)w.X[cur]), *y = gin((const T *)w.Y[cur]);
+  AS_G T *xn = gout(w.X[cur ^ 1]);
+  AS_G T *xs = gout(w.XS);
+  uint64_t *mask = w.mask_x ? w.mask_x + (st->k - w.mask_k0) * ((n + 63) >> 6) : nullptr;
   double d2[1] = {0.0};
   if (lb < w.n_long_cols) {
-    int64_t j = w.long_cols[lb];
-    int s = w.cp[j], e = w.cp[j + 1];
-    double acc[1] = {0.0};
-    for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)(w.vt[k] * y[w.ri[k]]);
-    double tot[1];
-    block_reduce<1>(acc, 0u, tot);
+    int64_t j = gin(w.long_cols)[lb];
+    const AS_C int32_t *cpc = cin(w.cp);
+    double t = long_rowdot<T>(ri, vt, y, cpc[j], cpc[j + 1]);
     if (threadIdx.x == 0) {
       double dd = 0.0;
-      bool in = primal_finish(w, j, (T)tot[0], tau, x[j], w.c[j], w.l[j], w.u[j],
-                              fold_read ? w.XS[j] : (T)0, xn, pend, fresh, dd);
-      w.part_dx2[lb] = dd;
-      if (w.mask_x && in)
-        record_bit(w.mask_x + (st->k - w.mask_k0) * ((w.n + 63) >> 6), j);
+      bool in = primal_finish<T>(j, (T)t, tau, x[j], c[j], l[j], u[j],
+                                 fold_read ? xs[j] : (T)0, xn, xs, pend, fresh, dd);
+      gout(w.part_dx2)[lb] = dd;
+      if (mask && in) record_bit(mask, j);
     }
     return;
   }
-  int64_t t0 = (int64_t)(lb - w.n_long_cols) * w.tpb_cols;
-  int64_t ntiles = (w.n + RPT * PDHG_BLOCK - 1) / (RPT * PDHG_BLOCK);
-  int64_t t1 = t0 + w.tpb_cols < ntiles ? t0 + w.tpb_cols : ntiles;
+  const int tpb = w.tpb_cols, long_seg = w.long_seg, direct = w.direct;
+  int64_t t0 = (int64_t)(lb - w.n_long_cols) * tpb;
+  int64_t ntiles = (n + PDHG_BLOCK - 1) / PDHG_BLOCK;
+  int64_t t1 = t0 + tpb < ntiles ? t0 + tpb : ntiles;
+  const AS_C int32_t *cpc = cin(w.cp);
   for (int64_t t = t0; t < t1; t++) {
-    int64_t r0 = t * RPT * PDHG_BLOCK;
-    int rs[RPT], re[RPT];
-    bool mine[RPT];
-    T xj[RPT], cj[RPT], lj[RPT], uj[RPT], xsj[RPT], s[RPT];
-#pragma unroll
-    for (int q = 0; q < RPT; q++) {  // issue the columns' own loads before the SpMV phase
-      int64_t j = r0 + q * PDHG_BLOCK + threadIdx.x;
-      rs[q] = re[q] = 0;
-      xj[q] = cj[q] = lj[q] = uj[q] = xsj[q] = 0;
-      if (j < w.n) {
-        rs[q] = w.cp[j];
-        re[q] = w.cp[j + 1];
-        xj[q] = x[j];
-        cj[q] = ld_stream(w.c + j);
-        lj[q] = ld_stream(w.l + j);
-        uj[q] = ld_stream(w.u + j);
-        if (fold_read) xsj[q] = w.XS[j];
-      }
-      mine[q] = j < w.n && (re[q] - rs[q] <= w.long_seg);
+    int64_t r0 = t * PDHG_BLOCK;
+    int64_t rend = r0 + PDHG_BLOCK < n ? r0 + PDHG_BLOCK : n;
+    int64_t j = r0 + threadIdx.x;
+    // the column's own loads go out with the tile bounds, before the SpMV
+    int base = cpc[r0], top = cpc[rend];
+    T xj = 0, cj = 0, lj = 0, uj = 0, xsj = 0;
+    if (j < n) {
+      xj = x[j];
+      cj = ld_stream(c + j);
+      lj = ld_stream(l + j);
+      uj = ld_stream(u + j);
+      if (fold_read) xsj = xs[j];
     }
-    tile_rowdot<T, RPT>(w.cp, w.ri, w.vt, y, w.n, r0, rs, re, mine, lds, s, w.direct);
-#pragma unroll
-    for (int q = 0; q < RPT; q++) {
-      int64_t j = r0 + q * PDHG_BLOCK + threadIdx.x;
-      bool in = false;
-      if (mine[q])
-        in = primal_finish(w, j, s[q], tau, xj[q], cj[q], lj[q], uj[q], xsj[q], xn, pend, fresh,
-                           d2[0]);
-      if (w.mask_x)
-        record_mask(w.mask_x + (st->k - w.mask_k0) * ((w.n + 63) >> 6), j & ~(int64_t)63, in);
-    }
+    bool mine;
+    T s = tile_rowdot<T>(cp, ri, vt, y, j, j < n, base, top, long_seg, lds, direct, mine);
+    bool in = false;
+    if (mine) in = primal_finish<T>(j, s, tau, xj, cj, lj, uj, xsj, xn, xs, pend, fresh, d2[0]);
+    if (mask) record_mask(mask, j & ~(int64_t)63, in);
   }
   double out[1];
   block_reduce<1>(d2, 0u, out);
-  if (threadIdx.x == 0) w.part_dx2[lb] = out[0];
+  if (threadIdx.x == 0) gout(w.part_dx2)[lb] = out[0];
 }
 
-// Returns whether the row's dual is unprojected (equality row or value > 0).
+// Dual update of row i from s = (A x')_i; returns whether the dual is
+// unprojected (equality row or value > 0).
 template <typename T>
-__device__ inline bool dual_finish(const IterView<T> &w, int64_t i, T s, T sigma, int cur, T yi,
-                                   T axi, T bi, uint8_t ki, T ysi, double pend, int fresh,
-                                   double &dy2, double &inter) {
+__device__ __forceinline__ bool dual_finish(int64_t i, T s, T sigma, T yi, T axi, T bi, uint8_t ki,
+                                            T ysi, AS_G T *yn, AS_G T *axn, AS_G T *ys,
+                                            double pend, int fresh, double &dy2, double &inter) {
   T yv = yi + sigma * (bi - (s + s - axi));
   bool in = (ki == 0) || (yv > (T)0);
   if (ki == 1 && yv < (T)0) yv = (T)0;
-  w.Y[cur ^ 1][i] = yv;
-  w.AX[cur ^ 1][i] = s;
+  yn[i] = yv;
+  axn[i] = s;
   double dy = (double)yv - (double)yi;
   dy2 += dy * dy;
   inter += dy * ((double)s - (double)axi);
-  if (pend > 0.0) w.YS[i] = (fresh ? (T)0 : ysi) + (T)pend * yi;
+  if (pend > 0.0) ys[i] = (fresh ? (T)0 : ysi) + (T)pend * yi;
   return in;
 }
 
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
-  constexpr int RPT = Rpt<T>::value;
-  __shared__ T lds[RPT * TILE_CAP_PER_ROWS];
+  __shared__ T lds[TILE_CAP + PDHG_BLOCK];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int inst = find_inst(g.p_dual, g.ninst, b);
-  const int lb = b - g.p_dual[inst];
-  const IterView<T> &w = I[inst].w;
-  const CtlState *st = I[inst].st;
+  const int inst = find_inst_u(g.p_dual, g.ninst, b);
+  const int lb = b - cin(g.p_dual)[inst];
+  const AS_C IterView<T> &w = cin(I)[inst].w;
+  const AS_C CtlState *st = cin(cin(I)[inst].st);
   const int cur = st->cur;
   const T sigma = (T)(st->eta * st->omega);
   const double pend = st->pending;
   const int fresh = st->fresh;
   const bool fold_read = pend > 0.0 && !fresh;
-  const T *__restrict__ xn = w.X[cur ^ 1];
-  const T *__restrict__ y = w.Y[cur];
-  const T *__restrict__ ax = w.AX[cur];
+  const int64_t m = w.m;
+  const AS_G int32_t *rp = gin(w.rp), *ci = gin(w.ci);
+  const AS_G T *v = gin(w.v), *bb = gin(w.b);
+  const AS_G uint8_t *kind = gin(w.kind);
+  const AS_G T *xn = gin((const T *)w.X[cur ^ 1]);
+  const AS_G T *y = gin((const T *)w.Y[cur]), *ax = gin((const T *)w.AX[cur]);
+  AS_G T *yn = gout(w.Y[cur ^ 1]), *axn = gout(w.AX[cur ^ 1]), *ys = gout(w.YS);
+  uint64_t *mask = w.mask_y ? w.mask_y + (st->k - w.mask_k0) * ((m + 63) >> 6) : nullptr;
   const int64_t G = w.grid_rows;
+  double acc[2] = {0.0, 0.0};
   if (lb < w.n_long_rows) {
-    int64_t i = w.long_rows[lb];
-    int s = w.rp[i], e = w.rp[i + 1];
-    double acc[1] = {0.0};
-    for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)(w.v[k] * xn[w.ci[k]]);
-    double tot[1];
-    block_reduce<1>(acc, 0u, tot);
+    int64_t i = gin(w.long_rows)[lb];
+    const AS_C int32_t *rpc = cin(w.rp);
+    double t = long_rowdot<T>(ci, v, xn, rpc[i], rpc[i + 1]);
     if (threadIdx.x == 0) {
-      double dy2 = 0.0, inter = 0.0;
-      bool in = dual_finish(w, i, (T)tot[0], sigma, cur, y[i], ax[i], w.b[i], w.kind[i],
-                            fold_read ? w.YS[i] : (T)0, pend, fresh, dy2, inter);
-      w.part_dy[lb] = dy2;
-      w.part_dy[G + lb] = inter;
-      if (w.mask_y && in)
-        record_bit(w.mask_y + (st->k - w.mask_k0) * ((w.m + 63) >> 6), i);
+      bool in = dual_finish<T>(i, (T)t, sigma, y[i], ax[i], bb[i], kind[i],
+                               fold_read ? ys[i] : (T)0, yn, axn, ys, pend, fresh, acc[0], acc[1]);
+      gout(w.part_dy)[lb] = acc[0];
+      gout(w.part_dy)[G + lb] = acc[1];
+      if (mask && in) record_bit(mask, i);
     }
     return;
   }
-  double v[2] = {0.0, 0.0};
-  int64_t t0 = (int64_t)(lb - w.n_long_rows) * w.tpb_rows;
-  int64_t ntiles = (w.m + RPT * PDHG_BLOCK - 1) / (RPT * PDHG_BLOCK);
-  int64_t t1 = t0 + w.tpb_rows < ntiles ? t0 + w.tpb_rows : ntiles;
+  const int tpb = w.tpb_rows, long_seg = w.long_seg, direct = w.direct;
+  int64_t t0 = (int64_t)(lb - w.n_long_rows) * tpb;
+  int64_t ntiles = (m + PDHG_BLOCK - 1) / PDHG_BLOCK;
+  int64_t t1 = t0 + tpb < ntiles ? t0 + tpb : ntiles;
+  const AS_C int32_t *rpc = cin(w.rp);
   for (int64_t t = t0; t < t1; t++) {
-    int64_t r0 = t * RPT * PDHG_BLOCK;
-    int rs[RPT], re[RPT];
-    bool mine[RPT];
-    T yi[RPT], axi[RPT], bi[RPT], ysi[RPT], s[RPT];
-    uint8_t ki[RPT];
-#pragma unroll
-    for (int q = 0; q < RPT; q++) {  // issue the rows' own loads before the SpMV phase
-      int64_t i = r0 + q * PDHG_BLOCK + threadIdx.x;
-      rs[q] = re[q] = 0;
-      yi[q] = axi[q] = bi[q] = ysi[q] = 0;
-      ki[q] = 0;
-      if (i < w.m) {
-        rs[q] = w.rp[i];
-        re[q] = w.rp[i + 1];
-        yi[q] = y[i];
-        axi[q] = ax[i];
-        bi[q] = ld_stream(w.b + i);
-        ki[q] = w.kind[i];
-        if (fold_read) ysi[q] = w.YS[i];
-      }
-      mine[q] = i < w.m && (re[q] - rs[q] <= w.long_seg);
+    int64_t r0 = t * PDHG_BLOCK;
+    int64_t rend = r0 + PDHG_BLOCK < m ? r0 + PDHG_BLOCK : m;
+    int64_t i = r0 + threadIdx.x;
+    int base = rpc[r0], top = rpc[rend];
+    T yi = 0, axi = 0, bi = 0, ysi = 0;
+    uint8_t ki = 0;
+    if (i < m) {
+      yi = y[i];
+      axi = ax[i];
+      bi = ld_stream(bb + i);
+      ki = kind[i];
+      if (fold_read) ysi = ys[i];
     }
-    tile_rowdot<T, RPT>(w.rp, w.ci, w.v, xn, w.m, r0, rs, re, mine, lds, s, w.direct);
-#pragma unroll
-    for (int q = 0; q < RPT; q++) {
-      int64_t i = r0 + q * PDHG_BLOCK + threadIdx.x;
-      bool in = false;
-      if (mine[q])
-        in = dual_finish(w, i, s[q], sigma, cur, yi[q], axi[q], bi[q], ki[q], ysi[q], pend, fresh,
-                         v[0], v[1]);
-      if (w.mask_y)
-        record_mask(w.mask_y + (st->k - w.mask_k0) * ((w.m + 63) >> 6), i & ~(int64_t)63, in);
-    }
+    bool mine;
+    T s = tile_rowdot<T>(rp, ci, v, xn, i, i < m, base, top, long_seg, lds, direct, mine);
+    bool in = false;
+    if (mine)
+      in = dual_finish<T>(i, s, sigma, yi, axi, bi, ki, ysi, yn, axn, ys, pend, fresh, acc[0],
+                          acc[1]);
+    if (mask) record_mask(mask, i & ~(int64_t)63, in);
   }
   double out[2];
-  block_reduce<2>(v, 0u, out);
+  block_reduce<2>(acc, 0u, out);
   if (threadIdx.x == 0) {
-    w.part_dy[lb] = out[0];
-    w.part_dy[G + lb] = out[1];
+    gout(w.part_dy)[lb] = out[0];
+    gout(w.part_dy)[G + lb] = out[1];
   }
 }
 
