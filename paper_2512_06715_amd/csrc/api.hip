@@ -181,7 +181,7 @@ void partition(pdhg_handle *h) {
 
 void set_grids(pdhg_handle *h) {
   for (int q = 0; q < 2; q++) {
-    int64_t tile = PDHG_BLOCK;
+    int64_t tile = PDHG_TILE;
     int tr = (int)((h->m + tile - 1) / tile), tc = (int)((h->n + tile - 1) / tile);
     h->grid_rows[q] = h->n_long_rows + (tr + h->tpb_rows - 1) / h->tpb_rows;
     h->grid_cols[q] = h->n_long_cols + (tc + h->tpb_cols - 1) / h->tpb_cols;
@@ -194,15 +194,15 @@ size_t layout(pdhg_handle *h, void *base) {
   bool mixed = h->o.precision == PDHG_MIXED;
   partition(h);
   h->rp = cv.take<int32_t>(m + 1);
-  h->ci = cv.take<int32_t>(nnz);
+  h->ci = cv.take<int32_t>(std::max<int64_t>(nnz, 1));  // the attempt kernels may read entry 0 of an empty matrix
   h->cp = cv.take<int32_t>(n + 1);
-  h->ri = cv.take<int32_t>(nnz);
+  h->ri = cv.take<int32_t>(std::max<int64_t>(nnz, 1));
   h->long_rows = cv.take<int32_t>(m);
   h->long_cols = cv.take<int32_t>(n);
   h->scan_tmp = cv.take<int32_t>(scan_tmp_ints(n + 1));
   h->tmp_next = cv.take<int32_t>(n + 1);
-  h->v = cv.take<double>(nnz);
-  h->vt = cv.take<double>(nnz);
+  h->v = cv.take<double>(std::max<int64_t>(nnz, 1));
+  h->vt = cv.take<double>(std::max<int64_t>(nnz, 1));
   h->b0 = cv.take<double>(m);
   h->b = cv.take<double>(m);
   h->Dr = cv.take<double>(m);
@@ -216,8 +216,8 @@ size_t layout(pdhg_handle *h, void *base) {
   h->kind = cv.take<uint8_t>(m);
   h->vk = cv.take<uint8_t>(n);
   if (mixed) {
-    h->vf = cv.take<float>(nnz);
-    h->vtf = cv.take<float>(nnz);
+    h->vf = cv.take<float>(std::max<int64_t>(nnz, 1));
+    h->vtf = cv.take<float>(std::max<int64_t>(nnz, 1));
     h->bf = cv.take<float>(m);
     h->cf = cv.take<float>(n);
     h->lf = cv.take<float>(n);

@@ -4,6 +4,10 @@
 #include <stdint.h>
 
 #define PDHG_BLOCK 256
+// rows of one tile of the attempt kernels (and their workgroup size)
+#ifndef PDHG_TILE
+#define PDHG_TILE 256
+#endif
 // default length above which a row / column is handled by a workgroup
 #define PDHG_LONG_SEG 64
 // tile groups per launch above which a workgroup takes several tiles

@@ -20,6 +20,28 @@
 
 namespace {
 
+// Address spaces.  Pointers read out of the instance tables are generic; the
+// attempt kernels cast them so that the compiler emits global (vector) and
+// scalar loads instead of flat ones, whose shared wait counter serialises
+// the otherwise independent load streams.  Instance tables, control states
+// and CSR pointers are not written while an attempt kernel runs, so their
+// uniform reads may go through the scalar path.
+#define AS_G __attribute__((address_space(1)))
+#define AS_C __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const AS_G T *gin(const T *p) {
+  return (const AS_G T *)p;
+}
+template <typename T>
+__device__ __forceinline__ AS_G T *gout(T *p) {
+  return (AS_G T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const AS_C T *cin(const T *p) {
+  return (const AS_C T *)p;
+}
+
+
 inline unsigned grid_of(int n) { return (unsigned)(n > 0 ? n : 1); }
 inline unsigned grid_for(int64_t n) {
   int64_t g = (n + PDHG_BLOCK - 1) / PDHG_BLOCK;
@@ -88,22 +110,51 @@ __device__ inline void block_reduce(double (&v)[NQ], unsigned maxmask, double *o
 }
 
 // Sum (or max) of `cnt` partials with stride `stride`, one workgroup of BS
-// threads, fixed order.
+// threads, fixed order: lane t combines partials t, t + BS, t + 2 BS, ... in
+// that order, then the block tree combines the lanes.  Loads go out CH per
+// lane at a time before any of them is used.  When `st` is given, its words
+// are fetched together with the first partials and left in `st_lds` (visible
+// to every lane on return).
 #define CTL_BLOCK 1024
+static_assert(sizeof(CtlState) % 8 == 0 && sizeof(CtlState) / 8 <= CTL_BLOCK, "state words");
+// Whole-state write-back (8-byte words) from one lane.
+__device__ inline void store_state(CtlState *dst, const CtlState &s) {
+  AS_G unsigned long long *d = gout((unsigned long long *)dst);
+  const unsigned long long *w = (const unsigned long long *)&s;
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(CtlState) / 8); q++) d[q] = w[q];
+}
+
 template <int NQ, int BS = CTL_BLOCK>
 __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t stride,
-                                       unsigned maxmask, double *out) {
+                                       unsigned maxmask, double *out,
+                                       const CtlState *st = nullptr, CtlState *st_lds = nullptr) {
+  constexpr int CH = NQ >= 8 ? 2 : 16 / NQ;
+  constexpr int SW = sizeof(CtlState) / 8;
+  const AS_G double *pg = gin(p);
+  unsigned long long sw = 0;
   double v[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; q++) v[q] = 0.0;
-#pragma unroll 8
-  for (int64_t b = threadIdx.x; b < cnt; b += BS) {
+  for (int64_t b0 = 0; b0 < cnt; b0 += CH * BS) {
+    double a[CH][NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; q++) {
-      double a = p[q * stride + b];
-      v[q] = ((maxmask >> q) & 1) ? fmax(v[q], a) : v[q] + a;
+    for (int c = 0; c < CH; c++) {
+      int64_t b = b0 + c * BS + threadIdx.x;
+      int64_t bc = b < cnt ? b : cnt - 1;
+#pragma unroll
+      for (int q = 0; q < NQ; q++) a[c][q] = pg[q * stride + bc];
+    }
+    if (b0 == 0 && st && threadIdx.x < SW) sw = gin((const unsigned long long *)st)[threadIdx.x];
+#pragma unroll
+    for (int c = 0; c < CH; c++) {
+      bool ok = b0 + c * BS + threadIdx.x < cnt;
+#pragma unroll
+      for (int q = 0; q < NQ; q++)
+        v[q] = ((maxmask >> q) & 1) ? fmax(v[q], ok ? a[c][q] : v[q]) : v[q] + (ok ? a[c][q] : 0.0);
     }
   }
+  if (st && threadIdx.x < SW) ((unsigned long long *)st_lds)[threadIdx.x] = sw;
   block_reduce<NQ, BS>(v, maxmask, out);
 }
 
@@ -121,27 +172,6 @@ __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t str
 // (the first blocks of the instance).  Each workgroup covers `tpb`
 // consecutive tiles and writes one partial per reduced quantity.
 
-// Address spaces.  Pointers read out of the instance tables are generic; the
-// attempt kernels cast them so that the compiler emits global (vector) and
-// scalar loads instead of flat ones, whose shared wait counter serialises
-// the otherwise independent load streams.  Instance tables, control states
-// and CSR pointers are not written while an attempt kernel runs, so their
-// uniform reads may go through the scalar path.
-#define AS_G __attribute__((address_space(1)))
-#define AS_C __attribute__((address_space(4)))
-template <typename T>
-__device__ __forceinline__ const AS_G T *gin(const T *p) {
-  return (const AS_G T *)p;
-}
-template <typename T>
-__device__ __forceinline__ AS_G T *gout(T *p) {
-  return (AS_G T *)p;
-}
-template <typename T>
-__device__ __forceinline__ const AS_C T *cin(const T *p) {
-  return (const AS_C T *)p;
-}
-
 // Instance owning logical block b (uniform): the largest i with pre[i] <= b.
 __device__ inline int find_inst_u(const int32_t *pre, int ninst, int b) {
   const AS_C int32_t *p = cin(pre);
@@ -156,7 +186,7 @@ __device__ inline int find_inst_u(const int32_t *pre, int ninst, int b) {
   return lo;
 }
 
-#define TILE_CAP 2048  // nonzeros of a tile staged in LDS
+#define TILE_CAP (8 * PDHG_TILE)  // nonzeros of a tile staged in LDS
 #define TILE_U 4       // nonzeros per lane loaded before their gathers
 
 // Streams read exactly once per launch bypass the cache hierarchy's reuse
@@ -166,13 +196,19 @@ __device__ __forceinline__ T ld_stream(const AS_G T *p) {
   return __builtin_nontemporal_load(p);
 }
 
+// Iterate stores of the attempt kernels.
+template <typename T>
+__device__ __forceinline__ void st_out(AS_G T *p, T v) {
+  *p = v;
+}
+
 // Products are rounded on their own (never fused into the sum), so the
 // LDS-staged and the per-row paths give bit-identical row sums.
 __device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
 __device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
 
 // Dot product s = sum_k v[k] x[idx[k]] of this lane's row i (rows r0 + lane of
-// a 256-row tile whose nonzeros are [base, top)), summed in CSR order.  The
+// a PDHG_TILE-row tile whose nonzeros are [base, top)), summed in CSR order.  The
 // row's bounds are loaded here, after the tile's index/value stream has been
 // issued, so the gathers wait only on that stream.  `mine` returns whether
 // the row is valid and short enough to be this tile's.  Every lane of the
@@ -186,12 +222,12 @@ __device__ __forceinline__ T tile_rowdot(const AS_G int32_t *ptr, const AS_G int
   T s = 0;
   int rs = 0, re = 0;
   if (!direct && cnt <= TILE_CAP) {
-    for (int k0 = 0; k0 < cnt; k0 += TILE_U * PDHG_BLOCK) {
+    for (int k0 = 0; k0 < cnt; k0 += TILE_U * PDHG_TILE) {
       int id[TILE_U];
       T vv[TILE_U];
 #pragma unroll
       for (int q = 0; q < TILE_U; q++) {
-        int k = k0 + q * PDHG_BLOCK + (int)threadIdx.x;
+        int k = k0 + q * PDHG_TILE + (int)threadIdx.x;
         int kc = base + (k < cnt ? k : cnt - 1);
         id[q] = ld_stream(idx + kc);
         vv[q] = ld_stream(v + kc);
@@ -202,7 +238,7 @@ __device__ __forceinline__ T tile_rowdot(const AS_G int32_t *ptr, const AS_G int
       }
 #pragma unroll
       for (int q = 0; q < TILE_U; q++) {
-        int k = k0 + q * PDHG_BLOCK + (int)threadIdx.x;
+        int k = k0 + q * PDHG_TILE + (int)threadIdx.x;
         // lanes past the tile write a slot of their own past the staged range
         lds[k < cnt ? k : TILE_CAP + (int)threadIdx.x] = mul_rn(vv[q], x[id[q]]);
       }
@@ -248,9 +284,9 @@ template <typename T>
 __device__ __forceinline__ double long_rowdot(const AS_G int32_t *idx, const AS_G T *v,
                                               const AS_G T *x, int s, int e) {
   double acc[1] = {0.0};
-  for (int k = s + threadIdx.x; k < e; k += PDHG_BLOCK) acc[0] += (double)mul_rn(v[k], x[idx[k]]);
+  for (int k = s + threadIdx.x; k < e; k += PDHG_TILE) acc[0] += (double)mul_rn(v[k], x[idx[k]]);
   double tot[1];
-  block_reduce<1>(acc, 0u, tot);
+  block_reduce<1, PDHG_TILE>(acc, 0u, tot);
   return tot[0];
 }
 
@@ -275,16 +311,16 @@ __device__ __forceinline__ bool primal_finish(int64_t j, T t, T tau, T xj, T cj,
                                               int fresh, double &d2) {
   T xt = xj - tau * (cj - t);
   T xv = clamp_box<T>(xt, lj, uj);
-  xn[j] = xv;
+  st_out(xn + j, xv);
   double d = (double)xv - (double)xj;
   d2 += d * d;
-  if (pend > 0.0) xs[j] = (fresh ? (T)0 : xsj) + (T)pend * xj;
+  if (pend > 0.0) st_out(xs + j, (fresh ? (T)0 : xsj) + (T)pend * xj);
   return xt > lj && xt < uj;
 }
 
 template <typename T>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
-  __shared__ T lds[TILE_CAP + PDHG_BLOCK];
+__global__ __launch_bounds__(PDHG_TILE) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = find_inst_u(g.p_primal, g.ninst, b);
   const int lb = b - cin(g.p_primal)[inst];
@@ -318,12 +354,12 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict
   }
   const int tpb = w.tpb_cols, long_seg = w.long_seg, direct = w.direct;
   int64_t t0 = (int64_t)(lb - w.n_long_cols) * tpb;
-  int64_t ntiles = (n + PDHG_BLOCK - 1) / PDHG_BLOCK;
+  int64_t ntiles = (n + PDHG_TILE - 1) / PDHG_TILE;
   int64_t t1 = t0 + tpb < ntiles ? t0 + tpb : ntiles;
   const AS_C int32_t *cpc = cin(w.cp);
   for (int64_t t = t0; t < t1; t++) {
-    int64_t r0 = t * PDHG_BLOCK;
-    int64_t rend = r0 + PDHG_BLOCK < n ? r0 + PDHG_BLOCK : n;
+    int64_t r0 = t * PDHG_TILE;
+    int64_t rend = r0 + PDHG_TILE < n ? r0 + PDHG_TILE : n;
     int64_t j = r0 + threadIdx.x;
     // the column's own loads go out with the tile bounds, before the SpMV
     int base = cpc[r0], top = cpc[rend];
@@ -342,7 +378,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_primal(const Inst<T> *__restrict
     if (mask) record_mask(mask, j & ~(int64_t)63, in);
   }
   double out[1];
-  block_reduce<1>(d2, 0u, out);
+  block_reduce<1, PDHG_TILE>(d2, 0u, out);
   if (threadIdx.x == 0) gout(w.part_dx2)[lb] = out[0];
 }
 
@@ -355,18 +391,18 @@ __device__ __forceinline__ bool dual_finish(int64_t i, T s, T sigma, T yi, T axi
   T yv = yi + sigma * (bi - (s + s - axi));
   bool in = (ki == 0) || (yv > (T)0);
   if (ki == 1 && yv < (T)0) yv = (T)0;
-  yn[i] = yv;
-  axn[i] = s;
+  st_out(yn + i, yv);
+  st_out(axn + i, s);
   double dy = (double)yv - (double)yi;
   dy2 += dy * dy;
   inter += dy * ((double)s - (double)axi);
-  if (pend > 0.0) ys[i] = (fresh ? (T)0 : ysi) + (T)pend * yi;
+  if (pend > 0.0) st_out(ys + i, (fresh ? (T)0 : ysi) + (T)pend * yi);
   return in;
 }
 
 template <typename T>
-__global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
-  __shared__ T lds[TILE_CAP + PDHG_BLOCK];
+__global__ __launch_bounds__(PDHG_TILE) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = find_inst_u(g.p_dual, g.ninst, b);
   const int lb = b - cin(g.p_dual)[inst];
@@ -402,12 +438,12 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__
   }
   const int tpb = w.tpb_rows, long_seg = w.long_seg, direct = w.direct;
   int64_t t0 = (int64_t)(lb - w.n_long_rows) * tpb;
-  int64_t ntiles = (m + PDHG_BLOCK - 1) / PDHG_BLOCK;
+  int64_t ntiles = (m + PDHG_TILE - 1) / PDHG_TILE;
   int64_t t1 = t0 + tpb < ntiles ? t0 + tpb : ntiles;
   const AS_C int32_t *rpc = cin(w.rp);
   for (int64_t t = t0; t < t1; t++) {
-    int64_t r0 = t * PDHG_BLOCK;
-    int64_t rend = r0 + PDHG_BLOCK < m ? r0 + PDHG_BLOCK : m;
+    int64_t r0 = t * PDHG_TILE;
+    int64_t rend = r0 + PDHG_TILE < m ? r0 + PDHG_TILE : m;
     int64_t i = r0 + threadIdx.x;
     int base = rpc[r0], top = rpc[rend];
     T yi = 0, axi = 0, bi = 0, ysi = 0;
@@ -428,7 +464,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__
     if (mask) record_mask(mask, i & ~(int64_t)63, in);
   }
   double out[2];
-  block_reduce<2>(acc, 0u, out);
+  block_reduce<2, PDHG_TILE>(acc, 0u, out);
   if (threadIdx.x == 0) {
     gout(w.part_dy)[lb] = out[0];
     gout(w.part_dy)[G + lb] = out[1];
@@ -442,19 +478,21 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_dual(const Inst<T> *__restrict__
 template <typename T>
 __global__ __launch_bounds__(CTL_BLOCK) void k_control(const Inst<T> *__restrict__ I) {
   __shared__ double r[3];
-  const IterView<T> &w = I[blockIdx.x].w;
-  CtlState *st = I[blockIdx.x].st;
-  reduce_partials<1>(w.part_dx2, w.grid_cols, 0, 0u, &r[0]);
-  reduce_partials<2>(w.part_dy, w.grid_rows, w.grid_rows, 0u, &r[1]);
+  __shared__ CtlState sl;
+  const AS_C Inst<T> &in = cin(I)[blockIdx.x];
+  CtlState *gst = in.st;
+  reduce_partials<1>(in.w.part_dx2, in.w.grid_cols, 0, 0u, &r[0], gst, &sl);
+  reduce_partials<2>(in.w.part_dy, in.w.grid_rows, in.w.grid_rows, 0u, &r[1]);
   if (threadIdx.x != 0) return;
+  CtlState st = sl;
   double dx2 = r[0], dy2 = r[1], inter = r[2];
-  double eta = st->eta, omega = st->omega;
-  long long k = st->k + 1;
-  if (st->pending > 0.0) st->fresh = 0;  // this attempt's kernels folded it
-  st->pending = 0.0;
+  double eta = st.eta, omega = st.omega;
+  long long k = st.k + 1;
+  if (st.pending > 0.0) st.fresh = 0;  // this attempt's kernels folded it
+  st.pending = 0.0;
   int accept = 1;
   double eta_new = eta;
-  if (w.adaptive) {
+  if (in.w.adaptive) {
     double nz = omega * dx2 + dy2 / omega;
     double ebar = (inter != 0.0) ? nz / (2.0 * fabs(inter)) : INFINITY;
     double kk = (double)(k + 1);
@@ -464,16 +502,17 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_control(const Inst<T> *__restrict
     eta_new = e1 < e2 ? e1 : e2;
   }
   if (accept) {
-    st->cur ^= 1;
-    st->pending = eta;
-    st->wsum += eta;
-    st->accepted += 1;
+    st.cur ^= 1;
+    st.pending = eta;
+    st.wsum += eta;
+    st.accepted += 1;
   }
-  st->eta = eta_new;
-  st->k = k;
-  st->dx2 = dx2;
-  st->dy2 = dy2;
-  st->inter = inter;
+  st.eta = eta_new;
+  st.k = k;
+  st.dx2 = dx2;
+  st.dy2 = dy2;
+  st.inter = inter;
+  store_state(gst, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -719,11 +758,16 @@ template <typename T>
 __global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const Inst<T> *__restrict__ I,
                                                             double tol, long long max_iter) {
   __shared__ double rq[EV_ROWQ], cq[EV_COLQ];
-  const EvalView<T> &e = I[blockIdx.x].e;
-  CtlState *st = I[blockIdx.x].st;
-  reduce_partials<EV_ROWQ>(e.part_rows, e.nblk_rows, e.nblk_rows, (1u << 2) | (1u << 7), rq);
+  __shared__ CtlState sl;
+  const AS_C Inst<T> &in = cin(I)[blockIdx.x];
+  const AS_C EvalView<T> &e = in.e;
+  CtlState *gst = in.st;
+  reduce_partials<EV_ROWQ>(e.part_rows, e.nblk_rows, e.nblk_rows, (1u << 2) | (1u << 7), rq, gst,
+                           &sl);
   reduce_partials<EV_COLQ>(e.part_cols, e.nblk_cols, e.nblk_cols, (1u << 2) | (1u << 8), cq);
   if (threadIdx.x != 0) return;
+  CtlState stv = sl;
+  CtlState *st = &stv;
   bool avg = e.use_average && st->wsum > 0.0;
   double omega = st->omega;
   PointKKT pc = point_kkt(rq, cq, omega, st->nb, st->nc);
@@ -785,6 +829,7 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const Inst<T> *__res
   st->rel_d = rep->rel_d;
   st->rel_gap = rep->rel_g;
   st->rel_kkt = rep->rel_kkt;
+  store_state(gst, stv);
 }
 
 template <typename T>
@@ -1147,12 +1192,12 @@ __global__ void k_spmv_plain(const int32_t *__restrict__ rp, const int32_t *__re
 
 template <typename T>
 void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s) {
-  k_primal<T><<<grid_of(g.n_primal), PDHG_BLOCK, 0, s>>>(I, g);
+  k_primal<T><<<grid_of(g.n_primal), PDHG_TILE, 0, s>>>(I, g);
 }
 
 template <typename T>
 void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s) {
-  k_dual<T><<<grid_of(g.n_dual), PDHG_BLOCK, 0, s>>>(I, g);
+  k_dual<T><<<grid_of(g.n_dual), PDHG_TILE, 0, s>>>(I, g);
 }
 
 template <typename T>
