@@ -103,6 +103,10 @@ typedef struct {
                              and keeps the fastest; cached per matrix in the process */
   int spmv_direct;        /* partition without autotune: 1 = per-row loops, 0 = LDS tiles */
   int long_seg;           /* rows/columns longer than this get a workgroup; 0 = 64 */
+  int reorder;            /* 1 (default): the solver works on P A Q' with P, Q a reverse
+                             Cuthill-McKee order of A's row/column graph (better locality
+                             of the SpMV gathers); every argument and result stays in the
+                             caller's order.  0: the caller's order */
 } pdhg_opts;
 
 typedef struct {
@@ -209,6 +213,14 @@ int pdhg_export_setup(pdhg_handle *h, uint8_t *var_kind, int32_t *colptr,
  * (transpose = 1, x[m], out[n]) with the solver's FP64 SpMV kernels; host
  * memory. */
 int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out);
+
+/* The locality ordering pdhg_setup applies when opts.reorder = 1, for a
+ * canonical CSR structure in host memory (host code only, no GPU needed):
+ * row_order[m] receives the original row of each internal row, col_order[n]
+ * the original column of each internal column.  Returns PDHG_ERR_CSR for a
+ * structure that is not canonical CSR. */
+int pdhg_locality_order(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                        int32_t *row_order, int32_t *col_order);
 
 /* The SpMV partition in use: out[0] tiles per workgroup, out[1] 1 for per-row
  * loops (0: LDS-staged tiles), out[2] long-segment threshold, out[3] number

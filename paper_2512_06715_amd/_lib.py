@@ -34,7 +34,7 @@ class PdhgOpts(ctypes.Structure):
                 ("unroll_iters", c_i64), ("checkpoint_every", c_i64), ("use_graph", c_int),
                 ("verbose", c_int), ("polish_tol", c_dbl), ("pw_update", c_int),
                 ("pw_theta", c_dbl), ("tiles_per_block", c_int), ("autotune", c_int),
-                ("spmv_direct", c_int), ("long_seg", c_int)]
+                ("spmv_direct", c_int), ("long_seg", c_int), ("reorder", c_int)]
 
 
 class PdhgInfo(ctypes.Structure):
@@ -77,6 +77,7 @@ SIGNATURES = {
     "pdhg_spmv": (c_int, [vp, c_int, vp, vp]),
     "pdhg_time_kernels": (c_int, [vp, c_int, ctypes.POINTER(c_dbl)]),
     "pdhg_get_partition": (c_int, [vp, ctypes.POINTER(c_int)]),
+    "pdhg_locality_order": (c_int, [c_i64, c_i64, vp, vp, vp, vp]),
 }
 
 _lib = None

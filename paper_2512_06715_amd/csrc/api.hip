@@ -133,6 +133,11 @@ struct pdhg_handle {
   float *vf = nullptr, *vtf = nullptr, *bf = nullptr, *cf = nullptr, *lf = nullptr,
         *uf = nullptr;
   uint8_t *kind, *vk;
+  // locality ordering: caller's index of each internal row / column and the
+  // internal index of each caller column (all null without reordering)
+  int32_t *rperm = nullptr, *cperm = nullptr, *cinv = nullptr;
+  int32_t *perm_buf = nullptr;
+  std::vector<int32_t> h_rperm, h_cperm;  // host copies
   double *scratch;
   int nscratch = 0;
   int *err;
@@ -215,6 +220,7 @@ size_t layout(pdhg_handle *h, void *base) {
   h->Dc = cv.take<double>(n);
   h->kind = cv.take<uint8_t>(m);
   h->vk = cv.take<uint8_t>(n);
+  h->perm_buf = h->o.reorder ? cv.take<int32_t>(m + 2 * n) : nullptr;
   if (mixed) {
     h->vf = cv.take<float>(std::max<int64_t>(nnz, 1));
     h->vtf = cv.take<float>(std::max<int64_t>(nnz, 1));
@@ -262,6 +268,7 @@ int check_opts(const pdhg_opts *o) {
   if (!(o->pw_theta >= 0.0 && o->pw_theta <= 1.0)) return fail(PDHG_ERR_ARG, "pw_theta must be in [0, 1]");
   if (o->tiles_per_block < 0) return fail(PDHG_ERR_ARG, "tiles_per_block must be >= 0");
   if (o->long_seg < 0) return fail(PDHG_ERR_ARG, "long_seg must be >= 0");
+  if (o->reorder != 0 && o->reorder != 1) return fail(PDHG_ERR_ARG, "reorder must be 0 or 1");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -335,6 +342,90 @@ int validate_host(const pdhg_lp *lp) {
     int r_ = (call);   \
     if (r_) return r_; \
   } while (0)
+
+// A caller-order vector src (host or device memory) into internal order:
+// dst[i] = src[perm[i]] (device), staged through `staging` (cnt doubles) when
+// src is host memory.  perm null: a plain copy.
+int to_internal(pdhg_handle *h, double *dst, const double *src, int src_on_device,
+                const int32_t *perm, int64_t cnt, double *staging) {
+  hipMemcpyKind kd = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (!perm) {
+    HC(hipMemcpyAsync(dst, src, sizeof(double) * cnt, kd, h->hs));
+    return PDHG_OK;
+  }
+  const double *from = src;
+  if (!src_on_device) {
+    HC(hipMemcpyAsync(staging, src, sizeof(double) * cnt, hipMemcpyHostToDevice, h->hs));
+    from = staging;
+  }
+  launch_gather_f64(dst, from, perm, cnt, h->hs);
+  HK();
+  return PDHG_OK;
+}
+
+// An internal-order device vector into the caller's order: dst[perm[i]] = src[i].
+int to_caller(pdhg_handle *h, double *dst, const double *src, const int32_t *perm, int64_t cnt) {
+  if (perm)
+    launch_scatter_f64(dst, src, perm, cnt, h->hs);
+  else
+    launch_copy_f64(dst, src, cnt, h->hs);
+  HK();
+  return PDHG_OK;
+}
+
+// Relabel the scaled problem by the locality ordering: the CSR of P A Q' is
+// built on the host from the scaled matrix, its transpose on the device by
+// the setup kernel, and every problem vector is gathered into the new order.
+int reorder_problem(pdhg_handle *h) {
+  const int64_t m = h->m, n = h->n, nnz = h->nnz;
+  std::vector<int32_t> rp(m + 1), ci(std::max<int64_t>(nnz, 1));
+  std::vector<double> v(std::max<int64_t>(nnz, 1));
+  HC(hipMemcpyAsync(rp.data(), h->rp, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost, h->hs));
+  if (nnz) {
+    HC(hipMemcpyAsync(ci.data(), h->ci, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, h->hs));
+    HC(hipMemcpyAsync(v.data(), h->v, sizeof(double) * nnz, hipMemcpyDeviceToHost, h->hs));
+  }
+  HC(hipStreamSynchronize(h->hs));
+  std::vector<int32_t> cp, ri, ro, co, prp, pci;
+  std::vector<double> none, pv;
+  transpose_csr(m, n, rp.data(), ci.data(), nullptr, cp, ri, none);
+  rcm_order(m, n, rp.data(), ci.data(), cp.data(), ri.data(), ro, co);
+  std::vector<int32_t> cinv(n);
+  for (int64_t j = 0; j < n; j++) cinv[co[j]] = (int32_t)j;
+  permute_csr(m, rp.data(), ci.data(), v.data(), ro, cinv, prp, pci, pv);
+  h->rperm = h->perm_buf;
+  h->cperm = h->perm_buf + m;
+  h->cinv = h->perm_buf + m + n;
+  HC(hipMemcpyAsync(h->rperm, ro.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, h->hs));
+  HC(hipMemcpyAsync(h->cperm, co.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, h->hs));
+  HC(hipMemcpyAsync(h->cinv, cinv.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, h->hs));
+  HC(hipMemcpyAsync(h->rp, prp.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, h->hs));
+  if (nnz) {
+    HC(hipMemcpyAsync(h->ci, pci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, h->hs));
+    HC(hipMemcpyAsync(h->v, pv.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, h->hs));
+  }
+  launch_transpose(h->rp, h->ci, h->v, m, n, nnz, h->cp, h->ri, h->vt, h->tmp_next, h->scan_tmp,
+                   h->hs);
+  HK();
+  double *tr = h->it.YA, *tc = h->it.XA;  // free until the first solve
+  for (double *a : {h->b0, h->b, h->Dr}) {
+    launch_copy_f64(tr, a, m, h->hs);
+    launch_gather_f64(a, tr, h->rperm, m, h->hs);
+  }
+  for (double *a : {h->c0, h->l0, h->u0, h->c, h->l, h->u, h->Dc}) {
+    launch_copy_f64(tc, a, n, h->hs);
+    launch_gather_f64(a, tc, h->cperm, n, h->hs);
+  }
+  HC(hipMemcpyAsync(tr, h->kind, m, hipMemcpyDeviceToDevice, h->hs));
+  launch_gather_u8(h->kind, (const uint8_t *)tr, h->rperm, m, h->hs);
+  HC(hipMemcpyAsync(tc, h->vk, n, hipMemcpyDeviceToDevice, h->hs));
+  launch_gather_u8(h->vk, (const uint8_t *)tc, h->cperm, n, h->hs);
+  HK();
+  HC(hipStreamSynchronize(h->hs));  // the host arrays go out of scope
+  h->h_rperm = std::move(ro);
+  h->h_cperm = std::move(co);
+  return PDHG_OK;
+}
 
 // Rows and columns longer than the partition's threshold get a workgroup each.
 int build_long_lists(pdhg_handle *h) {
@@ -425,6 +516,8 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.u = d.u;
   e.Dr = h->Dr;
   e.Dc = h->Dc;
+  e.rperm = h->rperm;
+  e.cperm = h->cperm;
   e.XA = b.XA;
   e.YA = b.YA;
   e.AXA = b.AXA;
@@ -851,6 +944,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->autotune = 0;
   o->spmv_direct = 0;
   o->long_seg = 0;
+  o->reorder = 1;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -941,6 +1035,7 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
     launch_scale_vectors(h->b0, h->c0, h->l0, h->u0, h->Dr, h->Dc, m, n, h->b, h->c, h->l, h->u,
                          h->hs);
     HK();
+    if (h->o.reorder) RC(reorder_problem(h));
     // long rows and columns (handled by a workgroup each in the iteration)
     h->hrp.resize(m + 1);
     h->hcp.resize(n + 1);
@@ -1138,13 +1233,17 @@ int backward_unrolled(pdhg_handle *h, double gv, double *grad_b, double *grad_c)
     }
     HK();
   }
-  // back to the original space: dV/db = Dr b-bar, dV/dc = Dc c-bar
-  double *ob = h->on_device ? grad_b : h->it.AXA;
-  double *oc = h->on_device ? grad_c : h->it.ATYA;
-  launch_scale_vectors(h->BB, h->CB, h->CB, h->CB, h->Dr, h->Dc, m, n, ob, oc, h->H, h->XB,
+  // back to the original space: dV/db = Dr b-bar, dV/dc = Dc c-bar (internal
+  // order in AXA / ATYA), then into the caller's order
+  double *tb = h->it.AXA, *tc = h->it.ATYA;
+  launch_scale_vectors(h->BB, h->CB, h->CB, h->CB, h->Dr, h->Dc, m, n, tb, tc, h->H, h->XB,
                        h->hs);
-  launch_axpby(ob, ob, gv, 0.0, m, h->hs);
-  launch_axpby(oc, oc, gv, 0.0, n, h->hs);
+  launch_axpby(tb, tb, gv, 0.0, m, h->hs);
+  launch_axpby(tc, tc, gv, 0.0, n, h->hs);
+  double *ob = h->on_device ? grad_b : h->it.YA;
+  double *oc = h->on_device ? grad_c : h->it.XA;
+  RC(to_caller(h, ob, tb, h->rperm, m));
+  RC(to_caller(h, oc, tc, h->cperm, n));
   HK();
   if (!h->on_device) {
     HC(hipMemcpyAsync(grad_b, ob, sizeof(double) * m, hipMemcpyDeviceToHost, h->hs));
@@ -1358,7 +1457,7 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
     IterBufs &ib = P.it[k];
     InstData d = base_data(hb);
     if (q.b) {  // b^ = Dr b
-      HC(hipMemcpyAsync(P.b0[k], q.b, sizeof(double) * m, kd, h->hs));
+      RC(to_internal(h, P.b0[k], q.b, hb->on_device, hb->rperm, m, ib.YA));
       launch_scale_vectors(P.b0[k], nullptr, nullptr, nullptr, hb->Dr, hb->Dc, m, 0, P.b[k], nullptr,
                            nullptr, nullptr, h->hs);
       d.b = P.b[k];
@@ -1369,20 +1468,25 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
     }
     const double *l0 = hb->l0, *u0 = hb->u0;
     if (P.l0[k]) {  // bounds: overrides, then fixings l = u = value
-      HC(hipMemcpyAsync(P.l0[k], q.l ? q.l : hb->l0, sizeof(double) * n,
-                        q.l ? kd : hipMemcpyDeviceToDevice, h->hs));
-      HC(hipMemcpyAsync(P.u0[k], q.u ? q.u : hb->u0, sizeof(double) * n,
-                        q.u ? kd : hipMemcpyDeviceToDevice, h->hs));
-      if (q.n_fix > 0) {
+      if (q.l)
+        RC(to_internal(h, P.l0[k], q.l, hb->on_device, hb->cperm, n, ib.XA));
+      else
+        HC(hipMemcpyAsync(P.l0[k], hb->l0, sizeof(double) * n, hipMemcpyDeviceToDevice, h->hs));
+      if (q.u)
+        RC(to_internal(h, P.u0[k], q.u, hb->on_device, hb->cperm, n, ib.XA));
+      else
+        HC(hipMemcpyAsync(P.u0[k], hb->u0, sizeof(double) * n, hipMemcpyDeviceToDevice, h->hs));
+      if (q.n_fix > 0) {  // caller's column indices, mapped through the ordering
         HC(hipMemcpyAsync(P.fix_idx[k], q.fix_idx, sizeof(int32_t) * q.n_fix, kd, h->hs));
         HC(hipMemcpyAsync(P.fix_val[k], q.fix_val, sizeof(double) * q.n_fix, kd, h->hs));
-        launch_fix_bounds(P.l0[k], P.u0[k], P.fix_idx[k], P.fix_val[k], q.n_fix, h->hs);
+        launch_fix_bounds(P.l0[k], P.u0[k], P.fix_idx[k], P.fix_val[k], q.n_fix, hb->cinv, n,
+                          h->hs);
       }
       launch_var_kind(P.l0[k], P.u0[k], n, P.vk[k], h->hs);
       l0 = P.l0[k];
       u0 = P.u0[k];
     }
-    if (q.c) HC(hipMemcpyAsync(P.c0[k], q.c, sizeof(double) * n, kd, h->hs));
+    if (q.c) RC(to_internal(h, P.c0[k], q.c, hb->on_device, hb->cperm, n, ib.XA));
     if (q.c || P.l0[k]) {
       // c^ = Dc c, l^ = l / Dc, u^ = u / Dc; untouched outputs go to free buffers
       launch_scale_vectors(nullptr, q.c ? P.c0[k] : hb->c0, l0, u0, hb->Dr, hb->Dc, 0, n, nullptr,
@@ -1464,9 +1568,8 @@ int pdhg_update(pdhg_handle *h, const double *b, const double *c) {
       if (!isfinite(c[j])) return fail(PDHG_ERR_NONFINITE, "non-finite c[%lld]", (long long)j);
   }
   RC(enter(h));
-  hipMemcpyKind kd = h->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  if (b) HC(hipMemcpyAsync(h->b0, b, sizeof(double) * h->m, kd, h->hs));
-  if (c) HC(hipMemcpyAsync(h->c0, c, sizeof(double) * h->n, kd, h->hs));
+  if (b) RC(to_internal(h, h->b0, b, h->on_device, h->rperm, h->m, h->it.YA));
+  if (c) RC(to_internal(h, h->c0, c, h->on_device, h->cperm, h->n, h->it.XA));
   launch_scale_vectors(h->b0, h->c0, h->l0, h->u0, h->Dr, h->Dc, h->m, h->n, h->b, h->c, h->l,
                        h->u, h->hs);
   launch_init_ctl(h->v, h->nnz, h->b, h->c, h->b0, h->c0, h->m, h->n, h->scratch, h->nscratch,
@@ -1503,14 +1606,46 @@ int pdhg_export_setup(pdhg_handle *h, uint8_t *var_kind, int32_t *colptr, int32_
     if (dst) HC(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->hs));
     return PDHG_OK;
   };
-  RC(d2h(var_kind, h->vk, h->n));
-  RC(d2h(colptr, h->cp, sizeof(int32_t) * (h->n + 1)));
-  RC(d2h(rowidx, h->ri, sizeof(int32_t) * h->nnz));
-  RC(d2h(valT, h->vt, sizeof(double) * h->nnz));
-  RC(d2h(val_s, h->v, sizeof(double) * h->nnz));
-  RC(d2h(Dr, h->Dr, sizeof(double) * h->m));
-  RC(d2h(Dc, h->Dc, sizeof(double) * h->n));
+  const int64_t m = h->m, n = h->n, nnz = h->nnz;
+  if (!h->rperm) {
+    RC(d2h(var_kind, h->vk, n));
+    RC(d2h(colptr, h->cp, sizeof(int32_t) * (n + 1)));
+    RC(d2h(rowidx, h->ri, sizeof(int32_t) * nnz));
+    RC(d2h(valT, h->vt, sizeof(double) * nnz));
+    RC(d2h(val_s, h->v, sizeof(double) * nnz));
+    RC(d2h(Dr, h->Dr, sizeof(double) * m));
+    RC(d2h(Dc, h->Dc, sizeof(double) * n));
+    HC(hipStreamSynchronize(h->hs));
+    return leave(h);
+  }
+  // the internal problem relabelled back into the caller's order (values are
+  // moved, never recomputed, so this is the scaled problem exactly)
+  std::vector<int32_t> prp(m + 1), pci(std::max<int64_t>(nnz, 1));
+  std::vector<double> pv(std::max<int64_t>(nnz, 1)), dr(m), dc(n);
+  std::vector<uint8_t> vk(n);
+  RC(d2h(prp.data(), h->rp, sizeof(int32_t) * (m + 1)));
+  RC(d2h(pci.data(), h->ci, sizeof(int32_t) * nnz));
+  RC(d2h(pv.data(), h->v, sizeof(double) * nnz));
+  RC(d2h(dr.data(), h->Dr, sizeof(double) * m));
+  RC(d2h(dc.data(), h->Dc, sizeof(double) * n));
+  RC(d2h(vk.data(), h->vk, n));
   HC(hipStreamSynchronize(h->hs));
+  std::vector<int32_t> rp, ci, cp, ri;
+  std::vector<double> v, vt;
+  unpermute_csr(m, prp.data(), pci.data(), pv.data(), h->h_rperm, h->h_cperm, rp, ci, v);
+  if (val_s) std::copy(v.begin(), v.begin() + nnz, val_s);
+  if (colptr || rowidx || valT) {
+    transpose_csr(m, n, rp.data(), ci.data(), v.data(), cp, ri, vt);
+    if (colptr) std::copy(cp.begin(), cp.end(), colptr);
+    if (rowidx) std::copy(ri.begin(), ri.begin() + nnz, rowidx);
+    if (valT) std::copy(vt.begin(), vt.begin() + nnz, valT);
+  }
+  for (int64_t i = 0; i < m; i++)
+    if (Dr) Dr[h->h_rperm[i]] = dr[i];
+  for (int64_t j = 0; j < n; j++) {
+    if (Dc) Dc[h->h_cperm[j]] = dc[j];
+    if (var_kind) var_kind[h->h_cperm[j]] = vk[j];
+  }
   return leave(h);
 }
 
@@ -1520,14 +1655,27 @@ int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out) {
   int64_t nin = transpose ? h->m : h->n, nout = transpose ? h->n : h->m;
   double *din = transpose ? h->it.YA : h->it.XA;
   double *dout = transpose ? h->it.ATYA : h->it.AXA;
-  HC(hipMemcpyAsync(din, x, sizeof(double) * nin, hipMemcpyHostToDevice, h->hs));
+  const std::vector<int32_t> &pin = transpose ? h->h_rperm : h->h_cperm;
+  const std::vector<int32_t> &pout = transpose ? h->h_cperm : h->h_rperm;
+  std::vector<double> xin, yout;
+  const double *src = x;
+  if (h->rperm) {  // caller's order <-> internal order on the host
+    xin.resize(nin);
+    for (int64_t q = 0; q < nin; q++) xin[q] = x[pin[q]];
+    src = xin.data();
+    yout.resize(nout);
+  }
+  HC(hipMemcpyAsync(din, src, sizeof(double) * nin, hipMemcpyHostToDevice, h->hs));
   if (transpose)
     launch_spmv(h->cp, h->ri, h->vt, h->n, din, dout, h->hs);
   else
     launch_spmv(h->rp, h->ci, h->v, h->m, din, dout, h->hs);
   HK();
-  HC(hipMemcpyAsync(out, dout, sizeof(double) * nout, hipMemcpyDeviceToHost, h->hs));
+  HC(hipMemcpyAsync(h->rperm ? yout.data() : out, dout, sizeof(double) * nout,
+                    hipMemcpyDeviceToHost, h->hs));
   HC(hipStreamSynchronize(h->hs));
+  if (h->rperm)
+    for (int64_t q = 0; q < nout; q++) out[pout[q]] = yout[q];
   return leave(h);
 }
 
@@ -1568,6 +1716,28 @@ int time_kernels(pdhg_handle *h, int attempts, double *ms) {
   return PDHG_OK;
 }
 }  // namespace
+
+extern "C" int pdhg_locality_order(int64_t m, int64_t n, const int32_t *row_ptr,
+                                   const int32_t *col_idx, int32_t *row_order,
+                                   int32_t *col_order) {
+  if (m <= 0 || n <= 0 || !row_ptr || !row_order || !col_order)
+    return fail(PDHG_ERR_ARG, "bad argument");
+  if (row_ptr[0] != 0) return fail(PDHG_ERR_CSR, "row_ptr[0] must be 0");
+  for (int64_t i = 0; i < m; i++) {
+    if (row_ptr[i + 1] < row_ptr[i]) return fail(PDHG_ERR_CSR, "row_ptr not monotone");
+    for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; k++)
+      if (col_idx[k] < 0 || col_idx[k] >= n || (k > row_ptr[i] && col_idx[k] <= col_idx[k - 1]))
+        return fail(PDHG_ERR_CSR, "column indices out of range or not ascending in row %lld",
+                    (long long)i);
+  }
+  std::vector<int32_t> cp, ri, ro, co;
+  std::vector<double> none;
+  transpose_csr(m, n, row_ptr, col_idx, nullptr, cp, ri, none);
+  rcm_order(m, n, row_ptr, col_idx, cp.data(), ri.data(), ro, co);
+  std::copy(ro.begin(), ro.end(), row_order);
+  std::copy(co.begin(), co.end(), col_order);
+  return PDHG_OK;
+}
 
 extern "C" int pdhg_get_partition(pdhg_handle *h, int *out) {
   if (!h || !out) return fail(PDHG_ERR_ARG, "null argument");

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #define PDHG_BLOCK 256
 // rows of one tile of the attempt kernels (and their workgroup size)
 #ifndef PDHG_TILE
@@ -87,6 +89,8 @@ struct EvalView {
   int use_average, restart;
   double pw_theta;               // 0 keeps the primal weight
   int long_seg;
+  // caller's index of each internal row / column (null: same order)
+  const int32_t *rperm, *cperm;
 };
 
 #define EV_ROWQ 10
@@ -113,9 +117,29 @@ void launch_scale_vectors(const double *b0, const double *c0, const double *l0,
                           double *u, hipStream_t s);
 void launch_fill(double *p, double v, int64_t n, hipStream_t s);
 void launch_fix_bounds(double *l, double *u, const int32_t *idx, const double *val, int64_t nfix,
+                       const int32_t *inv, int64_t n,
                        hipStream_t s);
 void launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
 void launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+
+// locality ordering (reorder.hip)
+void rcm_order(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cp,
+               const int32_t *ri, std::vector<int32_t> &row_order, std::vector<int32_t> &col_order);
+void permute_csr(int64_t m, const int32_t *rp, const int32_t *ci, const double *v,
+                 const std::vector<int32_t> &row_order, const std::vector<int32_t> &cinv,
+                 std::vector<int32_t> &prp, std::vector<int32_t> &pci, std::vector<double> &pv);
+void unpermute_csr(int64_t m, const int32_t *prp, const int32_t *pci, const double *pv,
+                   const std::vector<int32_t> &row_order, const std::vector<int32_t> &col_order,
+                   std::vector<int32_t> &rp, std::vector<int32_t> &ci, std::vector<double> &v);
+void transpose_csr(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                   std::vector<int32_t> &cp, std::vector<int32_t> &ri, std::vector<double> &vt);
+// dst[i] = src[order[i]] (gather) / dst[order[i]] = src[i] (scatter)
+void launch_gather_f64(double *dst, const double *src, const int32_t *order, int64_t cnt,
+                       hipStream_t s);
+void launch_gather_u8(uint8_t *dst, const uint8_t *src, const int32_t *order, int64_t cnt,
+                      hipStream_t s);
+void launch_scatter_f64(double *dst, const double *src, const int32_t *order, int64_t cnt,
+                        hipStream_t s);
 
 // One instance of a (possibly batched) solve: views of its problem data and
 // iterates, its control state, start point and result buffers.

@@ -868,7 +868,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_init_cols(const Inst<T> *__restr
   int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (j >= e.n) return;
   const double *x0 = I[inst].x0;
-  double xv = x0 ? x0[j] / e.Dc[j] : 0.0;
+  double xv = x0 ? x0[e.cperm ? e.cperm[j] : j] / e.Dc[j] : 0.0;
   xv = clamp_box<double>(xv, e.l[j], e.u[j]);
   e.X[0][j] = (T)xv;
   e.XL[j] = (double)(T)xv;
@@ -880,7 +880,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_init_rows(const Inst<T> *__restr
   int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (i >= e.m) return;
   const double *y0 = I[inst].y0;
-  double yv = y0 ? y0[i] / e.Dr[i] : 0.0;
+  double yv = y0 ? y0[e.rperm ? e.rperm[i] : i] / e.Dr[i] : 0.0;
   if (e.kind[i] == 1 && yv < 0.0) yv = 0.0;
   e.Y[0][i] = (T)yv;
   e.YL[i] = (double)(T)yv;
@@ -966,7 +966,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_unscale_cols(const Inst<T> *__re
   int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (j >= e.n) return;
   double xv = st->which ? e.XA[j] : (double)e.X[st->cur][j];
-  I[inst].xout[j] = e.Dc[j] * xv;
+  I[inst].xout[e.cperm ? e.cperm[j] : j] = e.Dc[j] * xv;
 }
 
 template <typename T>
@@ -976,7 +976,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_unscale_rows(const Inst<T> *__re
   int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (i >= e.m) return;
   double yv = st->which ? e.YA[i] : (double)e.Y[st->cur][i];
-  I[inst].yout[i] = e.Dr[i] * yv;
+  I[inst].yout[e.rperm ? e.rperm[i] : i] = e.Dr[i] * yv;
 }
 
 // ---------------------------------------------------------------------------

@@ -297,11 +297,15 @@ __global__ void k_scale_cols_vec(const double *__restrict__ c0, const double *__
 }
 
 __global__ void k_fix_bounds(double *l, double *u, const int32_t *__restrict__ idx,
-                             const double *__restrict__ val, int64_t nfix) {
+                             const double *__restrict__ val, int64_t nfix,
+                             const int32_t *__restrict__ inv, int64_t n) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nfix) return;
-  l[idx[k]] = val[k];
-  u[idx[k]] = val[k];
+  int64_t j = idx[k];
+  if (j < 0 || j >= n) return;  // out-of-range fixings are ignored
+  if (inv) j = inv[j];
+  l[j] = val[k];
+  u[j] = val[k];
 }
 
 }  // namespace
@@ -310,8 +314,8 @@ __global__ void k_fix_bounds(double *l, double *u, const int32_t *__restrict__ i
 // launchers
 
 void launch_fix_bounds(double *l, double *u, const int32_t *idx, const double *val, int64_t nfix,
-                       hipStream_t s) {
-  if (nfix > 0) k_fix_bounds<<<grid_for(nfix), PDHG_BLOCK, 0, s>>>(l, u, idx, val, nfix);
+                       const int32_t *inv, int64_t n, hipStream_t s) {
+  if (nfix > 0) k_fix_bounds<<<grid_for(nfix), PDHG_BLOCK, 0, s>>>(l, u, idx, val, nfix, inv, n);
 }
 
 void launch_validate(const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *kind,

@@ -162,6 +162,18 @@ class Problem:
             pass
 
 
+def locality_order(lp):
+    """(row_order, col_order) of the relabelling pdhg_setup applies with
+    reorder=1 (host computation, no GPU)."""
+    rp = np.ascontiguousarray(lp.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(lp.col_idx, dtype=np.int32)
+    ro = np.empty(lp.m, dtype=np.int32)
+    co = np.empty(lp.n, dtype=np.int32)
+    L.check(L.load().pdhg_locality_order(lp.m, lp.n, rp.ctypes.data, ci.ctypes.data,
+                                         ro.ctypes.data, co.ctypes.data))
+    return ro, co
+
+
 def solve(lp, x0=None, y0=None, **opts):
     p = Problem(lp, **opts)
     try:

@@ -121,3 +121,60 @@ def test_shape_errors():
     assert _setup_rc(lp)[0] == -5     # valid LP, no workspace
     lp.m = 0
     assert _setup_rc(lp)[0] == -1
+
+
+def _lines_per_wave(rp, ci, elem=4, line=128, wave=64):
+    """Distinct cache lines the lanes of one wave touch when 64 consecutive
+    nonzeros gather the vector by their column index (the LDS-staged SpMV)."""
+    L_ = np.asarray(ci, np.int64) * elem // line
+    nw = (len(L_) + wave - 1) // wave
+    pad = np.full(nw * wave, -1, np.int64)
+    pad[:len(L_)] = L_
+    pad = np.sort(pad.reshape(nw, wave), axis=1)
+    return ((np.diff(pad, axis=1) != 0).sum(axis=1) + 1).sum() / nw
+
+
+def test_locality_order_is_a_permutation_and_localises_gathers():
+    import scipy.sparse as sp
+    from paper_2512_06715_amd.solver import locality_order
+    lp = ucgen.workload("uc1000_t48")
+    ro, co = locality_order(lp)
+    assert np.array_equal(np.sort(ro), np.arange(lp.m))
+    assert np.array_equal(np.sort(co), np.arange(lp.n))
+    ro2, co2 = locality_order(lp)  # deterministic
+    assert np.array_equal(ro, ro2) and np.array_equal(co, co2)
+    A = sp.csr_matrix((lp.val, lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n))
+    P = A[ro][:, co].tocsr()
+    P.sort_indices()
+    for M0, M1 in ((A, P), (A.T.tocsr(), P.T.tocsr())):
+        before = _lines_per_wave(M0.indptr, M0.indices)
+        after = _lines_per_wave(M1.indptr, M1.indices)
+        assert after < 0.6 * before, (before, after)
+
+
+def test_locality_order_of_disconnected_and_empty_parts():
+    from paper_2512_06715_amd.solver import locality_order
+    # two blocks, an empty row and an empty column
+    A = np.zeros((5, 6))
+    A[0, 0] = A[0, 1] = A[1, 1] = 1.0
+    A[3, 4] = A[4, 4] = A[4, 5] = 2.0
+    lp = ucgen.dense_to_lp(A, np.zeros(5, np.uint8), np.ones(5), np.ones(6), np.zeros(6),
+                           np.ones(6))
+    ro, co = locality_order(lp)
+    assert sorted(ro) == list(range(5)) and sorted(co) == list(range(6))
+
+
+def test_locality_order_rejects_bad_csr():
+    lib = L.load()
+    rp = np.array([0, 2, 1], np.int32)
+    ci = np.array([0, 1], np.int32)
+    ro = np.empty(2, np.int32)
+    co = np.empty(2, np.int32)
+    rc = lib.pdhg_locality_order(2, 2, rp.ctypes.data, ci.ctypes.data, ro.ctypes.data,
+                                 co.ctypes.data)
+    assert rc == -2  # PDHG_ERR_CSR
+    rp = np.array([0, 2, 2], np.int32)
+    ci = np.array([1, 0], np.int32)  # not ascending
+    rc = lib.pdhg_locality_order(2, 2, rp.ctypes.data, ci.ctypes.data, ro.ctypes.data,
+                                 co.ctypes.data)
+    assert rc == -2  # PDHG_ERR_CSR

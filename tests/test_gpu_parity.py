@@ -33,12 +33,15 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("reorder", [1, 0])
 @pytest.mark.parametrize("name", list(CASES))
-def test_setup_bit_exact(gpu, oracle_mod, name):
+def test_setup_bit_exact(gpu, oracle_mod, name, reorder):
+    """The preprocessed problem, read back in the caller's order, is the
+    oracle's bit for bit, whether or not the solver relabels it internally."""
     from paper_2512_06715_amd.solver import Problem
     lp = CASES[name]()
-    print("case", name, ucgen.describe(lp), flush=True)
-    p = Problem(lp)
+    print("case", name, "reorder", reorder, ucgen.describe(lp), flush=True)
+    p = Problem(lp, reorder=reorder)
     g = p.export_setup()
     p.close()
     vk = oracle_mod.var_kind(lp.l, lp.u)
@@ -53,12 +56,13 @@ def test_setup_bit_exact(gpu, oracle_mod, name):
     assert np.array_equal(g["valT"].view(np.uint64), vt.view(np.uint64))
 
 
+@pytest.mark.parametrize("reorder", [1, 0])
 @pytest.mark.parametrize("name", ["uc14_t24", "dense_cols"])
-def test_one_attempt(gpu, oracle_mod, name):
+def test_one_attempt(gpu, oracle_mod, name, reorder):
     from paper_2512_06715_amd.solver import Problem
     lp = CASES[name]()
-    print("case", name, flush=True)
-    p = Problem(lp, max_iter=1, tol=1e-12, use_graph=0)
+    print("case", name, "reorder", reorder, flush=True)
+    p = Problem(lp, max_iter=1, tol=1e-12, use_graph=0, reorder=reorder)
     x, y, info = p.solve()
     p.close()
     xo, yo, io = oracle_mod.pdhg(lp, tol=1e-12, max_iter=1)
@@ -132,3 +136,29 @@ def test_autotune_picks_a_candidate(gpu, oracle_mod):
     assert info["status"] == 1
     assert oracle_mod.kkt(lp, x, y)["rel_kkt"] <= 1.001e-4
     print("autotuned partition", part, flush=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reorder_same_solution(gpu, oracle_mod, precision):
+    """The internal relabelling changes rounding order only: both orders solve
+    to the same optimum, and warm starts and results stay in the caller's
+    order (a solve started at the other's answer stops at once)."""
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc1000_t48")
+    print("case reorder", precision, flush=True)
+    res = {}
+    for r in (0, 1):
+        p = Problem(lp, reorder=r, tol=1e-4, precision=precision)
+        res[r] = p.solve()
+        p.close()
+        assert res[r][2]["status"] == 1
+    tol = 1e-4
+    for r in (0, 1):
+        k = oracle_mod.kkt(lp, res[r][0], res[r][1])
+        assert k["rel_kkt"] <= tol * 1.001
+    o0, o1 = res[0][2]["primal_obj"], res[1][2]["primal_obj"]
+    assert abs(o0 - o1) <= 2 * tol * (1 + abs(o0))
+    p = Problem(lp, reorder=1, tol=tol, precision=precision)
+    x, y, info = p.solve(x0=res[0][0], y0=res[0][1])
+    p.close()
+    assert info["attempts"] <= 256 and info["status"] == 1
