@@ -81,7 +81,7 @@ struct IterBufs {
   double *X[2], *Y[2], *AX[2], *XS, *YS;
   float *Xf[2], *Yf[2], *AXf[2], *XSf, *YSf;
   double *XL, *YL, *XA, *YA, *AXA, *ATY, *ATYA;
-  double *part_dx2, *part_dy, *part_rows, *part_cols;
+  double *part_dx2, *part_dy, *ctl_stage, *ev_stage, *part_rows, *part_cols;
   CtlState *st;
 };
 
@@ -110,6 +110,8 @@ void carve_iter(Carver &cv, IterBufs &b, int64_t m, int64_t n, int grid_rows, in
   b.ATYA = cv.take<double>(n);
   b.part_dx2 = cv.take<double>(grid_cols);
   b.part_dy = cv.take<double>(2 * (int64_t)grid_rows);
+  b.ctl_stage = cv.take<double>(3 * PDHG_CTL_SPLIT);
+  b.ev_stage = cv.take<double>((EV_ROWQ + EV_COLQ) * PDHG_CTL_SPLIT);
   b.part_rows = cv.take<double>((int64_t)nblk(m) * EV_ROWQ);
   b.part_cols = cv.take<double>((int64_t)nblk(n) * EV_COLQ);
   b.st = cv.take<CtlState>(1);
@@ -505,6 +507,7 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   w.grid_cols = h->grid_cols[sizeof(T) == 4];
   w.part_dx2 = b.part_dx2;
   w.part_dy = b.part_dy;
+  w.ctl_stage = b.ctl_stage;
   w.adaptive = h->o.step_mode == 0;
   w.long_seg = e.long_seg = h->long_seg;
   w.direct = h->direct;
@@ -527,6 +530,9 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.YL = b.YL;
   e.part_rows = b.part_rows;
   e.part_cols = b.part_cols;
+  e.ev_stage = b.ev_stage;
+  e.xbest = sizeof(T) == 4 ? b.X[0] : nullptr;
+  e.ybest = sizeof(T) == 4 ? b.Y[0] : nullptr;
   e.use_average = h->o.use_average;
   e.restart = h->o.restart;
   e.pw_theta = h->o.pw_update ? h->o.pw_theta : 0.0;
@@ -677,7 +683,7 @@ int run_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
               std::vector<CtlState> &final_state) {
   const int P = h->o.eval_period;
   const bool fp32 = sizeof(T) == 4;
-  std::vector<double> best(all.size(), INFINITY);
+  std::vector<double> best(all.size(), INFINITY), first(all.size(), INFINITY);
   std::vector<int> since(all.size(), 0);
   Groups g{};
   int version = reuse_graph ? gs.version : gs.version + 1;
@@ -707,10 +713,15 @@ int run_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
         status[i] = PDHG_TIME_LIMIT;
         continue;
       }
+      if (first[i] == INFINITY) first[i] = s.rel_kkt;
       if (s.rel_kkt < 0.9 * best[i]) {
         best[i] = s.rel_kkt;
         since[i] = 0;
-      } else if (stall_evals > 0 && ++since[i] >= stall_evals) {
+      } else if (stall_evals > 0 &&
+                 (++since[i] >= stall_evals ||
+                  (best[i] == first[i] && first[i] <= 10.0 * tol && s.rel_kkt > 10.0 * first[i]))) {
+        // stalled, or drifting away from a start point that was near the target
+        // and has not been improved on (the next phase starts from the best point)
         status[i] = 0;
         continue;
       }

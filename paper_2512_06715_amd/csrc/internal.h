@@ -10,6 +10,8 @@
 #ifndef PDHG_TILE
 #define PDHG_TILE 256
 #endif
+// workgroups per instance of the step-control kernel
+#define PDHG_CTL_SPLIT 16
 // default length above which a row / column is handled by a workgroup
 #define PDHG_LONG_SEG 64
 // tile groups per launch above which a workgroup takes several tiles
@@ -36,6 +38,7 @@ struct CtlState {
   double pobj, dobj, rel_p, rel_d, rel_gap, rel_kkt;
   // last attempt's reduced partials (diagnostics)
   double dx2, dy2, inter;
+  double best_kkt;        // FP32 phase: lowest KKT of an evaluated current iterate
   long long k, accepted, restarts, last_restart;
   int cur;                // buffer index of the current iterate
   int fresh;              // 1: the next fold starts the sums afresh
@@ -43,6 +46,8 @@ struct CtlState {
   int restart_flag;       // 0 none, 1 restart at current, 2 restart to average
   int have_avg;
   int init_pending;       // 1: the next evaluation records the restart reference
+  int ticket;             // step-control workgroups done with the current attempt
+  int stash;              // FP32 phase: the evaluated current iterate is a new best
 };
 
 // One precision's view of the scaled problem and iterates.
@@ -62,6 +67,7 @@ struct IterView {
   int grid_rows, grid_cols;      // long segments + tile groups
   double *part_dx2;              // [grid_cols]
   double *part_dy;               // [2 * grid_rows]
+  double *ctl_stage;             // [3 * PDHG_CTL_SPLIT] slice sums of the step control
   int adaptive;
   int long_seg;                  // rows longer than this get a workgroup each
   int direct;                    // 1: per-row loops instead of LDS-staged tiles
@@ -86,6 +92,10 @@ struct EvalView {
   int nblk_rows, nblk_cols;
   double *part_rows;             // [nblk_rows * EV_ROWQ]
   double *part_cols;             // [nblk_cols * EV_COLQ]
+  double *ev_stage;              // [(EV_ROWQ + EV_COLQ) * PDHG_CTL_SPLIT] slice results
+  // FP32 phase: the best evaluated iterate, kept in FP64 (the FP64 phase's
+  // start buffers); null in the FP64 views
+  double *xbest, *ybest;
   int use_average, restart;
   double pw_theta;               // 0 keeps the primal weight
   int long_seg;

@@ -112,11 +112,9 @@ __device__ inline void block_reduce(double (&v)[NQ], unsigned maxmask, double *o
 // Sum (or max) of `cnt` partials with stride `stride`, one workgroup of BS
 // threads, fixed order: lane t combines partials t, t + BS, t + 2 BS, ... in
 // that order, then the block tree combines the lanes.  Loads go out CH per
-// lane at a time before any of them is used.  When `st` is given, its words
-// are fetched together with the first partials and left in `st_lds` (visible
-// to every lane on return).
+// lane at a time before any of them is used.
 #define CTL_BLOCK 1024
-static_assert(sizeof(CtlState) % 8 == 0 && sizeof(CtlState) / 8 <= CTL_BLOCK, "state words");
+static_assert(sizeof(CtlState) % 8 == 0, "the state is copied in 8-byte words");
 // Whole-state write-back (8-byte words) from one lane.
 __device__ inline void store_state(CtlState *dst, const CtlState &s) {
   AS_G unsigned long long *d = gout((unsigned long long *)dst);
@@ -127,12 +125,9 @@ __device__ inline void store_state(CtlState *dst, const CtlState &s) {
 
 template <int NQ, int BS = CTL_BLOCK>
 __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t stride,
-                                       unsigned maxmask, double *out,
-                                       const CtlState *st = nullptr, CtlState *st_lds = nullptr) {
+                                       unsigned maxmask, double *out) {
   constexpr int CH = NQ >= 8 ? 2 : 16 / NQ;
-  constexpr int SW = sizeof(CtlState) / 8;
   const AS_G double *pg = gin(p);
-  unsigned long long sw = 0;
   double v[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; q++) v[q] = 0.0;
@@ -145,7 +140,6 @@ __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t str
 #pragma unroll
       for (int q = 0; q < NQ; q++) a[c][q] = pg[q * stride + bc];
     }
-    if (b0 == 0 && st && threadIdx.x < SW) sw = gin((const unsigned long long *)st)[threadIdx.x];
 #pragma unroll
     for (int c = 0; c < CH; c++) {
       bool ok = b0 + c * BS + threadIdx.x < cnt;
@@ -154,7 +148,6 @@ __device__ inline void reduce_partials(const double *p, int64_t cnt, int64_t str
         v[q] = ((maxmask >> q) & 1) ? fmax(v[q], ok ? a[c][q] : v[q]) : v[q] + (ok ? a[c][q] : 0.0);
     }
   }
-  if (st && threadIdx.x < SW) ((unsigned long long *)st_lds)[threadIdx.x] = sw;
   block_reduce<NQ, BS>(v, maxmask, out);
 }
 
@@ -471,21 +464,70 @@ __global__ __launch_bounds__(PDHG_TILE) void k_dual(const Inst<T> *__restrict__ 
   }
 }
 
-// Step-size control of one attempt (PDLP adaptive rule), one workgroup per
-// instance:
+// Step-size control of one attempt (PDLP adaptive rule):
 //   ebar = ||dz||_omega^2 / (2 |dy' A dx|),  accept iff eta <= ebar,
 //   eta <- min((1 - (k+1)^-0.3) ebar, (1 + (k+1)^-0.6) eta),  k = attempts so far.
+// PDHG_CTL_SPLIT workgroups per instance each sum a fixed slice of the
+// attempt kernels' partials; the last one to finish (device-scope ticket)
+// adds the slice sums in slice order and takes the decision.  The sums do
+// not depend on which workgroup finishes last.
 template <typename T>
-__global__ __launch_bounds__(CTL_BLOCK) void k_control(const Inst<T> *__restrict__ I) {
+__global__ __launch_bounds__(PDHG_BLOCK) void k_control(const Inst<T> *__restrict__ I) {
   __shared__ double r[3];
-  __shared__ CtlState sl;
-  const AS_C Inst<T> &in = cin(I)[blockIdx.x];
+  __shared__ int last;
+  const int inst = blockIdx.x / PDHG_CTL_SPLIT, part = blockIdx.x % PDHG_CTL_SPLIT;
+  const AS_C Inst<T> &in = cin(I)[inst];
   CtlState *gst = in.st;
-  reduce_partials<1>(in.w.part_dx2, in.w.grid_cols, 0, 0u, &r[0], gst, &sl);
-  reduce_partials<2>(in.w.part_dy, in.w.grid_rows, in.w.grid_rows, 0u, &r[1]);
-  if (threadIdx.x != 0) return;
-  CtlState st = sl;
-  double dx2 = r[0], dy2 = r[1], inter = r[2];
+  const int64_t nc = in.w.grid_cols, nr = in.w.grid_rows;
+  const int64_t c0 = nc * part / PDHG_CTL_SPLIT, c1 = nc * (part + 1) / PDHG_CTL_SPLIT;
+  const int64_t r0 = nr * part / PDHG_CTL_SPLIT, r1 = nr * (part + 1) / PDHG_CTL_SPLIT;
+  const AS_G double *px = gin((const double *)in.w.part_dx2), *py = gin((const double *)in.w.part_dy);
+  double v[3] = {0.0, 0.0, 0.0};
+  {
+    constexpr int CH = 4;
+    double a[CH], d[CH], e[CH];
+    for (int64_t b0 = 0; b0 < c1 - c0 || b0 < r1 - r0; b0 += CH * PDHG_BLOCK) {
+#pragma unroll
+      for (int q = 0; q < CH; q++) {
+        int64_t bx = c0 + b0 + q * PDHG_BLOCK + threadIdx.x;
+        int64_t by = r0 + b0 + q * PDHG_BLOCK + threadIdx.x;
+        a[q] = bx < c1 ? px[bx] : 0.0;
+        d[q] = by < r1 ? py[by] : 0.0;
+        e[q] = by < r1 ? py[nr + by] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < CH; q++) {
+        v[0] += a[q];
+        v[1] += d[q];
+        v[2] += e[q];
+      }
+    }
+  }
+  block_reduce<3, PDHG_BLOCK>(v, 0u, r);
+  double *stage = in.w.ctl_stage;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; q++) stage[3 * part + q] = r[q];
+    __threadfence();  // the slice sums are visible before the ticket counts them
+    last = atomicAdd(&gst->ticket, 1) == PDHG_CTL_SPLIT - 1;
+  }
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  __threadfence();
+  double dx2 = 0.0, dy2 = 0.0, inter = 0.0;
+  for (int p = 0; p < PDHG_CTL_SPLIT; p++) {
+    dx2 += __hip_atomic_load(stage + 3 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    dy2 += __hip_atomic_load(stage + 3 * p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    inter += __hip_atomic_load(stage + 3 * p + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  CtlState st;
+  {
+    const AS_G unsigned long long *src = gin((const unsigned long long *)gst);
+    unsigned long long *dst = (unsigned long long *)&st;
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(CtlState) / 8); q++) dst[q] = src[q];
+  }
+  st.ticket = 0;
   double eta = st.eta, omega = st.omega;
   long long k = st.k + 1;
   if (st.pending > 0.0) st.fresh = 0;  // this attempt's kernels folded it
@@ -753,20 +795,55 @@ __device__ inline PointKKT point_kkt(const double *rq, const double *cq, double 
 // the scaled KKT_omega (restart at the better of current and average when it
 // fell to 0.2 of the last restart's, or to 0.8 with no progress since the
 // previous evaluation, or after 0.36 of all attempts), primal-weight update.
-// One workgroup per instance.
+// PDHG_CTL_SPLIT workgroups per instance reduce fixed slices of the
+// evaluation partials; the last to finish combines the slices in slice order
+// and takes the decisions.
 template <typename T>
-__global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const Inst<T> *__restrict__ I,
-                                                            double tol, long long max_iter) {
-  __shared__ double rq[EV_ROWQ], cq[EV_COLQ];
-  __shared__ CtlState sl;
-  const AS_C Inst<T> &in = cin(I)[blockIdx.x];
+__global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const Inst<T> *__restrict__ I,
+                                                             double tol, long long max_iter) {
+  constexpr unsigned ROWMAX = (1u << 2) | (1u << 7), COLMAX = (1u << 2) | (1u << 8);
+  constexpr int NQ = EV_ROWQ + EV_COLQ;
+  __shared__ double r[NQ];
+  __shared__ int last;
+  const int inst = blockIdx.x / PDHG_CTL_SPLIT, part = blockIdx.x % PDHG_CTL_SPLIT;
+  const AS_C Inst<T> &in = cin(I)[inst];
   const AS_C EvalView<T> &e = in.e;
   CtlState *gst = in.st;
-  reduce_partials<EV_ROWQ>(e.part_rows, e.nblk_rows, e.nblk_rows, (1u << 2) | (1u << 7), rq, gst,
-                           &sl);
-  reduce_partials<EV_COLQ>(e.part_cols, e.nblk_cols, e.nblk_cols, (1u << 2) | (1u << 8), cq);
-  if (threadIdx.x != 0) return;
-  CtlState stv = sl;
+  const int64_t nbr = e.nblk_rows, nbc = e.nblk_cols;
+  const int64_t r0 = nbr * part / PDHG_CTL_SPLIT, r1 = nbr * (part + 1) / PDHG_CTL_SPLIT;
+  const int64_t c0 = nbc * part / PDHG_CTL_SPLIT, c1 = nbc * (part + 1) / PDHG_CTL_SPLIT;
+  reduce_partials<EV_ROWQ, PDHG_BLOCK>(e.part_rows + r0, r1 - r0, nbr, ROWMAX, r);
+  reduce_partials<EV_COLQ, PDHG_BLOCK>(e.part_cols + c0, c1 - c0, nbc, COLMAX, r + EV_ROWQ);
+  double *stage = e.ev_stage;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < NQ; q++) stage[NQ * part + q] = r[q];
+    __threadfence();  // the slice results are visible before the ticket counts them
+    last = atomicAdd(&gst->ticket, 1) == PDHG_CTL_SPLIT - 1;
+  }
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  __threadfence();
+  double rq[EV_ROWQ], cq[EV_COLQ];
+  for (int q = 0; q < NQ; q++) {
+    bool mx = q < EV_ROWQ ? ((ROWMAX >> q) & 1) : ((COLMAX >> (q - EV_ROWQ)) & 1);
+    double a = 0.0;
+    for (int p = 0; p < PDHG_CTL_SPLIT; p++) {
+      double t = __hip_atomic_load(stage + NQ * p + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a = mx ? fmax(a, t) : a + t;
+    }
+    if (q < EV_ROWQ)
+      rq[q] = a;
+    else
+      cq[q - EV_ROWQ] = a;
+  }
+  CtlState stv;
+  {
+    const AS_G unsigned long long *src = gin((const unsigned long long *)gst);
+    unsigned long long *dst = (unsigned long long *)&stv;
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(CtlState) / 8); q++) dst[q] = src[q];
+  }
+  stv.ticket = 0;
   CtlState *st = &stv;
   bool avg = e.use_average && st->wsum > 0.0;
   double omega = st->omega;
@@ -823,6 +900,11 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const Inst<T> *__res
     }
   }
   st->which = which;
+  st->stash = 0;
+  if (e.xbest && rep->rel_kkt < st->best_kkt) {  // FP32 phase: new best point
+    st->stash = 1;
+    st->best_kkt = rep->rel_kkt;
+  }
   st->pobj = rep->pobj;
   st->dobj = rep->dobj;
   st->rel_p = rep->rel_p;
@@ -830,6 +912,27 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_eval_control(const Inst<T> *__res
   st->rel_gap = rep->rel_g;
   st->rel_kkt = rep->rel_kkt;
   store_state(gst, stv);
+}
+
+// FP32 phase: keep the evaluated current iterate when it is the best so far
+// (in FP64, in the buffers the FP64 phase starts from).
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_stash_cols(const Inst<T> *__restrict__ I, Groups g) {
+  GROUP_BLOCK(p_cols)
+  if (!e.xbest || !st->stash) return;
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  if (j >= e.n) return;
+  // the evaluated point: the average when it was reported or restarted to
+  e.xbest[j] = (st->which || st->restart_flag == 2) ? e.XA[j] : (double)e.X[st->cur][j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_stash_rows(const Inst<T> *__restrict__ I, Groups g) {
+  GROUP_BLOCK(p_rows)
+  if (!e.ybest || !st->stash) return;
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  if (i >= e.m) return;
+  e.ybest[i] = (st->which || st->restart_flag == 2) ? e.YA[i] : (double)e.Y[st->cur][i];
 }
 
 template <typename T>
@@ -912,6 +1015,9 @@ __global__ void k_init_state(const Inst<T> *__restrict__ I) {
   st->restart_flag = 0;
   st->have_avg = 0;
   st->init_pending = 1;
+  st->ticket = 0;
+  st->best_kkt = INFINITY;
+  st->stash = 0;
   st->eta = st->eta0;
   st->omega = st->omega0;
 }
@@ -927,9 +1033,8 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_switch_cols(const Inst<float> *_
   GROUP_BLOCK(p_cols)
   int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (j >= e.n) return;
-  double xv = (double)If[inst].e.X[st->cur][j];
-  e.X[0][j] = xv;
-  e.XL[j] = xv;
+  (void)If;
+  e.XL[j] = e.X[0][j];  // X[0] holds the FP32 phase's best point
 }
 
 __global__ __launch_bounds__(PDHG_BLOCK) void k_switch_rows(const Inst<float> *__restrict__ If,
@@ -939,9 +1044,8 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_switch_rows(const Inst<float> *_
   GROUP_BLOCK(p_rows)
   int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (i >= e.m) return;
-  double yv = (double)If[inst].e.Y[st->cur][i];
-  e.Y[0][i] = yv;
-  e.YL[i] = yv;
+  (void)If;
+  e.YL[i] = e.Y[0][i];  // Y[0] holds the FP32 phase's best point
 }
 
 __global__ void k_switch_state(const Inst<double> *__restrict__ I) {
@@ -1162,6 +1266,7 @@ __global__ __launch_bounds__(CTL_BLOCK) void k_init_ctl(const double *part, int 
   double amax = r[0], nbs = sqrt(r[1]), ncs = sqrt(r[2]);
   st->nb = sqrt(r[3]);
   st->nc = sqrt(r[4]);
+  st->ticket = 0;
   st->eta0 = (fixed_eta > 0.0) ? fixed_eta : (amax > 0.0 ? 1.0 / amax : 1.0);
   if (fixed_omega > 0.0)
     st->omega0 = fixed_omega;
@@ -1202,7 +1307,7 @@ void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s) {
 
 template <typename T>
 void launch_control(const Inst<T> *I, const Groups &g, hipStream_t s) {
-  k_control<T><<<grid_of(g.ninst), CTL_BLOCK, 0, s>>>(I);
+  k_control<T><<<grid_of(g.ninst * PDHG_CTL_SPLIT), PDHG_BLOCK, 0, s>>>(I);
 }
 
 template <typename T>
@@ -1230,9 +1335,13 @@ void launch_evaluate(const Inst<T> *I, const Groups &g, double tol, int64_t max_
   launch_products<T>(I, g, SP_ATYA, s);
   k_eval_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
   k_eval_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
-  k_eval_control<T><<<grid_of(g.ninst), CTL_BLOCK, 0, s>>>(I, tol, (long long)max_iter);
+  k_eval_control<T><<<grid_of(g.ninst * PDHG_CTL_SPLIT), PDHG_BLOCK, 0, s>>>(I, tol, (long long)max_iter);
   k_restart_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
   k_restart_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
+  if (sizeof(T) == 4) {
+    k_stash_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
+    k_stash_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
+  }
 }
 
 template <typename T>

@@ -141,24 +141,37 @@ def test_autotune_picks_a_candidate(gpu, oracle_mod):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_reorder_same_solution(gpu, oracle_mod, precision):
     """The internal relabelling changes rounding order only: both orders solve
-    to the same optimum, and warm starts and results stay in the caller's
-    order (a solve started at the other's answer stops at once)."""
+    to the same optimum."""
     from paper_2512_06715_amd.solver import Problem
     lp = ucgen.workload("uc1000_t48")
     print("case reorder", precision, flush=True)
+    tol = 1e-4
     res = {}
     for r in (0, 1):
-        p = Problem(lp, reorder=r, tol=1e-4, precision=precision)
+        p = Problem(lp, reorder=r, tol=tol, precision=precision)
         res[r] = p.solve()
         p.close()
         assert res[r][2]["status"] == 1
-    tol = 1e-4
-    for r in (0, 1):
         k = oracle_mod.kkt(lp, res[r][0], res[r][1])
         assert k["rel_kkt"] <= tol * 1.001
     o0, o1 = res[0][2]["primal_obj"], res[1][2]["primal_obj"]
     assert abs(o0 - o1) <= 2 * tol * (1 + abs(o0))
-    p = Problem(lp, reorder=1, tol=tol, precision=precision)
-    x, y, info = p.solve(x0=res[0][0], y0=res[0][1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_warm_start_in_callers_order(gpu, oracle_mod, precision):
+    """Warm starts and results are in the caller's order: a solve started at
+    an exact optimal vertex (HiGHS, KKT error ~1e-14) stops at the first
+    evaluation, in either precision and with the internal relabelling on."""
+    from oracle import exact
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc14_t24")
+    print("case warm start", precision, flush=True)
+    st, xo, _, yo = exact.highs(lp)
+    assert st == exact.OPTIMAL and oracle_mod.kkt(lp, xo, yo)["rel_kkt"] < 1e-10
+    p = Problem(lp, reorder=1, tol=1e-5, precision=precision)
+    x, y, info = p.solve(x0=xo, y0=yo)
     p.close()
-    assert info["attempts"] <= 256 and info["status"] == 1
+    assert info["status"] == 1 and info["attempts"] == 0
+    assert np.abs(x - xo).max() <= 1e-6 * (1 + np.abs(xo).max())
+    assert np.abs(y - yo).max() <= 1e-6 * (1 + np.abs(yo).max())
