@@ -50,7 +50,7 @@ def kernel_bytes(kind: str, m: int, n: int, nnz: int, vb: int) -> int:
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("iterate.hip", "internal.h"):
+    for f in ("attempt.hip", "device.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2512_06715_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

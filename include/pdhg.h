@@ -228,11 +228,13 @@ int pdhg_locality_order(int64_t m, int64_t n, const int32_t *row_ptr, const int3
 int pdhg_get_partition(pdhg_handle *h, int *out);
 
 /* Run `attempts` more attempts from the handle's current iterate (the state
- * the last pdhg_solve left) with HIP events around each kernel on the
- * library's stream, and report average milliseconds per launch:
- * ms_out[0] primal step (A'y row-dot + projection, long columns included),
- * ms_out[1] dual step (Ax row-dot + projection, long rows included),
- * ms_out[2] step control, ms_out[3] whole attempt.  Precision as set up. */
+ * the last pdhg_solve left) on the library's stream, each kernel launched
+ * with start/stop events that take its dispatch's own timestamps, and report
+ * average milliseconds per launch: ms_out[0] primal step (A'y row-dot +
+ * projection, long columns included), ms_out[1] dual step (Ax row-dot +
+ * projection, long rows included), ms_out[2] step control, ms_out[3] whole
+ * attempt (first kernel's start to last kernel's end, launch gaps
+ * included).  Precision as set up. */
 int pdhg_time_kernels(pdhg_handle *h, int attempts, double *ms_out);
 
 #ifdef __cplusplus

@@ -1701,25 +1701,22 @@ int time_kernels(pdhg_handle *h, int attempts, double *ms) {
   Groups g{};
   RC(upload_group<T>(h, h->grp, one, act, g));
   const Inst<T> *dI = dev_insts<T>(h->grp);
-  hipEvent_t ev[4];
+  // the start/stop events of each kernel carry its dispatch's own timestamps
+  hipEvent_t ev[6];
   for (auto &e : ev) HC(hipEventCreate(&e));
   double acc[4] = {0, 0, 0, 0};
   for (int a = 0; a < attempts; a++) {
-    HC(hipEventRecord(ev[0], h->hs));
-    launch_primal<T>(dI, g, h->hs);
-    HC(hipEventRecord(ev[1], h->hs));
-    launch_dual<T>(dI, g, h->hs);
-    HC(hipEventRecord(ev[2], h->hs));
-    launch_control<T>(dI, g, h->hs);
-    HC(hipEventRecord(ev[3], h->hs));
+    launch_primal<T>(dI, g, h->hs, ev[0], ev[1]);
+    launch_dual<T>(dI, g, h->hs, ev[2], ev[3]);
+    launch_control<T>(dI, g, h->hs, ev[4], ev[5]);
     HK();
-    HC(hipEventSynchronize(ev[3]));
+    HC(hipEventSynchronize(ev[5]));
     float t;
     for (int q = 0; q < 3; q++) {
-      HC(hipEventElapsedTime(&t, ev[q], ev[q + 1]));
+      HC(hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]));
       acc[q] += t;
     }
-    HC(hipEventElapsedTime(&t, ev[0], ev[3]));
+    HC(hipEventElapsedTime(&t, ev[0], ev[5]));
     acc[3] += t;
   }
   for (auto &e : ev) HC(hipEventDestroy(e));

@@ -1,0 +1,342 @@
+// The two kernels of one PDHG attempt (Chambolle-Pock step of the paper's
+// "PDHG Background" section, box projection on x, sign-cone projection on
+// >= rows, PDLP adaptive step), each an SpMV with the projection fused:
+//   k_primal   x' = proj_[l,u](x - tau (c - A'y))            (row-dot over A')
+//   k_dual     y' = proj_Y(y + sigma (b - (2 A x' - A x)))   (row-dot over A,
+//              A x' cached for the next attempt)
+// Both write per-workgroup partials of the step-size test; the control kernel
+// (iterate.hip) reduces them.  Every kernel is grouped: one launch serves all
+// instances of a batch.
+#include "device.h"
+
+#include <hip/hip_ext.h>
+
+namespace {
+
+// Both kernels walk tiles of PDHG_TILE rows of a CSR matrix (A for the dual
+// step, the stored A' for the primal step).  A tile's nonzeros are one
+// contiguous range, so the workgroup streams column indices and values with
+// consecutive lanes on consecutive nonzeros (coalesced), forms the products
+// with the gathered vector into LDS, and each lane then sums its own row from
+// LDS in CSR order.  Tiles whose nonzeros do not fit the LDS buffer fall back
+// to one lane per row (as does the `direct` partition).  Rows longer than
+// `long_seg` get a workgroup each (the first blocks of the instance).  Each
+// workgroup covers `tpb` consecutive tiles and writes one partial per reduced
+// quantity.
+
+#define TILE_CAP (8 * PDHG_TILE)  // nonzeros of a tile staged in LDS
+#define TILE_U 4       // nonzeros per lane loaded before their gathers
+
+// Streams read exactly once per launch bypass the cache hierarchy's reuse
+// policy so that L2 keeps the gathered vector windows.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const AS_G T *p) {
+  return __builtin_nontemporal_load(p);
+}
+
+// Iterate stores of the attempt kernels.
+template <typename T>
+__device__ __forceinline__ void st_out(AS_G T *p, T v) {
+  *p = v;
+}
+
+// Products are rounded on their own (never fused into the sum), so the
+// LDS-staged and the per-row paths give bit-identical row sums.
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+
+// Dot product s = sum_k v[k] x[idx[k]] of this lane's row i (rows r0 + lane of
+// a PDHG_TILE-row tile whose nonzeros are [base, top)), summed in CSR order.  The
+// row's bounds are loaded here, after the tile's index/value stream has been
+// issued, so the gathers wait only on that stream.  `mine` returns whether
+// the row is valid and short enough to be this tile's.  Every lane of the
+// workgroup must call it.
+template <typename T>
+__device__ __forceinline__ T tile_rowdot(const AS_G int32_t *ptr, const AS_G int32_t *idx,
+                                         const AS_G T *v, const AS_G T *x, int64_t i, bool valid,
+                                         int base, int top, int long_seg, T *lds, int direct,
+                                         bool &mine) {
+  const int cnt = top - base;
+  T s = 0;
+  int rs = 0, re = 0;
+  if (!direct && cnt <= TILE_CAP) {
+    for (int k0 = 0; k0 < cnt; k0 += TILE_U * PDHG_TILE) {
+      int id[TILE_U];
+      T vv[TILE_U];
+#pragma unroll
+      for (int q = 0; q < TILE_U; q++) {
+        int k = k0 + q * PDHG_TILE + (int)threadIdx.x;
+        int kc = base + (k < cnt ? k : cnt - 1);
+        id[q] = ld_stream(idx + kc);
+        vv[q] = ld_stream(v + kc);
+      }
+      if (k0 == 0 && valid) {
+        rs = ptr[i];
+        re = ptr[i + 1];
+      }
+#pragma unroll
+      for (int q = 0; q < TILE_U; q++) {
+        int k = k0 + q * PDHG_TILE + (int)threadIdx.x;
+        // lanes past the tile write a slot of their own past the staged range
+        lds[k < cnt ? k : TILE_CAP + (int)threadIdx.x] = mul_rn(vv[q], x[id[q]]);
+      }
+    }
+    if (cnt == 0 && valid) {
+      rs = ptr[i];
+      re = ptr[i + 1];
+    }
+    __syncthreads();
+    mine = valid && (re - rs <= long_seg);
+    if (mine)
+      for (int k = rs - base; k < re - base; k++) s += lds[k];
+    __syncthreads();
+  } else {
+    if (valid) {
+      rs = ptr[i];
+      re = ptr[i + 1];
+    }
+    mine = valid && (re - rs <= long_seg);
+    if (mine) {
+      for (int k0 = rs; k0 < re; k0 += TILE_U) {
+        int id[TILE_U];
+        T vv[TILE_U];
+#pragma unroll
+        for (int q = 0; q < TILE_U; q++) {
+          int kc = k0 + q < re ? k0 + q : re - 1;
+          id[q] = idx[kc];
+          vv[q] = v[kc];
+        }
+#pragma unroll
+        for (int q = 0; q < TILE_U; q++) {
+          T p = mul_rn(vv[q], x[id[q]]);
+          if (k0 + q < re) s += p;
+        }
+      }
+    }
+  }
+  return s;
+}
+
+// One long row (a workgroup of its own): FP64 sum of the products.
+template <typename T>
+__device__ __forceinline__ double long_rowdot(const AS_G int32_t *idx, const AS_G T *v,
+                                              const AS_G T *x, int s, int e) {
+  double acc[1] = {0.0};
+  for (int k = s + threadIdx.x; k < e; k += PDHG_TILE) acc[0] += (double)mul_rn(v[k], x[idx[k]]);
+  double tot[1];
+  block_reduce<1, PDHG_TILE>(acc, 0u, tot);
+  return tot[0];
+}
+
+// Bit-packed mask of one wave's 64 consecutive rows (tile rows are
+// 64-aligned); bits are OR-ed in, so long rows can add theirs separately.
+__device__ inline void record_mask(uint64_t *mask, int64_t row0_of_wave, bool bit) {
+  uint64_t bits = __ballot(bit);
+  if ((threadIdx.x & 63) == 0 && bits) atomicOr((unsigned long long *)&mask[row0_of_wave >> 6],
+                                                 (unsigned long long)bits);
+}
+
+__device__ inline void record_bit(uint64_t *mask, int64_t row) {
+  atomicOr((unsigned long long *)&mask[row >> 6], 1ull << (row & 63));
+}
+
+// Primal update of column j from t = (A'y)_j; returns whether the pre-clamp
+// value lies strictly inside the box.  Folds the previous iterate into the
+// running sum when an accepted weight is pending.
+template <typename T>
+__device__ __forceinline__ bool primal_finish(int64_t j, T t, T tau, T xj, T cj, T lj, T uj,
+                                              T xsj, AS_G T *xn, AS_G T *xs, double pend,
+                                              int fresh, double &d2) {
+  T xt = xj - tau * (cj - t);
+  T xv = clamp_box<T>(xt, lj, uj);
+  st_out(xn + j, xv);
+  double d = (double)xv - (double)xj;
+  d2 += d * d;
+  if (pend > 0.0) st_out(xs + j, (fresh ? (T)0 : xsj) + (T)pend * xj);
+  return xt > lj && xt < uj;
+}
+
+template <typename T>
+__global__ __launch_bounds__(PDHG_TILE) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ T lds[TILE_CAP + PDHG_TILE];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = find_inst_u(g.p_primal, g.ninst, b);
+  const int lb = b - cin(g.p_primal)[inst];
+  const AS_C IterView<T> &w = cin(I)[inst].w;
+  const AS_C CtlState *st = cin(cin(I)[inst].st);
+  const int cur = st->cur;
+  const T tau = (T)(st->eta / st->omega);
+  const double pend = st->pending;
+  const int fresh = st->fresh;
+  const bool fold_read = pend > 0.0 && !fresh;
+  const int64_t n = w.n;
+  const AS_G int32_t *cp = gin(w.cp), *ri = gin(w.ri);
+  const AS_G T *vt = gin(w.vt), *c = gin(w.c), *l = gin(w.l), *u = gin(w.u);
+  const AS_G T *x = gin((const T *)w.X[cur]), *y = gin((const T *)w.Y[cur]);
+  AS_G T *xn = gout(w.X[cur ^ 1]);
+  AS_G T *xs = gout(w.XS);
+  uint64_t *mask = w.mask_x ? w.mask_x + (st->k - w.mask_k0) * ((n + 63) >> 6) : nullptr;
+  double d2[1] = {0.0};
+  if (lb < w.n_long_cols) {
+    int64_t j = gin(w.long_cols)[lb];
+    const AS_C int32_t *cpc = cin(w.cp);
+    double t = long_rowdot<T>(ri, vt, y, cpc[j], cpc[j + 1]);
+    if (threadIdx.x == 0) {
+      double dd = 0.0;
+      bool in = primal_finish<T>(j, (T)t, tau, x[j], c[j], l[j], u[j],
+                                 fold_read ? xs[j] : (T)0, xn, xs, pend, fresh, dd);
+      gout(w.part_dx2)[lb] = dd;
+      if (mask && in) record_bit(mask, j);
+    }
+    return;
+  }
+  const int tpb = w.tpb_cols, long_seg = w.long_seg, direct = w.direct;
+  int64_t t0 = (int64_t)(lb - w.n_long_cols) * tpb;
+  int64_t ntiles = (n + PDHG_TILE - 1) / PDHG_TILE;
+  int64_t t1 = t0 + tpb < ntiles ? t0 + tpb : ntiles;
+  const AS_C int32_t *cpc = cin(w.cp);
+  for (int64_t t = t0; t < t1; t++) {
+    int64_t r0 = t * PDHG_TILE;
+    int64_t rend = r0 + PDHG_TILE < n ? r0 + PDHG_TILE : n;
+    int64_t j = r0 + threadIdx.x;
+    // the column's own loads go out with the tile bounds, before the SpMV
+    int base = cpc[r0], top = cpc[rend];
+    T xj = 0, cj = 0, lj = 0, uj = 0, xsj = 0;
+    if (j < n) {
+      xj = x[j];
+      cj = ld_stream(c + j);
+      lj = ld_stream(l + j);
+      uj = ld_stream(u + j);
+      if (fold_read) xsj = xs[j];
+    }
+    bool mine;
+    T s = tile_rowdot<T>(cp, ri, vt, y, j, j < n, base, top, long_seg, lds, direct, mine);
+    bool in = false;
+    if (mine) in = primal_finish<T>(j, s, tau, xj, cj, lj, uj, xsj, xn, xs, pend, fresh, d2[0]);
+    if (mask) record_mask(mask, j & ~(int64_t)63, in);
+  }
+  double out[1];
+  block_reduce<1, PDHG_TILE>(d2, 0u, out);
+  if (threadIdx.x == 0) gout(w.part_dx2)[lb] = out[0];
+}
+
+// Dual update of row i from s = (A x')_i; returns whether the dual is
+// unprojected (equality row or value > 0).
+template <typename T>
+__device__ __forceinline__ bool dual_finish(int64_t i, T s, T sigma, T yi, T axi, T bi, uint8_t ki,
+                                            T ysi, AS_G T *yn, AS_G T *axn, AS_G T *ys,
+                                            double pend, int fresh, double &dy2, double &inter) {
+  T yv = yi + sigma * (bi - (s + s - axi));
+  bool in = (ki == 0) || (yv > (T)0);
+  if (ki == 1 && yv < (T)0) yv = (T)0;
+  st_out(yn + i, yv);
+  st_out(axn + i, s);
+  double dy = (double)yv - (double)yi;
+  dy2 += dy * dy;
+  inter += dy * ((double)s - (double)axi);
+  if (pend > 0.0) st_out(ys + i, (fresh ? (T)0 : ysi) + (T)pend * yi);
+  return in;
+}
+
+template <typename T>
+__global__ __launch_bounds__(PDHG_TILE) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ T lds[TILE_CAP + PDHG_TILE];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = find_inst_u(g.p_dual, g.ninst, b);
+  const int lb = b - cin(g.p_dual)[inst];
+  const AS_C IterView<T> &w = cin(I)[inst].w;
+  const AS_C CtlState *st = cin(cin(I)[inst].st);
+  const int cur = st->cur;
+  const T sigma = (T)(st->eta * st->omega);
+  const double pend = st->pending;
+  const int fresh = st->fresh;
+  const bool fold_read = pend > 0.0 && !fresh;
+  const int64_t m = w.m;
+  const AS_G int32_t *rp = gin(w.rp), *ci = gin(w.ci);
+  const AS_G T *v = gin(w.v), *bb = gin(w.b);
+  const AS_G uint8_t *kind = gin(w.kind);
+  const AS_G T *xn = gin((const T *)w.X[cur ^ 1]);
+  const AS_G T *y = gin((const T *)w.Y[cur]), *ax = gin((const T *)w.AX[cur]);
+  AS_G T *yn = gout(w.Y[cur ^ 1]), *axn = gout(w.AX[cur ^ 1]), *ys = gout(w.YS);
+  uint64_t *mask = w.mask_y ? w.mask_y + (st->k - w.mask_k0) * ((m + 63) >> 6) : nullptr;
+  const int64_t G = w.grid_rows;
+  double acc[2] = {0.0, 0.0};
+  if (lb < w.n_long_rows) {
+    int64_t i = gin(w.long_rows)[lb];
+    const AS_C int32_t *rpc = cin(w.rp);
+    double t = long_rowdot<T>(ci, v, xn, rpc[i], rpc[i + 1]);
+    if (threadIdx.x == 0) {
+      bool in = dual_finish<T>(i, (T)t, sigma, y[i], ax[i], bb[i], kind[i],
+                               fold_read ? ys[i] : (T)0, yn, axn, ys, pend, fresh, acc[0], acc[1]);
+      gout(w.part_dy)[lb] = acc[0];
+      gout(w.part_dy)[G + lb] = acc[1];
+      if (mask && in) record_bit(mask, i);
+    }
+    return;
+  }
+  const int tpb = w.tpb_rows, long_seg = w.long_seg, direct = w.direct;
+  int64_t t0 = (int64_t)(lb - w.n_long_rows) * tpb;
+  int64_t ntiles = (m + PDHG_TILE - 1) / PDHG_TILE;
+  int64_t t1 = t0 + tpb < ntiles ? t0 + tpb : ntiles;
+  const AS_C int32_t *rpc = cin(w.rp);
+  for (int64_t t = t0; t < t1; t++) {
+    int64_t r0 = t * PDHG_TILE;
+    int64_t rend = r0 + PDHG_TILE < m ? r0 + PDHG_TILE : m;
+    int64_t i = r0 + threadIdx.x;
+    int base = rpc[r0], top = rpc[rend];
+    T yi = 0, axi = 0, bi = 0, ysi = 0;
+    uint8_t ki = 0;
+    if (i < m) {
+      yi = y[i];
+      axi = ax[i];
+      bi = ld_stream(bb + i);
+      ki = kind[i];
+      if (fold_read) ysi = ys[i];
+    }
+    bool mine;
+    T s = tile_rowdot<T>(rp, ci, v, xn, i, i < m, base, top, long_seg, lds, direct, mine);
+    bool in = false;
+    if (mine)
+      in = dual_finish<T>(i, s, sigma, yi, axi, bi, ki, ysi, yn, axn, ys, pend, fresh, acc[0],
+                          acc[1]);
+    if (mask) record_mask(mask, i & ~(int64_t)63, in);
+  }
+  double out[2];
+  block_reduce<2, PDHG_TILE>(acc, 0u, out);
+  if (threadIdx.x == 0) {
+    gout(w.part_dy)[lb] = out[0];
+    gout(w.part_dy)[G + lb] = out[1];
+  }
+}
+
+}  // namespace
+
+// With events, the kernel is launched through hipExtLaunchKernelGGL, whose
+// start/stop events take the dispatch's own timestamps (the kernel's
+// duration, without launch gaps).
+template <typename T>
+void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
+                   hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_primal<T>, dim3(grid_of(g.n_primal)), dim3(PDHG_TILE), 0, s, t0, t1, 0,
+                          I, g);
+  else
+    k_primal<T><<<grid_of(g.n_primal), PDHG_TILE, 0, s>>>(I, g);
+}
+
+template <typename T>
+void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_dual<T>, dim3(grid_of(g.n_dual)), dim3(PDHG_TILE), 0, s, t0, t1, 0, I,
+                          g);
+  else
+    k_dual<T><<<grid_of(g.n_dual), PDHG_TILE, 0, s>>>(I, g);
+}
+
+#define INST(T)                                                                             \
+  template void launch_primal<T>(const Inst<T> *, const Groups &, hipStream_t, hipEvent_t,    \
+                                 hipEvent_t);                                              \
+  template void launch_dual<T>(const Inst<T> *, const Groups &, hipStream_t, hipEvent_t,      \
+                               hipEvent_t);
+INST(double)
+INST(float)

@@ -176,11 +176,14 @@ struct Groups {
 // ---------------------------------------------------------------------------
 // launchers (iterate.hip); every launch covers all instances of the group
 template <typename T>
-void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s);
+void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);
 template <typename T>
-void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s);
+void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);
 template <typename T>
-void launch_control(const Inst<T> *I, const Groups &g, hipStream_t s);
+void launch_control(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);
 template <typename T>
 void launch_attempt(const Inst<T> *I, const Groups &g, hipStream_t s);
 template <typename T>
