@@ -1,0 +1,94 @@
+"""The paper-scale case (6717 buses, 1100 units, 9000 lines, 96 periods;
+m = 2.03M, n = 3.22M, nnz = 7.19M) in the configuration bench.py times:
+device-resident inputs, internal locality ordering on.  The oracle cannot
+solve it in test time (tens of attempts per second), so it is checked on what
+the oracle can compute at this size: the preprocessing bit for bit, a
+64-attempt trajectory, and the KKT error of the returned points."""
+import numpy as np
+import pytest
+
+from paper_2512_06715_amd import ucgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lp():
+    return ucgen.workload("uc6717_t96")
+
+
+def device_lp(lp):
+    import torch
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).cuda()
+
+    class DevLP:
+        m, n = lp.m, lp.n
+        row_ptr = dev(lp.row_ptr, torch.int32)
+        col_idx = dev(lp.col_idx, torch.int32)
+        val = dev(lp.val, torch.float64)
+        row_kind = dev(lp.row_kind, torch.uint8)
+        b = dev(lp.b, torch.float64)
+        c = dev(lp.c, torch.float64)
+        l = dev(lp.l, torch.float64)
+        u = dev(lp.u, torch.float64)
+    return DevLP
+
+
+def test_fullsize_setup_bit_exact(gpu, oracle_mod, lp):
+    from paper_2512_06715_amd.solver import Problem
+    print("case uc6717_t96 setup", flush=True)
+    p = Problem(device_lp(lp), device=True, precision="mixed")
+    g = p.export_setup()
+    p.close()
+    assert np.array_equal(g["var_kind"], oracle_mod.var_kind(lp.l, lp.u))
+    vs, Dr, Dc = oracle_mod.scale(lp, 10, True)
+    assert np.array_equal(g["val_s"].view(np.uint64), vs.view(np.uint64))
+    assert np.array_equal(g["Dr"].view(np.uint64), Dr.view(np.uint64))
+    assert np.array_equal(g["Dc"].view(np.uint64), Dc.view(np.uint64))
+    cp, ri, vt = oracle_mod.transpose(lp.m, lp.n, lp.row_ptr, lp.col_idx, vs)
+    assert np.array_equal(g["colptr"], cp)
+    assert np.array_equal(g["rowidx"], ri)
+    assert np.array_equal(g["valT"].view(np.uint64), vt.view(np.uint64))
+
+
+@pytest.mark.parametrize("K,bound", [(1, 1e-12), (48, 1e-9)])
+def test_fullsize_trajectory_fp64(gpu, oracle_mod, lp, K, bound):
+    """K FP64 attempts from the origin against the oracle's.  The step-size
+    test divides by dy'(A dx), a sum over 2M rows with heavy cancellation
+    whose value depends on the summation order (a tree here, a sequential
+    loop in the oracle); measured at this size, eta differs in the 12th digit
+    after 8 attempts and x, y by 2e-14 after 1, 4e-12 after 32, 2e-11 after
+    48 and 2e-9 after 64 attempts, with or without the locality ordering."""
+    from paper_2512_06715_amd.solver import Problem
+    print("case uc6717_t96", K, "attempts", flush=True)
+    p = Problem(device_lp(lp), device=True, max_iter=K, tol=1e-12)
+    x, y, info = p.solve()
+    p.close()
+    x, y = x.cpu().numpy(), y.cpu().numpy()
+    xo, yo, io = oracle_mod.pdhg(lp, tol=1e-12, max_iter=K)
+    assert info["attempts"] == io["attempts"] == K
+    assert info["accepted"] == io["accepted"]
+    scale = 1 + np.linalg.norm(xo) + np.linalg.norm(yo)
+    err = np.linalg.norm(x - xo) + np.linalg.norm(y - yo)
+    assert err <= bound * scale, err / scale
+
+
+def test_fullsize_mixed_solve(gpu, oracle_mod, lp):
+    """The bench workload: mixed precision to relative KKT 1e-4.  The oracle
+    recomputes the KKT error of the returned point; the FP64 GPU solve of the
+    same LP gives the objective it is compared with."""
+    from paper_2512_06715_amd.solver import Problem
+    print("case uc6717_t96 mixed solve", flush=True)
+    dl = device_lp(lp)
+    res = {}
+    for prec in ("mixed", "fp64"):
+        p = Problem(dl, device=True, precision=prec, tol=1e-4)
+        x, y, info = p.solve()
+        p.close()
+        assert info["status"] == 1, (prec, info)
+        k = oracle_mod.kkt(lp, x.cpu().numpy(), y.cpu().numpy())
+        print(prec, "attempts", info["attempts"], "kkt", k["rel_kkt"], "obj", k["pobj"], flush=True)
+        assert k["rel_kkt"] <= 1.001e-4, (prec, k)
+        assert abs(k["rel_kkt"] - info["rel_kkt"]) <= 1e-6 * max(1.0, k["rel_kkt"])
+        res[prec] = k["pobj"]
+    assert abs(res["mixed"] - res["fp64"]) <= 5e-4 * abs(res["fp64"])
