@@ -102,9 +102,9 @@ def fp64_compare(lp, args):
 
 
 def batch_run(args):
-    """Batched LPs/s on small instances of the batched workload (500-2000 buses,
-    24 periods, mixed precision, KKT 1e-4 each) against the same instances
-    solved one at a time with pdhg_solve (setup excluded from both)."""
+    """Batched LPs/s on the small instances of the batched workload (500-2000
+    buses, 24 periods, mixed precision, KKT 1e-4 each) against the same
+    instances solved one at a time with pdhg_solve (setup excluded from both)."""
     import torch
     from paper_2512_06715_amd import ucgen
     from paper_2512_06715_amd.solver import Problem, solve_batch
@@ -125,11 +125,46 @@ def batch_run(args):
         ts += time.perf_counter() - t0
         p.close()
     n = len(lps)
-    return dict(batch=dict(instances=n, solved=ok, lps_per_s=round(n / tb, 4),
-                           sequential_lps_per_s=round(n / ts, 4), speedup=round(ts / tb, 3),
-                           batch_s=round(tb, 3), sequential_s=round(ts, 3),
-                           workload="small instances 0..%d of the batched workload "
-                                    "(N ~ U{500..2000}, T=24), mixed, KKT 1e-4" % (n - 1)))
+    return dict(instances=n, solved=ok, lps_per_s=round(n / tb, 4),
+                sequential_lps_per_s=round(n / ts, 4), speedup=round(ts / tb, 3),
+                batch_s=round(tb, 3), sequential_s=round(ts, 3),
+                workload="small instances 0..%d of the batched workload "
+                         "(N ~ U{500..2000}, T=24, distinct matrices), mixed, KKT 1e-4" % (n - 1))
+
+
+def batch_big_run(args):
+    """Batched LPs/s on branch-and-bound variants of the 4224-bus, 48-period
+    LP (0-20% of the commitments fixed; one shared matrix) against the same
+    variants solved one at a time (a batch of one)."""
+    import torch
+    from paper_2512_06715_amd import ucgen
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    lp = ucgen.workload("uc4224_t48")
+    base = Problem(lp, tol=args.tol, precision="mixed", max_iter=args.max_iter)
+    insts = []
+    for k in range(args.batch_big):
+        v = ucgen.fix_commitments(lp, seed=100 + k)
+        insts.append(dict(base=0, fix_idx=v.meta["fix_idx"], fix_val=v.meta["fix_val"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = solve_batch([base], insts)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    ok = sum(1 for r in res if r[2]["status"] == 1)
+    ts = 0.0
+    for d in insts:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solve_batch([base], [d])
+        torch.cuda.synchronize()
+        ts += time.perf_counter() - t0
+    base.close()
+    n = len(insts)
+    return dict(instances=n, solved=ok, lps_per_s=round(n / tb, 4),
+                sequential_lps_per_s=round(n / ts, 4), speedup=round(ts / tb, 3),
+                batch_s=round(tb, 3), sequential_s=round(ts, 3),
+                workload="%d branch-and-bound variants of uc4224_t48 (4224 buses, 700 units, "
+                         "5800 lines, 48 periods), mixed, KKT 1e-4" % n)
 
 
 def adjoint_run():
@@ -163,8 +198,11 @@ def main():
     ap.add_argument("--workload", default="uc6717_t96")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--no-compare-fp64", action="store_true")
-    ap.add_argument("--batch-small", type=int, default=8,
+    ap.add_argument("--batch-small", type=int, default=32,
                     help="small instances of the batched workload (0 skips the batch run)")
+    ap.add_argument("--batch-big", type=int, default=0,
+                    help="branch-and-bound variants of the 4224-bus, 48-period LP to batch "
+                         "(one shared matrix; 0 skips this run)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
@@ -259,7 +297,10 @@ def main():
         extra.update(fp64_compare(lp, args))
     if args.batch_small > 0:
         print("[bench] batched solve ...", file=sys.stderr, flush=True)
-        extra.update(batch_run(args))
+        extra["batch"] = batch_run(args)
+    if args.batch_big > 0:
+        print("[bench] batched branch-and-bound variants ...", file=sys.stderr, flush=True)
+        extra["batch_big"] = batch_big_run(args)
     if not args.no_adjoint:
         print("[bench] unrolled solve + adjoint ...", file=sys.stderr, flush=True)
         extra.update(adjoint_run())

@@ -628,6 +628,14 @@ int upload_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
   g.n_cols = pre[3 * c1 + na];
   g.n_lrows = pre[4 * c1 + na];
   g.n_lcols = pre[5 * c1 + na];
+  g.interleave = na > 1;
+  for (int k = 1; k < na && g.interleave; k++) {
+    const IterView<T> &a = sel[0].w, &b = sel[k].w;
+    g.interleave = a.rp == b.rp && a.cp == b.cp && a.v == b.v && a.vt == b.vt &&
+                   a.grid_rows == b.grid_rows && a.grid_cols == b.grid_cols &&
+                   a.tpb_rows == b.tpb_rows && a.tpb_cols == b.tpb_cols &&
+                   a.n_long_rows == b.n_long_rows && a.n_long_cols == b.n_long_cols;
+  }
   return PDHG_OK;
 }
 

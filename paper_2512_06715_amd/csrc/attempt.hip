@@ -160,8 +160,8 @@ template <typename T>
 __global__ __launch_bounds__(PDHG_TILE) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int inst = find_inst_u(g.p_primal, g.ninst, b);
-  const int lb = b - cin(g.p_primal)[inst];
+  const int inst = g.interleave ? b % g.ninst : find_inst_u(g.p_primal, g.ninst, b);
+  const int lb = g.interleave ? b / g.ninst : b - cin(g.p_primal)[inst];
   const AS_C IterView<T> &w = cin(I)[inst].w;
   const AS_C CtlState *st = cin(cin(I)[inst].st);
   const int cur = st->cur;
@@ -242,8 +242,8 @@ template <typename T>
 __global__ __launch_bounds__(PDHG_TILE) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int inst = find_inst_u(g.p_dual, g.ninst, b);
-  const int lb = b - cin(g.p_dual)[inst];
+  const int inst = g.interleave ? b % g.ninst : find_inst_u(g.p_dual, g.ninst, b);
+  const int lb = g.interleave ? b / g.ninst : b - cin(g.p_dual)[inst];
   const AS_C IterView<T> &w = cin(I)[inst].w;
   const AS_C CtlState *st = cin(cin(I)[inst].st);
   const int cur = st->cur;

@@ -171,6 +171,11 @@ struct Groups {
   const int32_t *p_rows, *p_cols;    // one block per 256 rows / columns
   const int32_t *p_lrows, *p_lcols;  // one block per long row / column
   int n_primal, n_dual, n_rows, n_cols, n_lrows, n_lcols;
+  // 1: every instance has the same matrix and attempt grids; the attempt
+  // kernels then number blocks tile-major (block b is local block b / ninst
+  // of instance b % ninst), so the instances' blocks of one tile run back to
+  // back on one XCD and its L2 serves the shared matrix tile once
+  int interleave;
 };
 
 // ---------------------------------------------------------------------------
