@@ -67,20 +67,28 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_control(const Inst<T> *__restric
     last = atomicAdd(&gst->ticket, 1) == PDHG_CTL_SPLIT - 1;
   }
   __syncthreads();
-  if (!last || threadIdx.x != 0) return;
+  if (!last) return;
+  // last workgroup: every lane fetches one slice sum or one state word after
+  // its acquire fence (one round trip), then lane 0 combines them in order
+  __shared__ double sl[3 * PDHG_CTL_SPLIT];
+  __shared__ unsigned long long sw[sizeof(CtlState) / 8];
   __threadfence();
+  if (threadIdx.x < 3 * PDHG_CTL_SPLIT) sl[threadIdx.x] = gin((const double *)stage)[threadIdx.x];
+  else if (threadIdx.x - 3 * PDHG_CTL_SPLIT < sizeof(CtlState) / 8)
+    sw[threadIdx.x - 3 * PDHG_CTL_SPLIT] =
+        gin((const unsigned long long *)gst)[threadIdx.x - 3 * PDHG_CTL_SPLIT];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   double dx2 = 0.0, dy2 = 0.0, inter = 0.0;
   for (int p = 0; p < PDHG_CTL_SPLIT; p++) {
-    dx2 += __hip_atomic_load(stage + 3 * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    dy2 += __hip_atomic_load(stage + 3 * p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    inter += __hip_atomic_load(stage + 3 * p + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    dx2 += sl[3 * p];
+    dy2 += sl[3 * p + 1];
+    inter += sl[3 * p + 2];
   }
   CtlState st;
   {
-    const AS_G unsigned long long *src = gin((const unsigned long long *)gst);
     unsigned long long *dst = (unsigned long long *)&st;
-#pragma unroll
-    for (int q = 0; q < (int)(sizeof(CtlState) / 8); q++) dst[q] = src[q];
+    for (int q = 0; q < (int)(sizeof(CtlState) / 8); q++) dst[q] = sw[q];
   }
   st.ticket = 0;
   double eta = st.eta, omega = st.omega;
@@ -376,14 +384,33 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const Inst<T> *__re
     last = atomicAdd(&gst->ticket, 1) == PDHG_CTL_SPLIT - 1;
   }
   __syncthreads();
-  if (!last || threadIdx.x != 0) return;
+  if (!last) return;
+  // last workgroup: the slice results and the state words fetched in
+  // parallel after the acquire fence, then combined in slice order by lane 0
+  constexpr int NS = NQ * PDHG_CTL_SPLIT, NW = NS + (int)(sizeof(CtlState) / 8);
+  static_assert(NW <= 2 * PDHG_BLOCK, "two words per lane");
+  __shared__ double sl[NS];
+  __shared__ unsigned long long sw[sizeof(CtlState) / 8];
   __threadfence();
+  {
+    const AS_G unsigned long long *src_s = gin((const unsigned long long *)stage);
+    const AS_G unsigned long long *src_w = gin((const unsigned long long *)gst);
+    const int t0 = threadIdx.x, t1 = threadIdx.x + PDHG_BLOCK;
+    unsigned long long a0 = t0 < NS ? src_s[t0] : (t0 < NW ? src_w[t0 - NS] : 0ull);
+    unsigned long long a1 = t1 < NS ? src_s[t1] : (t1 < NW ? src_w[t1 - NS] : 0ull);
+    if (t0 < NS) sl[t0] = __longlong_as_double((long long)a0);
+    else if (t0 < NW) sw[t0 - NS] = a0;
+    if (t1 < NS) sl[t1] = __longlong_as_double((long long)a1);
+    else if (t1 < NW) sw[t1 - NS] = a1;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   double rq[EV_ROWQ], cq[EV_COLQ];
   for (int q = 0; q < NQ; q++) {
     bool mx = q < EV_ROWQ ? ((ROWMAX >> q) & 1) : ((COLMAX >> (q - EV_ROWQ)) & 1);
     double a = 0.0;
     for (int p = 0; p < PDHG_CTL_SPLIT; p++) {
-      double t = __hip_atomic_load(stage + NQ * p + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      double t = sl[NQ * p + q];
       a = mx ? fmax(a, t) : a + t;
     }
     if (q < EV_ROWQ)
@@ -393,10 +420,8 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const Inst<T> *__re
   }
   CtlState stv;
   {
-    const AS_G unsigned long long *src = gin((const unsigned long long *)gst);
     unsigned long long *dst = (unsigned long long *)&stv;
-#pragma unroll
-    for (int q = 0; q < (int)(sizeof(CtlState) / 8); q++) dst[q] = src[q];
+    for (int q = 0; q < (int)(sizeof(CtlState) / 8); q++) dst[q] = sw[q];
   }
   stv.ticket = 0;
   CtlState *st = &stv;
