@@ -332,6 +332,7 @@ def main():
                     m=lp.m, n=lp.n, nnz=lp.nnz, tol=args.tol, precision=args.precision),
         time_to_tol_s=round(elapsed / args.steps, 3),
         attempts_per_solve=last["attempts"],
+        attempts_fp32=last.get("attempts_fp32"),
         status=last["status_name"],
         rel_kkt=last["rel_kkt"],
         primal_obj=last["primal_obj"],

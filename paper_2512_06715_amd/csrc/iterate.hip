@@ -245,24 +245,111 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_spmv_long(const Inst<T> *__
   if (threadIdx.x == 0) s.out[i] = tot[0];
 }
 
-// Row-space KKT pieces for the current point and the average:
+// Row dots of the evaluation, one 256-row tile of a FP64 CSR matrix per
+// workgroup: s0 = sum_k v[k] x0[idx[k]] and, when x1 is given,
+// s1 = sum_k v[k] x1[idx[k]], for this lane's row i, in CSR order with each
+// product rounded on its own.  The tile's indices and values are loaded once
+// and both products staged in LDS (tiles past EV_TILE_CAP nonzeros use
+// per-lane loops).  `mine` is false for rows longer than long_seg, whose
+// products a workgroup of their own computes beforehand.  Every lane must
+// call it; lds holds 2 (EV_TILE_CAP + PDHG_BLOCK) doubles.
+#define EV_TILE_CAP (8 * PDHG_BLOCK)
+template <typename X0>
+__device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, const double *v_,
+                                    const X0 *x0_, const double *x1_, int64_t i, bool valid,
+                                    int base, int top, int long_seg, double *lds, double &s0,
+                                    double &s1, bool &mine) {
+  const AS_G int32_t *ptr = gin(ptr_), *idx = gin(idx_);
+  const AS_G double *v = gin(v_), *x1 = gin(x1_);
+  const AS_G X0 *x0 = gin(x0_);
+  const int cnt = top - base;
+  const bool two = x1_ != nullptr;
+  double *lds1 = lds + EV_TILE_CAP + PDHG_BLOCK;
+  int rs = 0, re = 0;
+  s0 = s1 = 0.0;
+  if (cnt <= EV_TILE_CAP) {
+    for (int k0 = 0; k0 < cnt; k0 += 4 * PDHG_BLOCK) {
+      int id[4];
+      double vv[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        int k = k0 + q * PDHG_BLOCK + (int)threadIdx.x;
+        int kc = base + (k < cnt ? k : cnt - 1);
+        id[q] = __builtin_nontemporal_load(idx + kc);
+        vv[q] = __builtin_nontemporal_load(v + kc);
+      }
+      if (k0 == 0 && valid) {
+        rs = ptr[i];
+        re = ptr[i + 1];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        int k = k0 + q * PDHG_BLOCK + (int)threadIdx.x;
+        int slot = k < cnt ? k : EV_TILE_CAP + (int)threadIdx.x;
+        lds[slot] = __dmul_rn(vv[q], (double)x0[id[q]]);
+        if (two) lds1[slot] = __dmul_rn(vv[q], x1[id[q]]);
+      }
+    }
+    if (cnt == 0 && valid) {
+      rs = ptr[i];
+      re = ptr[i + 1];
+    }
+    __syncthreads();
+    mine = valid && (re - rs <= long_seg);
+    if (mine) {
+      for (int k = rs - base; k < re - base; k++) s0 += lds[k];
+      if (two)
+        for (int k = rs - base; k < re - base; k++) s1 += lds1[k];
+    }
+    __syncthreads();
+  } else {
+    if (valid) {
+      rs = ptr[i];
+      re = ptr[i + 1];
+    }
+    mine = valid && (re - rs <= long_seg);
+    if (mine)
+      for (int k = rs; k < re; k++) {
+        s0 += __dmul_rn(v[k], (double)x0[idx[k]]);
+        if (two) s1 += __dmul_rn(v[k], x1[idx[k]]);
+      }
+  }
+}
+
+// Row-space KKT pieces for the current point and the average, with A x_avg
+// computed here (and kept for a restart to the average):
 // [0] ||r_p||^2 scaled [1] ||r_p||^2 unscaled [2] ||r_p||_inf unscaled
 // [3] b'y [4] ||y - y_last||^2, then the same five for the average.
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ double lds[2 * (EV_TILE_CAP + PDHG_BLOCK)];
   GROUP_BLOCK(p_rows)
   int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   bool avg = have_avg(st, e.use_average);
+  double axa = 0.0;
+  if (avg) {
+    int64_t r0 = (int64_t)lb * PDHG_BLOCK, rend = r0 + PDHG_BLOCK < e.m ? r0 + PDHG_BLOCK : e.m;
+    double unused;
+    bool mine;
+    eval_rowdots<double>(e.rp, e.ci, e.v, e.XA, nullptr, i, i < e.m, e.rp[r0], e.rp[rend],
+                         e.long_seg, lds, axa, unused, mine);
+    if (i < e.m) {
+      if (mine)
+        e.AXA[i] = axa;
+      else
+        axa = e.AXA[i];  // long row: its own workgroup computed it
+    }
+  }
   double q[EV_ROWQ];
 #pragma unroll
   for (int t = 0; t < EV_ROWQ; t++) q[t] = 0.0;
   if (i < e.m) {
     int cur = st->cur;
-    double bi = e.b[i], dr = e.Dr[i], yl = e.YL[i];
-    bool ge = e.kind[i] == 1;
+    double bi = gin(e.b)[i], dr = gin(e.Dr)[i], yl = gin((const double *)e.YL)[i];
+    bool ge = gin(e.kind)[i] == 1;
     for (int p = 0; p < (avg ? 2 : 1); p++) {
-      double yi = p ? e.YA[i] : (double)e.Y[cur][i];
-      double axi = p ? e.AXA[i] : (double)e.AX[cur][i];
+      double yi = p ? gin((const double *)e.YA)[i] : (double)gin((const T *)e.Y[cur])[i];
+      double axi = p ? axa : (double)gin((const T *)e.AX[cur])[i];
       double r = bi - axi;
       if (ge && r < 0.0) r = 0.0;
       double ru = r / dr;
@@ -293,25 +380,38 @@ __device__ inline double bound_term(uint8_t vk, double lam, double l, double u) 
   return t;
 }
 
-// Column-space KKT pieces: [0] ||r_d||^2 scaled [1] ||r_d||^2 unscaled
+// Column-space KKT pieces, with A'y and A'y_avg computed here:
+// [0] ||r_d||^2 scaled [1] ||r_d||^2 unscaled
 // [2] ||r_d||_inf unscaled [3] bound part of the dual objective [4] c'x
 // [5] ||x - x_last||^2, then the same six for the average.
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ double lds[2 * (EV_TILE_CAP + PDHG_BLOCK)];
   GROUP_BLOCK(p_cols)
   int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   bool avg = have_avg(st, e.use_average);
+  double aty[2];
+  {
+    int64_t c0 = (int64_t)lb * PDHG_BLOCK, cend = c0 + PDHG_BLOCK < e.n ? c0 + PDHG_BLOCK : e.n;
+    bool mine;
+    eval_rowdots<T>(e.cp, e.ri, e.vt, e.Y[st->cur], avg ? e.YA : nullptr, j, j < e.n, e.cp[c0],
+                    e.cp[cend], e.long_seg, lds, aty[0], aty[1], mine);
+    if (j < e.n && !mine) {  // long column: its own workgroup computed it
+      aty[0] = e.ATY[j];
+      if (avg) aty[1] = e.ATYA[j];
+    }
+  }
   double q[EV_COLQ];
 #pragma unroll
   for (int t = 0; t < EV_COLQ; t++) q[t] = 0.0;
   if (j < e.n) {
     int cur = st->cur;
-    double cj = e.c[j], dc = e.Dc[j], lj = e.l[j], uj = e.u[j], xl = e.XL[j];
-    uint8_t vk = e.vk[j];
+    double cj = gin(e.c)[j], dc = gin(e.Dc)[j], lj = gin(e.l)[j], uj = gin(e.u)[j];
+    double xl = gin((const double *)e.XL)[j];
+    uint8_t vk = gin(e.vk)[j];
     for (int p = 0; p < (avg ? 2 : 1); p++) {
-      double xj = p ? e.XA[j] : (double)e.X[cur][j];
-      double aty = p ? e.ATYA[j] : e.ATY[j];
-      double lam = cj - aty;
+      double xj = p ? gin((const double *)e.XA)[j] : (double)gin((const T *)e.X[cur])[j];
+      double lam = cj - aty[p];
       double pl = proj_lambda(vk, lam);
       double rd = lam - pl;
       double rdu = rd / dc;
@@ -905,9 +1005,13 @@ void launch_evaluate(const Inst<T> *I, const Groups &g, double tol, int64_t max_
                      hipStream_t s) {
   k_avg_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
   k_avg_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
-  launch_products<T>(I, g, SP_ATY, s);
-  launch_products<T>(I, g, SP_AXA, s);
-  launch_products<T>(I, g, SP_ATYA, s);
+  // long rows and columns first (a workgroup each); the row and column
+  // kernels compute the other products themselves
+  if (g.n_lcols) {
+    k_eval_spmv_long<T><<<grid_of(g.n_lcols), PDHG_BLOCK, 0, s>>>(I, g, SP_ATY);
+    k_eval_spmv_long<T><<<grid_of(g.n_lcols), PDHG_BLOCK, 0, s>>>(I, g, SP_ATYA);
+  }
+  if (g.n_lrows) k_eval_spmv_long<T><<<grid_of(g.n_lrows), PDHG_BLOCK, 0, s>>>(I, g, SP_AXA);
   k_eval_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
   k_eval_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
   k_eval_control<T><<<grid_of(g.ninst * PDHG_CTL_SPLIT), PDHG_BLOCK, 0, s>>>(I, tol, (long long)max_iter);

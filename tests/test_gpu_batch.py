@@ -58,3 +58,34 @@ def test_batch_rejects_bad_instances(gpu):
     with pytest.raises(_lib.PdhgError):
         solve_batch([p], [dict(base=0, fix_idx=np.array([base.n + 5]), fix_val=np.array([1.0]))])
     p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("count", [3, 11])
+def test_shared_matrix_batch_matches_standalone(gpu, oracle_mod, precision, count):
+    """Node variants of one LP (one shared matrix): the attempt kernels number
+    their blocks tile-major so the instances' blocks of a tile share L2; the
+    arithmetic is the one-instance kernels', so every instance reproduces its
+    standalone solve bit for bit in FP64, also as the active set shrinks."""
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    base = ucgen.random_uc(14, 5, 20, 6, 1.0, seed=21)
+    nodes = node_variants(base, count - 1, 7)
+    print("case shared-matrix batch", precision, count, flush=True)
+    opts = dict(tol=1e-6, max_iter=300000, precision=precision)
+    p = Problem(base, **opts)
+    insts = [dict(base=0)] + [dict(base=0, fix_idx=v.meta["fix_idx"], fix_val=v.meta["fix_val"])
+                              for v in nodes]
+    res = solve_batch([p], insts)
+    p.close()
+    for k, (x, y, info) in enumerate(res):
+        lp = ([base] + nodes)[k]
+        assert info["status"] == 1, (k, info)
+        assert oracle_mod.kkt(lp, x, y)["rel_kkt"] <= 1.001e-6
+        q = Problem(lp, **opts)
+        xs, ys, info_s = q.solve()
+        q.close()
+        assert info_s["attempts"] == info["attempts"], k
+        if precision == "fp64":
+            assert np.array_equal(xs, x) and np.array_equal(ys, y), k
+        else:
+            np.testing.assert_allclose(x, xs, rtol=0, atol=1e-9 * (1 + np.abs(xs).max()))
