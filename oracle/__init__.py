@@ -74,6 +74,9 @@ def lib():
                                    [ctypes.c_int, ctypes.c_int, i64, ctypes.c_double,
                                     ctypes.c_double] + [P] * 6)
         L.orc_unrolled.restype = ctypes.c_int
+        L.orc_implied_bounds.argtypes = [i64, i64] + [P] * 5 + [ctypes.c_int, P, P]
+        L.orc_implied_bounds.restype = i64
+        L.orc_safe_bound.argtypes = [i64, i64] + [P] * 10
         _lib = L
     return _lib
 
@@ -89,6 +92,31 @@ def _arrs(lp):
     kind = np.ascontiguousarray(lp.row_kind, np.uint8)
     f = lambda a: np.ascontiguousarray(a, np.float64)
     return rp, ci, v, kind, f(lp.b), f(lp.c), f(lp.l), f(lp.u)
+
+
+def implied_bounds(lp, passes=64):
+    """(lo, hi): l, u with infinite entries replaced where bound propagation
+    over the rows finds a finite bound (widened to cover rounding)."""
+    rp, ci, v, kind, b, c, l, u = _arrs(lp)
+    lo, hi = l.copy(), u.copy()
+    lib().orc_implied_bounds(lp.m, lp.n, _p(rp), _p(ci), _p(v), _p(kind), _p(b), int(passes),
+                             _p(lo), _p(hi))
+    return lo, hi
+
+
+def safe_bound(lp, y, lo=None, hi=None) -> dict:
+    """Weak-duality lower bound on the optimum from y (y_i >= 0 enforced on
+    >= rows), with the bounds lo, hi (default: the implied bounds)."""
+    rp, ci, v, kind, b, c, l, u = _arrs(lp)
+    if lo is None or hi is None:
+        lo, hi = implied_bounds(lp)
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    out = np.zeros(4)
+    lib().orc_safe_bound(lp.m, lp.n, _p(rp), _p(ci), _p(v), _p(kind), _p(b), _p(c), _p(lo),
+                         _p(hi), _p(y), _p(out))
+    return dict(bound=out[0], value=out[1], allowance=out[2], infinite_terms=int(out[3]))
 
 
 def validate(lp) -> int:

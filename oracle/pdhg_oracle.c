@@ -679,3 +679,113 @@ int orc_unrolled(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   free(Axe); free(Adxe);
   return ORC_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* implied bounds and the safe dual bound                                 */
+
+/* Feasibility-based bound propagation over the rows (an = row gives
+ * a'x >= b and a'x <= b, a >= row only the first): with the other variables
+ * at the ends of their current bounds, each row bounds each of its
+ * variables.  Sweeps run over the rows in index order and use bounds found
+ * earlier in the same sweep.  Only infinite bounds are replaced, and a
+ * derived bound r/a is widened to r/a -+ 1e-9 (1 + |r/a|) to cover its
+ * rounding.  lo, hi: in the bounds l, u; out the implied bounds.  Returns
+ * the number of bounds made finite. */
+int64_t orc_implied_bounds(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci,
+                           const double *v, const uint8_t *kind, const double *b,
+                           int passes, double *lo, double *hi) {
+  int64_t made = 0;
+  (void)n;
+  for (int pass = 0; pass < passes; pass++) {
+    int64_t before = made;
+    for (int64_t i = 0; i < m; i++) {
+      /* activity bounds of row i: finite parts and counts of infinite terms */
+      double minf = 0.0, maxf = 0.0;
+      int64_t mininf = 0, maxinf = 0;
+      for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+        double a = v[k], L = lo[ci[k]], U = hi[ci[k]];
+        double tmin = a > 0.0 ? a * L : a * U, tmax = a > 0.0 ? a * U : a * L;
+        if (isinf(tmin)) mininf++; else minf += tmin;
+        if (isinf(tmax)) maxinf++; else maxf += tmax;
+      }
+      for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+        int32_t j = ci[k];
+        double a = v[k], L = lo[j], U = hi[j];
+        if (a == 0.0) continue;
+        double tmin = a > 0.0 ? a * L : a * U, tmax = a > 0.0 ? a * U : a * L;
+        /* a'x >= b: a_j x_j >= b - (max activity of the others) */
+        int64_t oinf = maxinf - (isinf(tmax) ? 1 : 0);
+        if (oinf == 0) {
+          double r = (b[i] - (maxf - (isinf(tmax) ? 0.0 : tmax))) / a;
+          double w = 1e-9 * (1.0 + fabs(r));
+          if (a > 0.0 && isinf(lo[j])) { lo[j] = r - w; made++; }
+          if (a < 0.0 && isinf(hi[j])) { hi[j] = r + w; made++; }
+        }
+        if (kind[i] == 0) { /* a'x <= b: a_j x_j <= b - (min activity of the others) */
+          int64_t oinf2 = mininf - (isinf(tmin) ? 1 : 0);
+          if (oinf2 == 0) {
+            double r = (b[i] - (minf - (isinf(tmin) ? 0.0 : tmin))) / a;
+            double w = 1e-9 * (1.0 + fabs(r));
+            if (a > 0.0 && isinf(hi[j])) { hi[j] = r + w; made++; }
+            if (a < 0.0 && isinf(lo[j])) { lo[j] = r - w; made++; }
+          }
+        }
+      }
+    }
+    if (made == before) break;
+  }
+  return made;
+}
+
+/* A lower bound on the LP optimum from any y (weak duality).  With y_i
+ * replaced by max(y_i, 0) on >= rows, every feasible x has
+ *   c'x = b'y + y'(Ax - b) + lambda'x >= b'y + sum_j lambda_j x_j,
+ * lambda = c - A'y, and x_j in [lo_j, hi_j] bounds the last sum from below
+ * by lambda_j lo_j (lambda_j > 0) or lambda_j hi_j (lambda_j < 0).  A
+ * nonzero lambda_j that needs an infinite bound makes the bound -INFINITY.
+ * The computed value is lowered by 2 (K + 4) eps S, with eps = 2^-53,
+ * K = n + m + (longest column) and S = sum_i |b_i y_i| +
+ * sum_j |bound_j| (|c_j| + sum_i |a_ij y_i|), which exceeds the rounding
+ * error of the sums.  out: [0] bound, [1] b'y + sum of bound terms (before
+ * the allowance), [2] the allowance, [3] number of infinite terms. */
+void orc_safe_bound(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci,
+                    const double *v, const uint8_t *kind, const double *b, const double *c,
+                    const double *lo, const double *hi, const double *y, double *out) {
+  double *aty = calloc((size_t)n, sizeof(double));
+  double *atyabs = calloc((size_t)n, sizeof(double));
+  int64_t *clen = calloc((size_t)n, sizeof(int64_t));
+  double by = 0.0, byabs = 0.0;
+  for (int64_t i = 0; i < m; i++) {
+    double yi = (kind[i] == 1 && y[i] < 0.0) ? 0.0 : y[i];
+    by += b[i] * yi;
+    byabs += fabs(b[i] * yi);
+    for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+      aty[ci[k]] += v[k] * yi;
+      atyabs[ci[k]] += fabs(v[k] * yi);
+      clen[ci[k]]++;
+    }
+  }
+  double terms = 0.0, sabs = 0.0;
+  int64_t ninf = 0, kmax = 0;
+  for (int64_t j = 0; j < n; j++) {
+    double lam = c[j] - aty[j];
+    double bnd = lam > 0.0 ? lo[j] : (lam < 0.0 ? hi[j] : 0.0);
+    if (clen[j] > kmax) kmax = clen[j];
+    if (lam == 0.0) continue;
+    if (isinf(bnd)) {
+      ninf++;
+      continue;
+    }
+    terms += lam * bnd;
+    sabs += fabs(bnd) * (fabs(c[j]) + atyabs[j]);
+  }
+  double val = by + terms;
+  double allow = 2.0 * (double)(n + m + kmax + 4) * ldexp(1.0, -53) * (byabs + sabs);
+  out[0] = ninf ? -INFINITY : val - allow;
+  out[1] = val;
+  out[2] = allow;
+  out[3] = (double)ninf;
+  free(aty);
+  free(atyabs);
+  free(clen);
+}

@@ -307,3 +307,100 @@ def test_unrolled_jvp_matches_finite_differences(oracle_mod):
     Vm, _ = oracle_mod.unrolled(lp_m, K, eta, omega)
     fd = (Vp - Vm) / (2 * h)
     assert abs(fd - dV) <= 1e-6 * (1 + abs(dV))
+
+
+def test_implied_bounds_hand_example(oracle_mod):
+    """x1 - x2 = 0 with 0 <= x2 <= 3 and x1 free bounds x1 to [0, 3]; 2 x3 + x2 >= 1
+    with x3 >= 0 bounds nothing new (x3 has no finite upper limit from it)."""
+    A = np.array([[1.0, -1.0, 0.0], [0.0, 1.0, 2.0]])
+    lp = ucgen.dense_to_lp(A, np.array([0, 1], np.uint8), np.array([0.0, 1.0]), np.zeros(3),
+                           np.array([-np.inf, 0.0, 0.0]), np.array([np.inf, 3.0, np.inf]))
+    lo, hi = oracle_mod.implied_bounds(lp)
+    assert lo[0] == 0.0 - 1e-9 and hi[0] == 3.0 + 1e-9 * 4.0
+    assert lo[1] == 0.0 and hi[1] == 3.0 and lo[2] == 0.0 and np.isinf(hi[2])
+
+
+def test_safe_bound_is_a_lower_bound_on_toys(oracle_mod):
+    """Weak duality against vertex enumeration: for any y (projected on >=
+    rows) the bound is at most the optimum; at the simplex's optimal duals
+    it equals the optimum up to its rounding allowance."""
+    rng = np.random.default_rng(17)
+    n_exact = n_finite = 0
+    for t in range(400):
+        m, n = int(rng.integers(1, 5)), int(rng.integers(1, 5))
+        lp = feasible_toy(rng, m, n)
+        s1, x1, o1 = exact.vertex_enum(lp)
+        if s1 != exact.OPTIMAL:
+            continue
+        lo, hi = oracle_mod.implied_bounds(lp)
+        assert np.all(x1 >= lo - 1e-12) and np.all(x1 <= hi + 1e-12), t
+        for k in range(5):
+            y = rng.standard_normal(m) * 3
+            r = oracle_mod.safe_bound(lp, y)
+            assert r["bound"] <= o1 + 1e-12 * (1 + abs(o1)), (t, k, r, o1)
+            n_finite += np.isfinite(r["bound"])
+        s2, x2, o2, y2 = exact.simplex(lp)
+        r = oracle_mod.safe_bound(lp, y2)
+        if np.isfinite(r["bound"]):
+            assert r["bound"] <= o1 + 1e-12 * (1 + abs(o1))
+            assert abs(r["bound"] - o1) <= 1e-9 * (1 + abs(o1)), (t, r, o1)
+            n_exact += 1
+    assert n_exact > 100 and n_finite > 100
+
+
+def test_safe_bound_on_uc_with_implied_angle_bounds(oracle_mod):
+    """UC relaxation: the bus angles are free; propagation through the flow
+    rows from the fixed reference angle bounds them, so the bound at HiGHS's
+    duals is finite and within 1e-9 of the optimum (and below it)."""
+    lp = ucgen.workload("uc14_t24")
+    st, x, obj, y = exact.highs(lp)
+    lo, hi = oracle_mod.implied_bounds(lp)
+    meta = lp.meta
+    N, G, L, T = meta["N"], meta["G"], meta["L"], meta["T"]
+    per = 4 * G + 3 * N + L + 1
+    theta = np.concatenate([np.arange(t * per + 4 * G, t * per + 4 * G + N) for t in range(T)])
+    assert np.all(np.isfinite(lo[theta])) and np.all(np.isfinite(hi[theta]))
+    assert np.all(x >= lo - 1e-9) and np.all(x <= hi + 1e-9)
+    r = oracle_mod.safe_bound(lp, y)
+    assert np.isfinite(r["bound"]) and r["bound"] <= obj
+    assert obj - r["bound"] <= 1e-9 * abs(obj), (obj, r)
+    # without the implied bounds the free angles make it -inf
+    r0 = oracle_mod.safe_bound(lp, y, lp.l, lp.u)
+    assert r0["bound"] == -np.inf or r0["infinite_terms"] == 0
+
+
+def test_implied_bounds_and_safe_bound_with_free_variables(oracle_mod):
+    """Toys with a free variable tied to boxed ones by an equality row: the
+    propagated bounds contain every optimal point found by enumeration, and
+    the safe bound at the simplex's duals is finite and equals the optimum."""
+    rng = np.random.default_rng(29)
+    checked = 0
+    for t in range(300):
+        m, n = int(rng.integers(1, 4)), int(rng.integers(2, 5))
+        base = feasible_toy(rng, m, n)
+        A = np.zeros((m + 1, n + 1))
+        for i in range(m):
+            A[i, base.col_idx[base.row_ptr[i]:base.row_ptr[i + 1]]] = \
+                base.val[base.row_ptr[i]:base.row_ptr[i + 1]]
+        w = rng.integers(-2, 3, n).astype(float)
+        A[m, :n] = w
+        A[m, n] = -1.0                       # x_free = w'x
+        A[:m, n] = rng.integers(-2, 3, m)    # the free variable also enters the other rows
+        kind = np.append(base.row_kind, 0).astype(np.uint8)
+        x0 = base.l + rng.random(n) * (base.u - base.l)
+        b = np.append(base.b + A[:m, n] * (w @ x0), 0.0)
+        b[:m] = np.where(base.row_kind == 0, A[:m, :n] @ x0 + A[:m, n] * (w @ x0), b[:m])
+        c = np.append(base.c, rng.integers(-3, 4))
+        lp = ucgen.dense_to_lp(A, kind, b, c, np.append(base.l, -np.inf),
+                               np.append(base.u, np.inf))
+        s2, x2, o2, y2 = exact.simplex(lp)
+        if s2 != exact.OPTIMAL:
+            continue
+        lo, hi = oracle_mod.implied_bounds(lp)
+        assert np.isfinite(lo[n]) and np.isfinite(hi[n]), t
+        assert lo[n] - 1e-9 <= x2[n] <= hi[n] + 1e-9, t
+        r = oracle_mod.safe_bound(lp, y2)
+        assert np.isfinite(r["bound"]) and r["bound"] <= o2 + 1e-12 * (1 + abs(o2)), (t, r, o2)
+        assert abs(r["bound"] - o2) <= 1e-8 * (1 + abs(o2)), (t, r, o2)
+        checked += 1
+    assert checked > 100
