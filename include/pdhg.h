@@ -119,6 +119,13 @@ typedef struct {
   double rel_primal, rel_dual, rel_gap, rel_kkt;
   double eta, omega;      /* final step size and primal weight (scaled space) */
   double setup_s, solve_s;
+  /* A lower bound on the LP optimum that holds whatever the accuracy of the
+   * returned y (weak duality): b'y + sum_j min over x_j in [lo_j, hi_j] of
+   * lambda_j x_j with lambda = c - A'y, lowered by an allowance that exceeds
+   * the rounding of the sums; [lo, hi] are l, u with infinite ends replaced
+   * by implied bounds (pdhg_implied_bounds) where the LP's rows give them.
+   * -INFINITY when a nonzero lambda_j needs an infinite bound. */
+  double dual_bound;
 } pdhg_info;
 
 typedef struct pdhg_handle pdhg_handle;
@@ -145,13 +152,18 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x,
  * load scenario).  Instances whose base handle is the same share that
  * handle's preprocessed matrix; b, c, l, u override the base's vectors when
  * non-null (original space, same memory kind as the base LP), and the n_fix
- * (index, value) pairs fix variables (l = u = value) on top of the bounds. */
+ * (index, value) pairs fix variables (l = u = value) on top of the bounds.
+ * x0[n], y0[m] (nullable, same memory kind) warm-start the instance, e.g.
+ * a child node from its parent's solution.  The dual bound of an instance
+ * uses the base's implied bounds only when b, l and u are not overridden
+ * (fixings only tighten the bounds the implied ones were derived from). */
 typedef struct {
   int32_t base;
   const double *b, *c, *l, *u;
   const int32_t *fix_idx;
   const double *fix_val;
   int64_t n_fix;
+  const double *x0, *y0;
 } pdhg_instance;
 
 /* Device workspace bytes for pdhg_solve_batch with these instances. */
@@ -213,6 +225,13 @@ int pdhg_export_setup(pdhg_handle *h, uint8_t *var_kind, int32_t *colptr,
  * (transpose = 1, x[m], out[n]) with the solver's FP64 SpMV kernels; host
  * memory. */
 int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out);
+
+/* The implied bounds pdhg_setup derived for the dual bound (host memory,
+ * caller's order, original units): lo[n], hi[n] are l, u with infinite ends
+ * replaced where propagation over the rows bounds them (widened by
+ * 1e-9 (1 + |bound|)).  After pdhg_update with a new b they no longer apply
+ * and this returns l, u. */
+int pdhg_implied_bounds(pdhg_handle *h, double *lo, double *hi);
 
 /* The locality ordering pdhg_setup applies when opts.reorder = 1, for a
  * canonical CSR structure in host memory (host code only, no GPU needed):

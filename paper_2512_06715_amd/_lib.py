@@ -42,7 +42,8 @@ class PdhgInfo(ctypes.Structure):
                 ("accepted", c_i64), ("restarts", c_i64), ("attempts_fp32", c_i64),
                 ("primal_obj", c_dbl), ("dual_obj", c_dbl), ("rel_primal", c_dbl),
                 ("rel_dual", c_dbl), ("rel_gap", c_dbl), ("rel_kkt", c_dbl),
-                ("eta", c_dbl), ("omega", c_dbl), ("setup_s", c_dbl), ("solve_s", c_dbl)]
+                ("eta", c_dbl), ("omega", c_dbl), ("setup_s", c_dbl), ("solve_s", c_dbl),
+                ("dual_bound", c_dbl)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -52,7 +53,7 @@ class PdhgInfo(ctypes.Structure):
 
 class PdhgInstance(ctypes.Structure):
     _fields_ = [("base", ctypes.c_int32), ("b", vp), ("c", vp), ("l", vp), ("u", vp),
-                ("fix_idx", vp), ("fix_val", vp), ("n_fix", c_i64)]
+                ("fix_idx", vp), ("fix_val", vp), ("n_fix", c_i64), ("x0", vp), ("y0", vp)]
 
 
 # name -> (restype, argtypes)
@@ -78,6 +79,7 @@ SIGNATURES = {
     "pdhg_time_kernels": (c_int, [vp, c_int, ctypes.POINTER(c_dbl)]),
     "pdhg_get_partition": (c_int, [vp, ctypes.POINTER(c_int)]),
     "pdhg_locality_order": (c_int, [c_i64, c_i64, vp, vp, vp, vp]),
+    "pdhg_implied_bounds": (c_int, [vp, vp, vp]),
 }
 
 _lib = None

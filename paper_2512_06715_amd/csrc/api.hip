@@ -140,6 +140,12 @@ struct pdhg_handle {
   int32_t *rperm = nullptr, *cperm = nullptr, *cinv = nullptr;
   int32_t *perm_buf = nullptr;
   std::vector<int32_t> h_rperm, h_cperm;  // host copies
+  // implied bounds for the dual bound: device (scaled, internal order) and
+  // host (caller's order, original units), and the caller's l, u
+  double *ilo = nullptr, *ihi = nullptr;
+  std::vector<double> h_ilo, h_ihi, h_l, h_u;
+  bool impl_valid = false;
+  double bound_allow = 0.0;
   double *scratch;
   int nscratch = 0;
   int *err;
@@ -223,6 +229,8 @@ size_t layout(pdhg_handle *h, void *base) {
   h->kind = cv.take<uint8_t>(m);
   h->vk = cv.take<uint8_t>(n);
   h->perm_buf = h->o.reorder ? cv.take<int32_t>(m + 2 * n) : nullptr;
+  h->ilo = cv.take<double>(n);
+  h->ihi = cv.take<double>(n);
   if (mixed) {
     h->vf = cv.take<float>(std::max<int64_t>(nnz, 1));
     h->vtf = cv.take<float>(std::max<int64_t>(nnz, 1));
@@ -429,6 +437,76 @@ int reorder_problem(pdhg_handle *h) {
   return PDHG_OK;
 }
 
+// Implied bounds of the caller's problem (original order and units), from
+// the host copy of the LP; the longest column sets the rounding allowance of
+// the dual bound.
+int setup_implied_bounds(pdhg_handle *h, const pdhg_lp *lp) {
+  const int64_t m = h->m, n = h->n, nnz = h->nnz;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v, b;
+  std::vector<uint8_t> kind;
+  const int32_t *prp = lp->row_ptr, *pci = lp->col_idx;
+  const double *pv = lp->val, *pb = lp->b;
+  const uint8_t *pk = lp->row_kind;
+  h->h_l.resize(n);
+  h->h_u.resize(n);
+  if (h->on_device) {
+    rp.resize(m + 1);
+    ci.resize(std::max<int64_t>(nnz, 1));
+    v.resize(std::max<int64_t>(nnz, 1));
+    b.resize(m);
+    kind.resize(m);
+    HC(hipMemcpyAsync(rp.data(), lp->row_ptr, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost,
+                      h->hs));
+    if (nnz) {
+      HC(hipMemcpyAsync(ci.data(), lp->col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost,
+                        h->hs));
+      HC(hipMemcpyAsync(v.data(), lp->val, sizeof(double) * nnz, hipMemcpyDeviceToHost, h->hs));
+    }
+    HC(hipMemcpyAsync(b.data(), lp->b, sizeof(double) * m, hipMemcpyDeviceToHost, h->hs));
+    HC(hipMemcpyAsync(kind.data(), lp->row_kind, m, hipMemcpyDeviceToHost, h->hs));
+    HC(hipMemcpyAsync(h->h_l.data(), lp->l, sizeof(double) * n, hipMemcpyDeviceToHost, h->hs));
+    HC(hipMemcpyAsync(h->h_u.data(), lp->u, sizeof(double) * n, hipMemcpyDeviceToHost, h->hs));
+    HC(hipStreamSynchronize(h->hs));
+    prp = rp.data();
+    pci = ci.data();
+    pv = v.data();
+    pb = b.data();
+    pk = kind.data();
+  } else {
+    std::copy(lp->l, lp->l + n, h->h_l.begin());
+    std::copy(lp->u, lp->u + n, h->h_u.begin());
+  }
+  h->h_ilo = h->h_l;
+  h->h_ihi = h->h_u;
+  implied_bounds(m, prp, pci, pv, pk, pb, 64, h->h_ilo.data(), h->h_ihi.data());
+  std::vector<int64_t> clen(n, 0);
+  int64_t kmax = 0;
+  for (int64_t k = 0; k < nnz; k++) kmax = std::max(kmax, ++clen[pci[k]]);
+  h->bound_allow = 2.0 * (double)(n + m + kmax + 4) * std::ldexp(1.0, -53);
+  return PDHG_OK;
+}
+
+// The implied bounds on the device: internal order, scaled like l and u.
+int upload_implied_bounds(pdhg_handle *h) {
+  const int64_t n = h->n;
+  double *tl = h->it.XA, *tu = h->it.ATY, *tg = h->it.ATYA;  // free during setup
+  HC(hipMemcpyAsync(tl, h->h_ilo.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->hs));
+  HC(hipMemcpyAsync(tu, h->h_ihi.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->hs));
+  if (h->cperm) {
+    launch_gather_f64(tg, tl, h->cperm, n, h->hs);
+    launch_copy_f64(tl, tg, n, h->hs);
+    launch_gather_f64(tg, tu, h->cperm, n, h->hs);
+    launch_copy_f64(tu, tg, n, h->hs);
+  }
+  // (the scaled-c output of this launcher goes to the free buffer tg)
+  launch_scale_vectors(nullptr, tl, tl, tu, h->Dr, h->Dc, 0, n, nullptr, tg, h->ilo, h->ihi, h->hs);
+  HK();
+  HC(hipStreamSynchronize(h->hs));  // the host arrays stay, but keep setup ordered
+  h->impl_valid = true;
+  return PDHG_OK;
+}
+
 // Rows and columns longer than the partition's threshold get a workgroup each.
 int build_long_lists(pdhg_handle *h) {
   std::vector<int32_t> lr, lc;
@@ -532,6 +610,9 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.part_cols = b.part_cols;
   e.ev_stage = b.ev_stage;
   e.xbest = sizeof(T) == 4 ? b.X[0] : nullptr;
+  e.ilo = h->impl_valid ? h->ilo : nullptr;
+  e.ihi = h->impl_valid ? h->ihi : nullptr;
+  e.bound_allow = h->bound_allow;
   e.ybest = sizeof(T) == 4 ? b.Y[0] : nullptr;
   e.use_average = h->o.use_average;
   e.restart = h->o.restart;
@@ -775,6 +856,7 @@ void fill_info(pdhg_info *info, const CtlState &s, int status, int64_t attempts_
   info->omega = s.omega;
   info->setup_s = setup_s;
   info->solve_s = solve_s;
+  info->dual_bound = s.dual_bound;
 }
 
 // Solve a group of prepared instances (start points and result pointers set)
@@ -1040,6 +1122,7 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
       if (herr & VERR_BOUNDS) return fail(PDHG_ERR_BOUNDS, "invalid variable bounds");
       if (herr & VERR_NONFINITE) return fail(PDHG_ERR_NONFINITE, "non-finite entry in A, b or c");
     }
+    RC(setup_implied_bounds(h, lp));
     launch_var_kind(h->l0, h->u0, n, h->vk, h->hs);
     launch_transpose(h->rp, h->ci, h->v, m, n, nnz, h->cp, h->ri, h->vt, h->tmp_next, h->scan_tmp,
                      h->hs);
@@ -1055,6 +1138,7 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
                          h->hs);
     HK();
     if (h->o.reorder) RC(reorder_problem(h));
+    RC(upload_implied_bounds(h));
     // long rows and columns (handled by a workgroup each in the iteration)
     h->hrp.resize(m + 1);
     h->hcp.resize(n + 1);
@@ -1343,6 +1427,7 @@ struct BatchPlan {
   std::vector<int32_t *> fix_idx;
   std::vector<double *> fix_val;
   std::vector<double *> xo, yo;  // staging for host results
+  std::vector<double *> x0, y0;  // staging for host warm starts
   GroupDev gd;
 };
 
@@ -1357,7 +1442,7 @@ size_t batch_layout(pdhg_handle *const *hs, const pdhg_instance *inst, int batch
   P.vk.assign(batch, nullptr);
   P.fix_idx.assign(batch, nullptr);
   P.fix_val.assign(batch, nullptr);
-  P.xo = P.yo = nd;
+  P.xo = P.yo = P.x0 = P.y0 = nd;
   for (int k = 0; k < batch; k++) {
     const pdhg_handle *h = hs[inst[k].base];
     int64_t m = h->m, n = h->n;
@@ -1392,6 +1477,8 @@ size_t batch_layout(pdhg_handle *const *hs, const pdhg_instance *inst, int batch
     if (!h->on_device) {
       P.xo[k] = cv.take<double>(n);
       P.yo[k] = cv.take<double>(m);
+      if (inst[k].x0) P.x0[k] = cv.take<double>(n);
+      if (inst[k].y0) P.y0[k] = cv.take<double>(m);
     }
   }
   carve_group(cv, P.gd, batch);
@@ -1539,6 +1626,23 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
     HC(hipStreamSynchronize(h->hs));  // the base's scratch is reused by the next instance
     i64[k] = make_inst<double>(hb, d, ib);
     i32[k] = make_inst<float>(hb, d, ib);
+    if (q.b || q.l || q.u) {  // the base's implied bounds assume its b, l, u
+      i64[k].e.ilo = i64[k].e.ihi = nullptr;
+      i32[k].e.ilo = i32[k].e.ihi = nullptr;
+    }
+    const double *wx = q.x0, *wy = q.y0;  // warm start, caller's order
+    if (!hb->on_device) {
+      if (q.x0) {
+        HC(hipMemcpyAsync(P.x0[k], q.x0, sizeof(double) * n, hipMemcpyHostToDevice, h->hs));
+        wx = P.x0[k];
+      }
+      if (q.y0) {
+        HC(hipMemcpyAsync(P.y0[k], q.y0, sizeof(double) * m, hipMemcpyHostToDevice, h->hs));
+        wy = P.y0[k];
+      }
+    }
+    i64[k].x0 = i32[k].x0 = wx;
+    i64[k].y0 = i32[k].y0 = wy;
     double *xo = hb->on_device ? x[k] : P.xo[k];
     double *yo = hb->on_device ? y[k] : P.yo[k];
     i64[k].xout = i32[k].xout = xo;
@@ -1587,7 +1691,10 @@ int pdhg_update(pdhg_handle *h, const double *b, const double *c) {
       if (!isfinite(c[j])) return fail(PDHG_ERR_NONFINITE, "non-finite c[%lld]", (long long)j);
   }
   RC(enter(h));
-  if (b) RC(to_internal(h, h->b0, b, h->on_device, h->rperm, h->m, h->it.YA));
+  if (b) {
+    RC(to_internal(h, h->b0, b, h->on_device, h->rperm, h->m, h->it.YA));
+    h->impl_valid = false;  // they were derived from the old right-hand side
+  }
   if (c) RC(to_internal(h, h->c0, c, h->on_device, h->cperm, h->n, h->it.XA));
   launch_scale_vectors(h->b0, h->c0, h->l0, h->u0, h->Dr, h->Dc, h->m, h->n, h->b, h->c, h->l,
                        h->u, h->hs);
@@ -1732,6 +1839,15 @@ int time_kernels(pdhg_handle *h, int attempts, double *ms) {
   return PDHG_OK;
 }
 }  // namespace
+
+extern "C" int pdhg_implied_bounds(pdhg_handle *h, double *lo, double *hi) {
+  if (!h || !lo || !hi) return fail(PDHG_ERR_ARG, "null argument");
+  const std::vector<double> &a = h->impl_valid ? h->h_ilo : h->h_l;
+  const std::vector<double> &b = h->impl_valid ? h->h_ihi : h->h_u;
+  std::copy(a.begin(), a.end(), lo);
+  std::copy(b.begin(), b.end(), hi);
+  return PDHG_OK;
+}
 
 extern "C" int pdhg_locality_order(int64_t m, int64_t n, const int32_t *row_ptr,
                                    const int32_t *col_idx, int32_t *row_order,

@@ -39,6 +39,7 @@ struct CtlState {
   // last attempt's reduced partials (diagnostics)
   double dx2, dy2, inter;
   double best_kkt;        // FP32 phase: lowest KKT of an evaluated current iterate
+  double dual_bound;      // weak-duality lower bound from the reported point's y
   long long k, accepted, restarts, last_restart;
   int cur;                // buffer index of the current iterate
   int fresh;              // 1: the next fold starts the sums afresh
@@ -96,6 +97,9 @@ struct EvalView {
   // FP32 phase: the best evaluated iterate, kept in FP64 (the FP64 phase's
   // start buffers); null in the FP64 views
   double *xbest, *ybest;
+  // implied bounds (scaled, internal order) for the dual bound; null: use l, u
+  const double *ilo, *ihi;
+  double bound_allow;            // rounding allowance factor 2 (n + m + longest column + 4) 2^-53
   int use_average, restart;
   double pw_theta;               // 0 keeps the primal weight
   int long_seg;
@@ -103,8 +107,8 @@ struct EvalView {
   const int32_t *rperm, *cperm;
 };
 
-#define EV_ROWQ 10
-#define EV_COLQ 12
+#define EV_ROWQ 12
+#define EV_COLQ 18
 
 // ---------------------------------------------------------------------------
 // launchers (setup.hip)
@@ -131,6 +135,10 @@ void launch_fix_bounds(double *l, double *u, const int32_t *idx, const double *v
                        hipStream_t s);
 void launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
 void launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+
+// implied bounds by row propagation (implied.hip)
+int64_t implied_bounds(int64_t m, const int32_t *rp, const int32_t *ci, const double *v,
+                       const uint8_t *kind, const double *b, int passes, double *lo, double *hi);
 
 // locality ordering (reorder.hip)
 void rcm_order(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cp,

@@ -258,7 +258,7 @@ template <typename X0>
 __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, const double *v_,
                                     const X0 *x0_, const double *x1_, int64_t i, bool valid,
                                     int base, int top, int long_seg, double *lds, double &s0,
-                                    double &s1, bool &mine) {
+                                    double &s1, double &a0, double &a1, bool &mine) {
   const AS_G int32_t *ptr = gin(ptr_), *idx = gin(idx_);
   const AS_G double *v = gin(v_), *x1 = gin(x1_);
   const AS_G X0 *x0 = gin(x0_);
@@ -266,7 +266,7 @@ __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, co
   const bool two = x1_ != nullptr;
   double *lds1 = lds + EV_TILE_CAP + PDHG_BLOCK;
   int rs = 0, re = 0;
-  s0 = s1 = 0.0;
+  s0 = s1 = a0 = a1 = 0.0;
   if (cnt <= EV_TILE_CAP) {
     for (int k0 = 0; k0 < cnt; k0 += 4 * PDHG_BLOCK) {
       int id[4];
@@ -297,9 +297,15 @@ __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, co
     __syncthreads();
     mine = valid && (re - rs <= long_seg);
     if (mine) {
-      for (int k = rs - base; k < re - base; k++) s0 += lds[k];
+      for (int k = rs - base; k < re - base; k++) {
+        s0 += lds[k];
+        a0 += fabs(lds[k]);
+      }
       if (two)
-        for (int k = rs - base; k < re - base; k++) s1 += lds1[k];
+        for (int k = rs - base; k < re - base; k++) {
+          s1 += lds1[k];
+          a1 += fabs(lds1[k]);
+        }
     }
     __syncthreads();
   } else {
@@ -310,8 +316,14 @@ __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, co
     mine = valid && (re - rs <= long_seg);
     if (mine)
       for (int k = rs; k < re; k++) {
-        s0 += __dmul_rn(v[k], (double)x0[idx[k]]);
-        if (two) s1 += __dmul_rn(v[k], x1[idx[k]]);
+        double p0 = __dmul_rn(v[k], (double)x0[idx[k]]);
+        s0 += p0;
+        a0 += fabs(p0);
+        if (two) {
+          double p1 = __dmul_rn(v[k], x1[idx[k]]);
+          s1 += p1;
+          a1 += fabs(p1);
+        }
       }
   }
 }
@@ -319,7 +331,8 @@ __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, co
 // Row-space KKT pieces for the current point and the average, with A x_avg
 // computed here (and kept for a restart to the average):
 // [0] ||r_p||^2 scaled [1] ||r_p||^2 unscaled [2] ||r_p||_inf unscaled
-// [3] b'y [4] ||y - y_last||^2, then the same five for the average.
+// [3] b'y [4] ||y - y_last||^2, then the same five for the average;
+// [10], [11] sum |b_i y_i| (current, average) for the dual bound's allowance.
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ double lds[2 * (EV_TILE_CAP + PDHG_BLOCK)];
@@ -329,10 +342,10 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(const Inst<T> *__restr
   double axa = 0.0;
   if (avg) {
     int64_t r0 = (int64_t)lb * PDHG_BLOCK, rend = r0 + PDHG_BLOCK < e.m ? r0 + PDHG_BLOCK : e.m;
-    double unused;
+    double unused[3];
     bool mine;
     eval_rowdots<double>(e.rp, e.ci, e.v, e.XA, nullptr, i, i < e.m, e.rp[r0], e.rp[rend],
-                         e.long_seg, lds, axa, unused, mine);
+                         e.long_seg, lds, axa, unused[0], unused[1], unused[2], mine);
     if (i < e.m) {
       if (mine)
         e.AXA[i] = axa;
@@ -358,6 +371,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(const Inst<T> *__restr
       q[5 * p + 2] = fabs(ru);
       q[5 * p + 3] = bi * yi;
       q[5 * p + 4] = (yi - yl) * (yi - yl);
+      q[10 + p] = fabs(bi * yi);
     }
   }
   double out[EV_ROWQ];
@@ -383,22 +397,31 @@ __device__ inline double bound_term(uint8_t vk, double lam, double l, double u) 
 // Column-space KKT pieces, with A'y and A'y_avg computed here:
 // [0] ||r_d||^2 scaled [1] ||r_d||^2 unscaled
 // [2] ||r_d||_inf unscaled [3] bound part of the dual objective [4] c'x
-// [5] ||x - x_last||^2, then the same six for the average.
+// [5] ||x - x_last||^2, then the same six for the average; then for the
+// dual bound [12] sum of lambda_j times the bound the sign of lambda_j
+// selects (finite ones), [13] count of infinite ones, [14] allowance part
+// sum |bound_j| (|c_j| + sum_i |a_ij y_i|); [15..17] the same for the average.
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ double lds[2 * (EV_TILE_CAP + PDHG_BLOCK)];
   GROUP_BLOCK(p_cols)
   int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   bool avg = have_avg(st, e.use_average);
-  double aty[2];
+  double aty[2], atyabs[2];
   {
     int64_t c0 = (int64_t)lb * PDHG_BLOCK, cend = c0 + PDHG_BLOCK < e.n ? c0 + PDHG_BLOCK : e.n;
     bool mine;
     eval_rowdots<T>(e.cp, e.ri, e.vt, e.Y[st->cur], avg ? e.YA : nullptr, j, j < e.n, e.cp[c0],
-                    e.cp[cend], e.long_seg, lds, aty[0], aty[1], mine);
-    if (j < e.n && !mine) {  // long column: its own workgroup computed it
+                    e.cp[cend], e.long_seg, lds, aty[0], aty[1], atyabs[0], atyabs[1], mine);
+    if (j < e.n && !mine) {  // long column: its own workgroup computed the sums
       aty[0] = e.ATY[j];
       if (avg) aty[1] = e.ATYA[j];
+      atyabs[0] = atyabs[1] = 0.0;
+      const T *yc = e.Y[st->cur];
+      for (int k = e.cp[j]; k < e.cp[j + 1]; k++) {
+        atyabs[0] += fabs(__dmul_rn(e.vt[k], (double)yc[e.ri[k]]));
+        if (avg) atyabs[1] += fabs(__dmul_rn(e.vt[k], e.YA[e.ri[k]]));
+      }
     }
   }
   double q[EV_COLQ];
@@ -409,6 +432,12 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(const Inst<T> *__restr
     double cj = gin(e.c)[j], dc = gin(e.Dc)[j], lj = gin(e.l)[j], uj = gin(e.u)[j];
     double xl = gin((const double *)e.XL)[j];
     uint8_t vk = gin(e.vk)[j];
+    // bounds for the dual bound: l, u, tightened by the implied ones
+    double blo = lj, bhi = uj;
+    if (e.ilo) {
+      blo = fmax(blo, gin(e.ilo)[j]);
+      bhi = fmin(bhi, gin(e.ihi)[j]);
+    }
     for (int p = 0; p < (avg ? 2 : 1); p++) {
       double xj = p ? gin((const double *)e.XA)[j] : (double)gin((const T *)e.X[cur])[j];
       double lam = cj - aty[p];
@@ -421,6 +450,13 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(const Inst<T> *__restr
       q[6 * p + 3] = bound_term(vk, pl, lj, uj);
       q[6 * p + 4] = cj * xj;
       q[6 * p + 5] = (xj - xl) * (xj - xl);
+      double bnd = lam > 0.0 ? blo : (lam < 0.0 ? bhi : 0.0);
+      if (lam != 0.0 && isinf(bnd)) {
+        q[12 + 3 * p + 1] = 1.0;
+      } else if (lam != 0.0) {
+        q[12 + 3 * p + 0] = lam * bnd;
+        q[12 + 3 * p + 2] = fabs(bnd) * (fabs(cj) + atyabs[p]);
+      }
     }
   }
   double out[EV_COLQ];
@@ -580,6 +616,12 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const Inst<T> *__re
     }
   }
   st->which = which;
+  {  // weak-duality bound of the reported point's y
+    const bool at_avg = rep == &pa && avg;
+    const double *r = rq + (at_avg ? 5 : 0), *cc = cq + (at_avg ? 15 : 12);
+    const double byabs = rq[at_avg ? 11 : 10];
+    st->dual_bound = cc[1] > 0.0 ? -INFINITY : (r[3] + cc[0]) - e.bound_allow * (byabs + cc[2]);
+  }
   st->stash = 0;
   if (e.xbest && rep->rel_kkt < st->best_kkt) {  // FP32 phase: new best point
     st->stash = 1;

@@ -162,6 +162,14 @@ class Problem:
             pass
 
 
+def implied_bounds(problem):
+    """(lo, hi): the implied bounds the dual bound uses (caller's order)."""
+    lo = np.zeros(problem.n)
+    hi = np.zeros(problem.n)
+    L.check(L.load().pdhg_implied_bounds(problem.handle, _ptr(lo), _ptr(hi)))
+    return lo, hi
+
+
 def locality_order(lp):
     """(row_order, col_order) of the relabelling pdhg_setup applies with
     reorder=1 (host computation, no GPU)."""
@@ -187,8 +195,8 @@ def solve_batch(problems, instances, stream=None):
 
     problems: list of Problem (the bases; same precision).
     instances: list of dicts with key 'base' (index into problems) and optional
-    'b', 'c', 'l', 'u' (original-space overrides) and 'fix_idx', 'fix_val'
-    (variables fixed to a value).  Host problems take numpy arrays, device
+    'b', 'c', 'l', 'u' (original-space overrides), 'fix_idx', 'fix_val'
+    (variables fixed to a value) and 'x0', 'y0' (warm start).  Host problems take numpy arrays, device
     problems torch CUDA tensors.  Returns a list of (x, y, info dict).
     """
     import torch
@@ -216,7 +224,9 @@ def solve_batch(problems, instances, stream=None):
         arr[k] = L.PdhgInstance(bi, _ptr(conv(d.get("b"), np.float64)),
                                 _ptr(conv(d.get("c"), np.float64)),
                                 _ptr(conv(d.get("l"), np.float64)),
-                                _ptr(conv(d.get("u"), np.float64)), _ptr(fi), _ptr(fv), nfix)
+                                _ptr(conv(d.get("u"), np.float64)), _ptr(fi), _ptr(fv), nfix,
+                                _ptr(conv(d.get("x0"), np.float64)),
+                                _ptr(conv(d.get("y0"), np.float64)))
         if base.device:
             x = torch.empty(base.n, dtype=torch.float64, device="cuda")
             y = torch.empty(base.m, dtype=torch.float64, device="cuda")
