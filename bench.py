@@ -31,20 +31,26 @@ METRIC = "PDHG iters/s + time-to-1e-4 KKT (6717-bus UC LP); batched LPs/s; % HBM
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(kind: str, m: int, n: int, nnz: int, vb: int) -> int:
+def kernel_bytes(kind: str, m: int, n: int, nnz: int, vb: int, compact: bool = True) -> int:
     """Algorithmic HBM bytes of one launch (each array element moved once).
 
     vb = bytes per matrix value and per iterate element (8 FP64, 4 FP32).
-    dual:   row pointers 4(m+1), columns 4 nnz, values vb nnz, gather x' vb n,
-            read y, Ax, b (3 vb m) and the row kind (m), write y', Ax' (2 vb m),
-            fold the accepted y into the running sum (read + write, 2 vb m).
-    primal: column pointers 4(n+1), rows 4 nnz, values vb nnz, gather y vb m,
-            read x, c, l, u (4 vb n), write x' (vb n), fold x into the sum (2 vb n).
+    Structure of the matrix the launch walks (rows r, tiles of 256 rows):
+    32-bit CSR: pointers 4(r+1), indices 4 nnz; 16-bit tile-relative form
+    (compact): row ends 2r, indices 2 nnz, per tile its smallest index and
+    its nonzero range (8 bytes).
+    dual:   structure of A, values vb nnz, gather x' vb n, read y, Ax, b
+            (3 vb m) and the row kind (m), write y', Ax' (2 vb m), fold the
+            accepted y into the running sum (read + write, 2 vb m).
+    primal: structure of A', values vb nnz, gather y vb m, read x, c, l, u
+            (4 vb n), write x' (vb n), fold x into the sum (2 vb n).
     """
+    def structure(r):
+        return 2 * r + 8 * ((r + 255) // 256) + 2 * nnz if compact else 4 * (r + 1) + 4 * nnz
     if kind == "dual":
-        return 4 * (m + 1) + (4 + vb) * nnz + vb * n + 3 * vb * m + m + 2 * vb * m + 2 * vb * m
+        return structure(m) + vb * nnz + vb * n + 3 * vb * m + m + 2 * vb * m + 2 * vb * m
     if kind == "primal":
-        return 4 * (n + 1) + (4 + vb) * nnz + vb * m + 4 * vb * n + vb * n + 2 * vb * n
+        return structure(n) + vb * nnz + vb * m + 4 * vb * n + vb * n + 2 * vb * n
     raise ValueError(kind)
 
 
@@ -276,9 +282,10 @@ def main():
 
     # live per-kernel timing on the library stream
     kt = prob.time_kernels(args.kernel_attempts)
+    compact = bool(prob.partition()["compact"])
     vb = 8 if args.precision == "fp64" else 4
     dom = "dual" if kt["dual"] >= kt["primal"] else "primal"
-    nbytes = kernel_bytes(dom, lp.m, lp.n, lp.nnz, vb)
+    nbytes = kernel_bytes(dom, lp.m, lp.n, lp.nnz, vb, compact)
     achieved = nbytes / (kt[dom] * 1e-3) / 1e9
     kname = f"k_{dom}"
     roofline_kernel = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -286,6 +293,7 @@ def main():
                     traffic=load_traffic(kname, args.workload, args.precision),
                     kernel=kname, ms_per_launch=round(kt[dom], 5),
                     algorithmic_bytes_per_launch=nbytes,
+                    index_form="16-bit tile-relative" if compact else "32-bit CSR",
                     kernel_ms=dict((k, round(v, 5)) for k, v in kt.items()))
     roofline = roofline_kernel
     prob.close()

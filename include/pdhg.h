@@ -107,6 +107,12 @@ typedef struct {
                              Cuthill-McKee order of A's row/column graph (better locality
                              of the SpMV gathers); every argument and result stays in the
                              caller's order.  0: the caller's order */
+  int compact_index;      /* 1 (default): the attempt kernels read the matrix structure in a
+                             16-bit form relative to each 256-row tile (row ends counted from
+                             the tile's first nonzero, indices from the tile's smallest one)
+                             when every tile of A and A' has at most 65535 nonzeros and an
+                             index span of at most 65535; otherwise, and with 0, the 32-bit
+                             CSR.  The results do not depend on it */
 } pdhg_opts;
 
 typedef struct {
@@ -241,9 +247,10 @@ int pdhg_implied_bounds(pdhg_handle *h, double *lo, double *hi);
 int pdhg_locality_order(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
                         int32_t *row_order, int32_t *col_order);
 
-/* The SpMV partition in use: out[0] tiles per workgroup, out[1] 1 for per-row
- * loops (0: LDS-staged tiles), out[2] long-segment threshold, out[3] number
- * of long rows plus long columns. */
+/* The SpMV partition in use, out[5]: out[0] tiles per workgroup, out[1] 1 for
+ * per-row loops (0: LDS-staged tiles), out[2] long-segment threshold, out[3]
+ * number of long rows plus long columns, out[4] 1 when the attempt kernels
+ * read the 16-bit structure (opts.compact_index). */
 int pdhg_get_partition(pdhg_handle *h, int *out);
 
 /* Run `attempts` more attempts from the handle's current iterate (the state

@@ -34,7 +34,8 @@ class PdhgOpts(ctypes.Structure):
                 ("unroll_iters", c_i64), ("checkpoint_every", c_i64), ("use_graph", c_int),
                 ("verbose", c_int), ("polish_tol", c_dbl), ("pw_update", c_int),
                 ("pw_theta", c_dbl), ("tiles_per_block", c_int), ("autotune", c_int),
-                ("spmv_direct", c_int), ("long_seg", c_int), ("reorder", c_int)]
+                ("spmv_direct", c_int), ("long_seg", c_int), ("reorder", c_int),
+                ("compact_index", c_int)]
 
 
 class PdhgInfo(ctypes.Structure):
@@ -98,6 +99,10 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2512_06715_amd.build`")
+        # torch's HIP runtime is loaded first, so the library binds to the
+        # same one (loading the library before torch leaves two runtimes in
+        # the process, and the second finds no device)
+        import torch  # noqa: F401
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

@@ -135,6 +135,11 @@ struct pdhg_handle {
   float *vf = nullptr, *vtf = nullptr, *bf = nullptr, *cf = nullptr, *lf = nullptr,
         *uf = nullptr;
   uint8_t *kind, *vk;
+  // 16-bit tile-relative structure of A (rows) and A' (columns), used by the
+  // attempt kernels when `compact` (every tile fits)
+  uint16_t *rofs, *cofs, *cix16, *rix16;
+  int32_t *tb_rows, *tb_cols;
+  bool compact = false;
   // locality ordering: caller's index of each internal row / column and the
   // internal index of each caller column (all null without reordering)
   int32_t *rperm = nullptr, *cperm = nullptr, *cinv = nullptr;
@@ -212,6 +217,12 @@ size_t layout(pdhg_handle *h, void *base) {
   h->ri = cv.take<int32_t>(std::max<int64_t>(nnz, 1));
   h->long_rows = cv.take<int32_t>(m);
   h->long_cols = cv.take<int32_t>(n);
+  h->rofs = cv.take<uint16_t>(m);
+  h->cofs = cv.take<uint16_t>(n);
+  h->cix16 = cv.take<uint16_t>(std::max<int64_t>(nnz, 1));
+  h->rix16 = cv.take<uint16_t>(std::max<int64_t>(nnz, 1));
+  h->tb_rows = cv.take<int32_t>(nblk(m));
+  h->tb_cols = cv.take<int32_t>(nblk(n));
   h->scan_tmp = cv.take<int32_t>(scan_tmp_ints(n + 1));
   h->tmp_next = cv.take<int32_t>(n + 1);
   h->v = cv.take<double>(std::max<int64_t>(nnz, 1));
@@ -279,6 +290,8 @@ int check_opts(const pdhg_opts *o) {
   if (o->tiles_per_block < 0) return fail(PDHG_ERR_ARG, "tiles_per_block must be >= 0");
   if (o->long_seg < 0) return fail(PDHG_ERR_ARG, "long_seg must be >= 0");
   if (o->reorder != 0 && o->reorder != 1) return fail(PDHG_ERR_ARG, "reorder must be 0 or 1");
+  if (o->compact_index != 0 && o->compact_index != 1)
+    return fail(PDHG_ERR_ARG, "compact_index must be 0 or 1");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -507,6 +520,22 @@ int upload_implied_bounds(pdhg_handle *h) {
   return PDHG_OK;
 }
 
+// The 16-bit form of the final (scaled, reordered) structure, kept when
+// every tile of both matrices fits it.
+int build_compact(pdhg_handle *h) {
+  h->compact = false;
+  if (!h->o.compact_index) return PDHG_OK;
+  HC(hipMemsetAsync(h->err, 0, sizeof(int), h->hs));
+  launch_compact(h->rp, h->ci, h->m, h->rofs, h->cix16, h->tb_rows, h->err, h->hs);
+  launch_compact(h->cp, h->ri, h->n, h->cofs, h->rix16, h->tb_cols, h->err, h->hs);
+  HK();
+  int herr = 0;
+  HC(hipMemcpyAsync(&herr, h->err, sizeof(int), hipMemcpyDeviceToHost, h->hs));
+  HC(hipStreamSynchronize(h->hs));
+  h->compact = herr == 0;
+  return PDHG_OK;
+}
+
 // Rows and columns longer than the partition's threshold get a workgroup each.
 int build_long_lists(pdhg_handle *h) {
   std::vector<int32_t> lr, lc;
@@ -589,6 +618,12 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   w.adaptive = h->o.step_mode == 0;
   w.long_seg = e.long_seg = h->long_seg;
   w.direct = h->direct;
+  w.rofs = h->compact ? h->rofs : nullptr;
+  w.cofs = h->compact ? h->cofs : nullptr;
+  w.cix16 = h->compact ? h->cix16 : nullptr;
+  w.rix16 = h->compact ? h->rix16 : nullptr;
+  w.tb_rows = h->compact ? h->tb_rows : nullptr;
+  w.tb_cols = h->compact ? h->tb_cols : nullptr;
   e.v = h->v;
   e.vt = h->vt;
   e.b = d.b;
@@ -709,6 +744,8 @@ int upload_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
   g.n_cols = pre[3 * c1 + na];
   g.n_lrows = pre[4 * c1 + na];
   g.n_lcols = pre[5 * c1 + na];
+  g.compact = 1;
+  for (int k = 0; k < na; k++) g.compact = g.compact && sel[k].w.cix16 != nullptr;
   g.interleave = na > 1;
   for (int k = 1; k < na && g.interleave; k++) {
     const IterView<T> &a = sel[0].w, &b = sel[k].w;
@@ -1046,6 +1083,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->spmv_direct = 0;
   o->long_seg = 0;
   o->reorder = 1;
+  o->compact_index = 1;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -1138,6 +1176,7 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
                          h->hs);
     HK();
     if (h->o.reorder) RC(reorder_problem(h));
+    RC(build_compact(h));
     RC(upload_implied_bounds(h));
     // long rows and columns (handled by a workgroup each in the iteration)
     h->hrp.resize(m + 1);
@@ -1877,6 +1916,7 @@ extern "C" int pdhg_get_partition(pdhg_handle *h, int *out) {
   out[1] = h->direct;
   out[2] = h->long_seg;
   out[3] = h->n_long_rows + h->n_long_cols;
+  out[4] = h->compact ? 1 : 0;
   return PDHG_OK;
 }
 

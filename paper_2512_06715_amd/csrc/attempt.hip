@@ -45,17 +45,52 @@ __device__ __forceinline__ void st_out(AS_G T *p, T v) {
 __device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
 __device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
 
+// The structure of one tile: 32-bit CSR (ptr, idx), or with C the 16-bit
+// tile-relative form (row ends `ofs` counted from the tile's first nonzero,
+// indices `ix16` counted from the tile's smallest index `tb`).  Row i of the
+// tile is lane threadIdx.x.
+template <bool C>
+struct TileIx {
+  const AS_G int32_t *ptr, *idx;
+  const AS_G uint16_t *ofs, *ix16;
+  int tb;
+  // index of nonzero k: streamed (read once per launch) or cached
+  __device__ __forceinline__ int col_stream(int k) const {
+    if constexpr (C)
+      return tb + (int)ld_stream(ix16 + k);
+    else
+      return ld_stream(idx + k);
+  }
+  __device__ __forceinline__ int col(int k) const {
+    if constexpr (C)
+      return tb + (int)ix16[k];
+    else
+      return idx[k];
+  }
+  // nonzero range [rs, re) of this lane's row i; base = the tile's first
+  __device__ __forceinline__ void bounds(int64_t i, int base, int &rs, int &re) const {
+    if constexpr (C) {
+      const bool first = threadIdx.x == 0;
+      const int prev = ofs[first ? i : i - 1];  // always an entry of this tile
+      re = base + (int)ofs[i];
+      rs = first ? base : base + prev;
+    } else {
+      rs = ptr[i];
+      re = ptr[i + 1];
+    }
+  }
+};
+
 // Dot product s = sum_k v[k] x[idx[k]] of this lane's row i (rows r0 + lane of
 // a PDHG_TILE-row tile whose nonzeros are [base, top)), summed in CSR order.  The
 // row's bounds are loaded here, after the tile's index/value stream has been
 // issued, so the gathers wait only on that stream.  `mine` returns whether
 // the row is valid and short enough to be this tile's.  Every lane of the
 // workgroup must call it.
-template <typename T>
-__device__ __forceinline__ T tile_rowdot(const AS_G int32_t *ptr, const AS_G int32_t *idx,
-                                         const AS_G T *v, const AS_G T *x, int64_t i, bool valid,
-                                         int base, int top, int long_seg, T *lds, int direct,
-                                         bool &mine) {
+template <typename T, bool C>
+__device__ __forceinline__ T tile_rowdot(const TileIx<C> &ix, const AS_G T *v, const AS_G T *x,
+                                         int64_t i, bool valid, int base, int top, int long_seg,
+                                         T *lds, int direct, bool &mine) {
   const int cnt = top - base;
   T s = 0;
   int rs = 0, re = 0;
@@ -67,13 +102,10 @@ __device__ __forceinline__ T tile_rowdot(const AS_G int32_t *ptr, const AS_G int
       for (int q = 0; q < TILE_U; q++) {
         int k = k0 + q * PDHG_TILE + (int)threadIdx.x;
         int kc = base + (k < cnt ? k : cnt - 1);
-        id[q] = ld_stream(idx + kc);
+        id[q] = ix.col_stream(kc);
         vv[q] = ld_stream(v + kc);
       }
-      if (k0 == 0 && valid) {
-        rs = ptr[i];
-        re = ptr[i + 1];
-      }
+      if (k0 == 0 && valid) ix.bounds(i, base, rs, re);
 #pragma unroll
       for (int q = 0; q < TILE_U; q++) {
         int k = k0 + q * PDHG_TILE + (int)threadIdx.x;
@@ -81,20 +113,14 @@ __device__ __forceinline__ T tile_rowdot(const AS_G int32_t *ptr, const AS_G int
         lds[k < cnt ? k : TILE_CAP + (int)threadIdx.x] = mul_rn(vv[q], x[id[q]]);
       }
     }
-    if (cnt == 0 && valid) {
-      rs = ptr[i];
-      re = ptr[i + 1];
-    }
+    if (cnt == 0 && valid) ix.bounds(i, base, rs, re);
     __syncthreads();
     mine = valid && (re - rs <= long_seg);
     if (mine)
       for (int k = rs - base; k < re - base; k++) s += lds[k];
     __syncthreads();
   } else {
-    if (valid) {
-      rs = ptr[i];
-      re = ptr[i + 1];
-    }
+    if (valid) ix.bounds(i, base, rs, re);
     mine = valid && (re - rs <= long_seg);
     if (mine) {
       for (int k0 = rs; k0 < re; k0 += TILE_U) {
@@ -103,7 +129,7 @@ __device__ __forceinline__ T tile_rowdot(const AS_G int32_t *ptr, const AS_G int
 #pragma unroll
         for (int q = 0; q < TILE_U; q++) {
           int kc = k0 + q < re ? k0 + q : re - 1;
-          id[q] = idx[kc];
+          id[q] = ix.col(kc);
           vv[q] = v[kc];
         }
 #pragma unroll
@@ -140,23 +166,34 @@ __device__ inline void record_bit(uint64_t *mask, int64_t row) {
   atomicOr((unsigned long long *)&mask[row >> 6], 1ull << (row & 63));
 }
 
+// Folds the previous iterate into the running sum of the average when an
+// accepted weight is pending.  It does not depend on the row's product, so
+// the tile's workgroup folds every row of the tile, long ones included (in
+// the finish step of its own rows, separately for the long ones): every
+// element of the sums is read and written by one lane of one workgroup per
+// launch, never by the long row's own workgroup.
+template <typename T>
+__device__ __forceinline__ void fold_sum(AS_G T *sum, int64_t i, T prev, T v, double pend,
+                                         int fresh) {
+  if (pend > 0.0) st_out(sum + i, (fresh ? (T)0 : prev) + (T)pend * v);
+}
+
 // Primal update of column j from t = (A'y)_j; returns whether the pre-clamp
-// value lies strictly inside the box.  Folds the previous iterate into the
-// running sum when an accepted weight is pending.
+// value lies strictly inside the box.  With xs, also folds x_j into the sum.
 template <typename T>
 __device__ __forceinline__ bool primal_finish(int64_t j, T t, T tau, T xj, T cj, T lj, T uj,
-                                              T xsj, AS_G T *xn, AS_G T *xs, double pend,
+                                              AS_G T *xn, AS_G T *xs, T xsj, double pend,
                                               int fresh, double &d2) {
   T xt = xj - tau * (cj - t);
   T xv = clamp_box<T>(xt, lj, uj);
   st_out(xn + j, xv);
   double d = (double)xv - (double)xj;
   d2 += d * d;
-  if (pend > 0.0) st_out(xs + j, (fresh ? (T)0 : xsj) + (T)pend * xj);
+  if (xs) fold_sum<T>(xs, j, xsj, xj, pend, fresh);
   return xt > lj && xt < uj;
 }
 
-template <typename T>
+template <typename T, bool C>
 __global__ __launch_bounds__(PDHG_TILE) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -183,8 +220,8 @@ __global__ __launch_bounds__(PDHG_TILE) void k_primal(const Inst<T> *__restrict_
     double t = long_rowdot<T>(ri, vt, y, cpc[j], cpc[j + 1]);
     if (threadIdx.x == 0) {
       double dd = 0.0;
-      bool in = primal_finish<T>(j, (T)t, tau, x[j], c[j], l[j], u[j],
-                                 fold_read ? xs[j] : (T)0, xn, xs, pend, fresh, dd);
+      bool in = primal_finish<T>(j, (T)t, tau, x[j], c[j], l[j], u[j], xn, nullptr, (T)0, 0.0, 0,
+                                 dd);
       gout(w.part_dx2)[lb] = dd;
       if (mask && in) record_bit(mask, j);
     }
@@ -209,10 +246,14 @@ __global__ __launch_bounds__(PDHG_TILE) void k_primal(const Inst<T> *__restrict_
       uj = ld_stream(u + j);
       if (fold_read) xsj = xs[j];
     }
+    const TileIx<C> ix{cp, ri, gin(w.cofs), gin(w.rix16), C ? cin(w.tb_cols)[t] : 0};
     bool mine;
-    T s = tile_rowdot<T>(cp, ri, vt, y, j, j < n, base, top, long_seg, lds, direct, mine);
+    T s = tile_rowdot<T, C>(ix, vt, y, j, j < n, base, top, long_seg, lds, direct, mine);
     bool in = false;
-    if (mine) in = primal_finish<T>(j, s, tau, xj, cj, lj, uj, xsj, xn, xs, pend, fresh, d2[0]);
+    if (mine)
+      in = primal_finish<T>(j, s, tau, xj, cj, lj, uj, xn, xs, xsj, pend, fresh, d2[0]);
+    else if (j < n)
+      fold_sum<T>(xs, j, xsj, xj, pend, fresh);  // long column
     if (mask) record_mask(mask, j & ~(int64_t)63, in);
   }
   double out[1];
@@ -224,7 +265,7 @@ __global__ __launch_bounds__(PDHG_TILE) void k_primal(const Inst<T> *__restrict_
 // unprojected (equality row or value > 0).
 template <typename T>
 __device__ __forceinline__ bool dual_finish(int64_t i, T s, T sigma, T yi, T axi, T bi, uint8_t ki,
-                                            T ysi, AS_G T *yn, AS_G T *axn, AS_G T *ys,
+                                            AS_G T *yn, AS_G T *axn, AS_G T *ys, T ysi,
                                             double pend, int fresh, double &dy2, double &inter) {
   T yv = yi + sigma * (bi - (s + s - axi));
   bool in = (ki == 0) || (yv > (T)0);
@@ -234,11 +275,11 @@ __device__ __forceinline__ bool dual_finish(int64_t i, T s, T sigma, T yi, T axi
   double dy = (double)yv - (double)yi;
   dy2 += dy * dy;
   inter += dy * ((double)s - (double)axi);
-  if (pend > 0.0) st_out(ys + i, (fresh ? (T)0 : ysi) + (T)pend * yi);
+  if (ys) fold_sum<T>(ys, i, ysi, yi, pend, fresh);
   return in;
 }
 
-template <typename T>
+template <typename T, bool C>
 __global__ __launch_bounds__(PDHG_TILE) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -266,8 +307,8 @@ __global__ __launch_bounds__(PDHG_TILE) void k_dual(const Inst<T> *__restrict__ 
     const AS_C int32_t *rpc = cin(w.rp);
     double t = long_rowdot<T>(ci, v, xn, rpc[i], rpc[i + 1]);
     if (threadIdx.x == 0) {
-      bool in = dual_finish<T>(i, (T)t, sigma, y[i], ax[i], bb[i], kind[i],
-                               fold_read ? ys[i] : (T)0, yn, axn, ys, pend, fresh, acc[0], acc[1]);
+      bool in = dual_finish<T>(i, (T)t, sigma, y[i], ax[i], bb[i], kind[i], yn, axn, nullptr,
+                               (T)0, 0.0, 0, acc[0], acc[1]);
       gout(w.part_dy)[lb] = acc[0];
       gout(w.part_dy)[G + lb] = acc[1];
       if (mask && in) record_bit(mask, i);
@@ -293,12 +334,15 @@ __global__ __launch_bounds__(PDHG_TILE) void k_dual(const Inst<T> *__restrict__ 
       ki = kind[i];
       if (fold_read) ysi = ys[i];
     }
+    const TileIx<C> ix{rp, ci, gin(w.rofs), gin(w.cix16), C ? cin(w.tb_rows)[t] : 0};
     bool mine;
-    T s = tile_rowdot<T>(rp, ci, v, xn, i, i < m, base, top, long_seg, lds, direct, mine);
+    T s = tile_rowdot<T, C>(ix, v, xn, i, i < m, base, top, long_seg, lds, direct, mine);
     bool in = false;
     if (mine)
-      in = dual_finish<T>(i, s, sigma, yi, axi, bi, ki, ysi, yn, axn, ys, pend, fresh, acc[0],
+      in = dual_finish<T>(i, s, sigma, yi, axi, bi, ki, yn, axn, ys, ysi, pend, fresh, acc[0],
                           acc[1]);
+    else if (i < m)
+      fold_sum<T>(ys, i, ysi, yi, pend, fresh);  // long row
     if (mask) record_mask(mask, i & ~(int64_t)63, in);
   }
   double out[2];
@@ -314,23 +358,41 @@ __global__ __launch_bounds__(PDHG_TILE) void k_dual(const Inst<T> *__restrict__ 
 // With events, the kernel is launched through hipExtLaunchKernelGGL, whose
 // start/stop events take the dispatch's own timestamps (the kernel's
 // duration, without launch gaps).
+template <typename T, bool C>
+void launch_primal_as(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
+                      hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_primal<T, C>, dim3(grid_of(g.n_primal)), dim3(PDHG_TILE), 0, s, t0, t1,
+                          0, I, g);
+  else
+    k_primal<T, C><<<grid_of(g.n_primal), PDHG_TILE, 0, s>>>(I, g);
+}
+
+template <typename T, bool C>
+void launch_dual_as(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
+                    hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_dual<T, C>, dim3(grid_of(g.n_dual)), dim3(PDHG_TILE), 0, s, t0, t1, 0,
+                          I, g);
+  else
+    k_dual<T, C><<<grid_of(g.n_dual), PDHG_TILE, 0, s>>>(I, g);
+}
+
 template <typename T>
 void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
                    hipEvent_t t1) {
-  if (t0)
-    hipExtLaunchKernelGGL(k_primal<T>, dim3(grid_of(g.n_primal)), dim3(PDHG_TILE), 0, s, t0, t1, 0,
-                          I, g);
+  if (g.compact)
+    launch_primal_as<T, true>(I, g, s, t0, t1);
   else
-    k_primal<T><<<grid_of(g.n_primal), PDHG_TILE, 0, s>>>(I, g);
+    launch_primal_as<T, false>(I, g, s, t0, t1);
 }
 
 template <typename T>
 void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-  if (t0)
-    hipExtLaunchKernelGGL(k_dual<T>, dim3(grid_of(g.n_dual)), dim3(PDHG_TILE), 0, s, t0, t1, 0, I,
-                          g);
+  if (g.compact)
+    launch_dual_as<T, true>(I, g, s, t0, t1);
   else
-    k_dual<T><<<grid_of(g.n_dual), PDHG_TILE, 0, s>>>(I, g);
+    launch_dual_as<T, false>(I, g, s, t0, t1);
 }
 
 #define INST(T)                                                                             \

@@ -72,6 +72,12 @@ struct IterView {
   int adaptive;
   int long_seg;                  // rows longer than this get a workgroup each
   int direct;                    // 1: per-row loops instead of LDS-staged tiles
+  // 16-bit tile-relative form of both matrices' structure (null when some
+  // tile does not fit): per row, the end of its nonzeros counted from the
+  // tile's first nonzero; per nonzero, its index minus the tile's smallest
+  // one; per tile, that smallest index
+  const uint16_t *rofs, *cofs, *cix16, *rix16;
+  const int32_t *tb_rows, *tb_cols;
   // unrolled-mode recording: when non-null, attempt k - mask_k0 writes its
   // projection masks (bit j: pre-clamp x strictly inside the box; bit i:
   // equality row or pre-projection y > 0) into words [(k - mask_k0) * words]
@@ -122,6 +128,8 @@ void launch_transpose(const int32_t *rp, const int32_t *ci, const double *v,
                       int64_t m, int64_t n, int64_t nnz, int32_t *cp, int32_t *ri,
                       double *vt, int32_t *tmp_next, int32_t *scan_tmp, hipStream_t s);
 int64_t scan_tmp_ints(int64_t len);
+void launch_compact(const int32_t *ptr, const int32_t *idx, int64_t rows, uint16_t *rofs,
+                    uint16_t *ix16, int32_t *tb, int *fail, hipStream_t s);
 void launch_scale_pass(int32_t *rp, int32_t *ci, double *v, int32_t *cp, int32_t *ri,
                        double *vt, int64_t m, int64_t n, int pc, double *rs, double *cs,
                        double *Dr, double *Dc, hipStream_t s);
@@ -184,6 +192,8 @@ struct Groups {
   // of instance b % ninst), so the instances' blocks of one tile run back to
   // back on one XCD and its L2 serves the shared matrix tile once
   int interleave;
+  // 1: every instance has the 16-bit structure; the attempt kernels read it
+  int compact;
 };
 
 // ---------------------------------------------------------------------------

@@ -360,7 +360,9 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(const Inst<T> *__restr
     int cur = st->cur;
     double bi = gin(e.b)[i], dr = gin(e.Dr)[i], yl = gin((const double *)e.YL)[i];
     bool ge = gin(e.kind)[i] == 1;
-    for (int p = 0; p < (avg ? 2 : 1); p++) {
+#pragma unroll
+    for (int p = 0; p < 2; p++) {
+      if (p == 1 && !avg) break;
       double yi = p ? gin((const double *)e.YA)[i] : (double)gin((const T *)e.Y[cur])[i];
       double axi = p ? axa : (double)gin((const T *)e.AX[cur])[i];
       double r = bi - axi;
@@ -438,7 +440,9 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(const Inst<T> *__restr
       blo = fmax(blo, gin(e.ilo)[j]);
       bhi = fmin(bhi, gin(e.ihi)[j]);
     }
-    for (int p = 0; p < (avg ? 2 : 1); p++) {
+#pragma unroll
+    for (int p = 0; p < 2; p++) {  // constant indices keep q in registers
+      if (p == 1 && !avg) break;
       double xj = p ? gin((const double *)e.XA)[j] : (double)gin((const T *)e.X[cur])[j];
       double lam = cj - aty[p];
       double pl = proj_lambda(vk, lam);

@@ -308,6 +308,47 @@ __global__ void k_fix_bounds(double *l, double *u, const int32_t *__restrict__ i
   u[j] = val[k];
 }
 
+// 16-bit tile-relative structure of a CSR matrix, one workgroup per tile of
+// PDHG_TILE rows: rofs[i] = ptr[i + 1] - ptr[r0] (r0 the tile's first row),
+// ix16[k] = idx[k] - tb[t], tb[t] = the smallest index of the tile's
+// nonzeros.  A tile with more than 65535 nonzeros or an index span above
+// 65535 sets *fail and leaves the arrays incomplete.
+__global__ __launch_bounds__(PDHG_BLOCK) void k_compact(const int32_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ idx,
+                                                        int64_t rows, uint16_t *rofs,
+                                                        uint16_t *ix16, int32_t *tb, int *fail) {
+  static_assert(PDHG_BLOCK == PDHG_TILE, "one lane per tile row");
+  __shared__ int smin[PDHG_BLOCK], smax[PDHG_BLOCK];
+  const int64_t t = blockIdx.x, r0 = t * PDHG_TILE;
+  const int64_t rend = r0 + PDHG_TILE < rows ? r0 + PDHG_TILE : rows;
+  const int base = ptr[r0], top = ptr[rend];
+  int mn = 0x7fffffff, mx = -1;
+  for (int k = base + (int)threadIdx.x; k < top; k += PDHG_BLOCK) {
+    mn = min(mn, idx[k]);
+    mx = max(mx, idx[k]);
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = PDHG_BLOCK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + h]);
+      smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  mn = top > base ? smin[0] : 0;
+  mx = top > base ? smax[0] : 0;
+  if (top - base > 65535 || mx - mn > 65535) {
+    if (threadIdx.x == 0) atomicOr(fail, 1);
+    return;
+  }
+  if (threadIdx.x == 0) tb[t] = mn;
+  for (int k = base + (int)threadIdx.x; k < top; k += PDHG_BLOCK) ix16[k] = (uint16_t)(idx[k] - mn);
+  const int64_t i = r0 + threadIdx.x;
+  if (i < rend) rofs[i] = (uint16_t)(ptr[i + 1] - base);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -366,6 +407,13 @@ void launch_scale_vectors(const double *b0, const double *c0, const double *l0, 
                           double *c, double *l, double *u, hipStream_t s) {
   k_scale_rows_vec<<<grid_for(m), PDHG_BLOCK, 0, s>>>(b0, Dr, m, b);
   k_scale_cols_vec<<<grid_for(n), PDHG_BLOCK, 0, s>>>(c0, l0, u0, Dc, n, c, l, u);
+}
+
+void launch_compact(const int32_t *ptr, const int32_t *idx, int64_t rows, uint16_t *rofs,
+                    uint16_t *ix16, int32_t *tb, int *fail, hipStream_t s) {
+  int64_t tiles = (rows + PDHG_TILE - 1) / PDHG_TILE;
+  k_compact<<<(unsigned)(tiles > 0 ? tiles : 1), PDHG_BLOCK, 0, s>>>(ptr, idx, rows, rofs, ix16,
+                                                                      tb, fail);
 }
 
 void launch_fill(double *p, double v, int64_t n, hipStream_t s) {

@@ -139,9 +139,10 @@ class Problem:
 
     def partition(self) -> dict:
         """The SpMV partition in use (chosen by the autotuner or the options)."""
-        out = (ctypes.c_int * 4)()
+        out = (ctypes.c_int * 5)()
         L.check(L.load().pdhg_get_partition(self.handle, out))
-        return dict(tiles_per_block=out[0], direct=out[1], long_seg=out[2], long_segments=out[3])
+        return dict(tiles_per_block=out[0], direct=out[1], long_seg=out[2], long_segments=out[3],
+                    compact=out[4])
 
     def time_kernels(self, attempts: int = 200) -> dict:
         """Average ms per launch of the attempt kernels, timed with HIP events."""

@@ -26,6 +26,24 @@ def dense_column_lp(seed=7, m=300, n=120):
     return ucgen.dense_to_lp(A, kind, b, c, lo, hi)
 
 
+def wide_tile_lp(seed=3, m=500, n=70000):
+    """Sparse LP whose row tiles each join columns near 0 with columns near n
+    (an index span above 65535 inside one 256-row tile)."""
+    rng = np.random.default_rng(seed)
+    rp, ci, vv = [0], [], []
+    for i in range(m):
+        cols = sorted({(i * 131) % n, (i * 131 + 7) % n, n - 1 - i})
+        ci += cols
+        vv += list(rng.uniform(0.5, 2.0, len(cols)))
+        rp.append(len(ci))
+    lp = ucgen.UCLP(m, n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(vv),
+                    (rng.random(m) < 0.5).astype(np.uint8), np.zeros(m), rng.standard_normal(n),
+                    np.zeros(n), np.ones(n), {})
+    x0 = rng.random(n)
+    lp.b = ucgen.scipy_csr(lp) @ x0 - lp.row_kind * rng.random(m)
+    return lp
+
+
 CASES = {
     "uc14_t24": lambda: ucgen.workload("uc14_t24"),
     "uc1000_t48": lambda: ucgen.workload("uc1000_t48"),
@@ -175,3 +193,63 @@ def test_warm_start_in_callers_order(gpu, oracle_mod, precision):
     assert info["status"] == 1 and info["attempts"] == 0
     assert np.abs(x - xo).max() <= 1e-6 * (1 + np.abs(xo).max())
     assert np.abs(y - yo).max() <= 1e-6 * (1 + np.abs(yo).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("part", [dict(), dict(spmv_direct=1), dict(long_seg=8, tiles_per_block=3)])
+@pytest.mark.parametrize("name", ["uc14_t24", "dense_cols", "uc1000_t48"])
+def test_compact_index_bit_identical(gpu, name, part, precision):
+    """The 16-bit tile-relative structure changes only how indices are read:
+    300 attempts (evaluations and restarts included) give bit-identical
+    iterates with and without it."""
+    from paper_2512_06715_amd.solver import Problem
+    lp = CASES[name]()
+    print("case compact", name, part, precision, flush=True)
+    res = []
+    for ci in (1, 0):
+        p = Problem(lp, max_iter=300, tol=1e-12, precision=precision, compact_index=ci, **part)
+        assert p.partition()["compact"] == ci
+        x, y, info = p.solve()
+        p.close()
+        res.append((x, y, info))
+    (x1, y1, i1), (x0, y0, i0) = res
+    assert i1["attempts"] == i0["attempts"] and i1["accepted"] == i0["accepted"]
+    assert np.array_equal(x1.view(np.uint64), x0.view(np.uint64))
+    assert np.array_equal(y1.view(np.uint64), y0.view(np.uint64))
+
+
+def test_compact_index_falls_back_on_wide_tiles(gpu, oracle_mod):
+    """A tile whose indices span more than 65535 keeps the 32-bit structure,
+    and the attempt still matches the oracle."""
+    from paper_2512_06715_amd.solver import Problem
+    lp = wide_tile_lp()
+    print("case wide tiles", flush=True)
+    p = Problem(lp, max_iter=4, tol=1e-12, reorder=0, use_graph=0)
+    assert p.partition()["compact"] == 0
+    x, y, info = p.solve()
+    p.close()
+    xo, yo, io = oracle_mod.pdhg(lp, tol=1e-12, max_iter=4)
+    assert info["attempts"] == io["attempts"] == 4
+    np.testing.assert_allclose(x, xo, rtol=1e-12, atol=1e-12 * (1 + np.abs(xo).max()))
+    np.testing.assert_allclose(y, yo, rtol=1e-12, atol=1e-12 * (1 + np.abs(yo).max()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_repeat_runs_bit_identical(gpu, precision):
+    """Two runs of the same solve give the same bits.  With a low long-row
+    threshold thousands of rows have workgroups of their own while their
+    tiles' workgroups fold the running sums of the average; 300 attempts
+    cover restarts to the average, which read those sums."""
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc1000_t48")
+    print("case repeat", precision, flush=True)
+    res = []
+    for _ in range(2):
+        p = Problem(lp, max_iter=300, tol=1e-12, precision=precision, long_seg=8)
+        x, y, info = p.solve()
+        p.close()
+        res.append((x, y, info))
+    assert res[0][2]["restarts"] >= 2
+    assert res[0][2]["omega"] == res[1][2]["omega"]
+    assert np.array_equal(res[0][0].view(np.uint64), res[1][0].view(np.uint64))
+    assert np.array_equal(res[0][1].view(np.uint64), res[1][1].view(np.uint64))
