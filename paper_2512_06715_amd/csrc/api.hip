@@ -219,14 +219,16 @@ size_t layout(pdhg_handle *h, void *base) {
   h->long_cols = cv.take<int32_t>(n);
   h->rofs = cv.take<uint16_t>(m);
   h->cofs = cv.take<uint16_t>(n);
-  h->cix16 = cv.take<uint16_t>(std::max<int64_t>(nnz, 1));
-  h->rix16 = cv.take<uint16_t>(std::max<int64_t>(nnz, 1));
+  // index and value arrays: two entries past the last nonzero, which the
+  // paired loads of the attempt kernels may read
+  h->cix16 = cv.take<uint16_t>(nnz + 2);
+  h->rix16 = cv.take<uint16_t>(nnz + 2);
   h->tb_rows = cv.take<int32_t>(nblk(m));
   h->tb_cols = cv.take<int32_t>(nblk(n));
   h->scan_tmp = cv.take<int32_t>(scan_tmp_ints(n + 1));
   h->tmp_next = cv.take<int32_t>(n + 1);
-  h->v = cv.take<double>(std::max<int64_t>(nnz, 1));
-  h->vt = cv.take<double>(std::max<int64_t>(nnz, 1));
+  h->v = cv.take<double>(nnz + 2);
+  h->vt = cv.take<double>(nnz + 2);
   h->b0 = cv.take<double>(m);
   h->b = cv.take<double>(m);
   h->Dr = cv.take<double>(m);
@@ -243,8 +245,8 @@ size_t layout(pdhg_handle *h, void *base) {
   h->ilo = cv.take<double>(n);
   h->ihi = cv.take<double>(n);
   if (mixed) {
-    h->vf = cv.take<float>(std::max<int64_t>(nnz, 1));
-    h->vtf = cv.take<float>(std::max<int64_t>(nnz, 1));
+    h->vf = cv.take<float>(nnz + 2);
+    h->vtf = cv.take<float>(nnz + 2);
     h->bf = cv.take<float>(m);
     h->cf = cv.take<float>(n);
     h->lf = cv.take<float>(n);

@@ -87,6 +87,64 @@ struct TileIx {
 // issued, so the gathers wait only on that stream.  `mine` returns whether
 // the row is valid and short enough to be this tile's.  Every lane of the
 // workgroup must call it.
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
+// LDS staging of a tile's products from the 16-bit structure, two nonzeros
+// per load: pair p covers entries a0 + 2p and a0 + 2p + 1 with a0 the even
+// entry at or below the tile's first, so each lane reads one aligned 32-bit
+// word of indices and one aligned pair of values (the index and value arrays
+// hold two entries past the last nonzero) and writes both products as one
+// aligned LDS pair at slot 2p.  The caller's rows read from lds + (base - a0).
+// Entries outside the tile (at most the one before its first and the one
+// after its last) gather x at the tile's smallest index, and no row reads
+// their slots; lanes past the last pair repeat it and write the same values.
+// The lane's row bounds (rs, re) are loaded after the first loads of the
+// stream.
+template <typename T>
+__device__ __forceinline__ void stage_pairs(const TileIx<true> &ix, const AS_G T *v,
+                                            const AS_G T *x, int base, int top, T *lds, int64_t i,
+                                            bool valid, int &rs, int &re) {
+  typedef typename Pair<T>::type T2;
+  const int a0 = base & ~1;
+  const int npair = (top - a0 + 1) >> 1;
+  const AS_G uint32_t *iw = (const AS_G uint32_t *)(ix.ix16 + a0);
+  const AS_G T2 *vw = (const AS_G T2 *)(v + a0);
+  constexpr int TP = TILE_U / 2;
+  for (int p0 = 0; p0 < npair; p0 += TP * PDHG_TILE) {
+    uint32_t w[TP];
+    T2 vv[TP];
+#pragma unroll
+    for (int q = 0; q < TP; q++) {
+      int p = p0 + q * PDHG_TILE + (int)threadIdx.x;
+      int pc = p < npair ? p : npair - 1;
+      w[q] = ld_stream(iw + pc);
+      vv[q] = ld_stream(vw + pc);
+    }
+    if (p0 == 0 && valid) ix.bounds(i, base, rs, re);
+#pragma unroll
+    for (int q = 0; q < TP; q++) {
+      int p = p0 + q * PDHG_TILE + (int)threadIdx.x;
+      int pc = p < npair ? p : npair - 1;
+      int e = a0 + 2 * pc;  // absolute entry of the pair's first
+      int c0 = e >= base ? ix.tb + (int)(w[q] & 0xffffu) : ix.tb;
+      int c1 = e + 1 < top ? ix.tb + (int)(w[q] >> 16) : ix.tb;
+      T2 pr;
+      pr.x = mul_rn(vv[q].x, x[c0]);
+      pr.y = mul_rn(vv[q].y, x[c1]);
+      *(T2 *)(lds + 2 * pc) = pr;
+    }
+  }
+}
+
 template <typename T, bool C>
 __device__ __forceinline__ T tile_rowdot(const TileIx<C> &ix, const AS_G T *v, const AS_G T *x,
                                          int64_t i, bool valid, int base, int top, int long_seg,
@@ -94,7 +152,20 @@ __device__ __forceinline__ T tile_rowdot(const TileIx<C> &ix, const AS_G T *v, c
   const int cnt = top - base;
   T s = 0;
   int rs = 0, re = 0;
-  if (!direct && cnt <= TILE_CAP) {
+  if (C && !direct && cnt <= TILE_CAP) {
+    const int off = base & 1;  // slot of the tile's first entry
+    if constexpr (C) {
+      if (cnt > 0)
+        stage_pairs<T>(ix, v, x, base, top, lds, i, valid, rs, re);
+      else if (valid)
+        ix.bounds(i, base, rs, re);
+    }
+    __syncthreads();
+    mine = valid && (re - rs <= long_seg);
+    if (mine)
+      for (int k = rs - base + off; k < re - base + off; k++) s += lds[k];
+    __syncthreads();
+  } else if (!direct && cnt <= TILE_CAP) {
     for (int k0 = 0; k0 < cnt; k0 += TILE_U * PDHG_TILE) {
       int id[TILE_U];
       T vv[TILE_U];
@@ -194,8 +265,8 @@ __device__ __forceinline__ bool primal_finish(int64_t j, T t, T tau, T xj, T cj,
 }
 
 template <typename T, bool C>
-__global__ __launch_bounds__(PDHG_TILE) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
-  __shared__ T lds[TILE_CAP + PDHG_TILE];
+__global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ __align__(16) T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = g.interleave ? b % g.ninst : find_inst_u(g.p_primal, g.ninst, b);
   const int lb = g.interleave ? b / g.ninst : b - cin(g.p_primal)[inst];
@@ -280,8 +351,8 @@ __device__ __forceinline__ bool dual_finish(int64_t i, T s, T sigma, T yi, T axi
 }
 
 template <typename T, bool C>
-__global__ __launch_bounds__(PDHG_TILE) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
-  __shared__ T lds[TILE_CAP + PDHG_TILE];
+__global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ __align__(16) T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = g.interleave ? b % g.ninst : find_inst_u(g.p_dual, g.ninst, b);
   const int lb = g.interleave ? b / g.ninst : b - cin(g.p_dual)[inst];
