@@ -76,7 +76,9 @@ def lib():
         L.orc_unrolled.restype = ctypes.c_int
         L.orc_implied_bounds.argtypes = [i64, i64] + [P] * 5 + [ctypes.c_int, P, P]
         L.orc_implied_bounds.restype = i64
-        L.orc_safe_bound.argtypes = [i64, i64] + [P] * 10
+        L.orc_safe_bound.argtypes = [i64, i64] + [P] * 12
+        L.orc_bound_repair.argtypes = [i64, i64] + [P] * 9
+        L.orc_bound_repair.restype = i64
         _lib = L
     return _lib
 
@@ -104,19 +106,40 @@ def implied_bounds(lp, passes=64):
     return lo, hi
 
 
-def safe_bound(lp, y, lo=None, hi=None) -> dict:
-    """Weak-duality lower bound on the optimum from y (y_i >= 0 enforced on
-    >= rows), with the bounds lo, hi (default: the implied bounds)."""
+def bound_repair(lp, lo=None, hi=None):
+    """(ylo, yhi): per row, the interval that keeps the reduced costs of its
+    single-entry columns with an infinite bound sign-feasible (with a 2^-40
+    relative margin), intersected with y >= 0 on >= rows.  lo, hi: the
+    bounds the safe bound uses (default: the implied bounds)."""
+    rp, ci, v, kind, b, c, l, u = _arrs(lp)
+    if lo is None or hi is None:
+        lo, hi = implied_bounds(lp)
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    ylo, yhi = np.empty(lp.m), np.empty(lp.m)
+    lib().orc_bound_repair(lp.m, lp.n, _p(rp), _p(ci), _p(v), _p(kind), _p(c), _p(lo), _p(hi),
+                           _p(ylo), _p(yhi))
+    return ylo, yhi
+
+
+def safe_bound(lp, y, lo=None, hi=None, repair=True) -> dict:
+    """Weak-duality lower bound on the optimum from y (projected on >= rows
+    and, with `repair`, clamped into the repair intervals), with the bounds
+    lo, hi (default: the implied bounds)."""
     rp, ci, v, kind, b, c, l, u = _arrs(lp)
     if lo is None or hi is None:
         lo, hi = implied_bounds(lp)
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
     y = np.ascontiguousarray(y, np.float64)
-    out = np.zeros(4)
+    ylo = yhi = None
+    if repair:
+        ylo, yhi = bound_repair(lp, lo, hi)
+    out = np.zeros(5)
     lib().orc_safe_bound(lp.m, lp.n, _p(rp), _p(ci), _p(v), _p(kind), _p(b), _p(c), _p(lo),
-                         _p(hi), _p(y), _p(out))
-    return dict(bound=out[0], value=out[1], allowance=out[2], infinite_terms=int(out[3]))
+                         _p(hi), _p(ylo), _p(yhi), _p(y), _p(out))
+    return dict(bound=out[0], value=out[1], allowance=out[2], infinite_terms=int(out[3]),
+                repaired_rows=int(out[4]))
 
 
 def validate(lp) -> int:

@@ -737,54 +737,136 @@ int64_t orc_implied_bounds(int64_t m, int64_t n, const int32_t *rp, const int32_
   return made;
 }
 
-/* A lower bound on the LP optimum from any y (weak duality).  With y_i
- * replaced by max(y_i, 0) on >= rows, every feasible x has
- *   c'x = b'y + y'(Ax - b) + lambda'x >= b'y + sum_j lambda_j x_j,
- * lambda = c - A'y, and x_j in [lo_j, hi_j] bounds the last sum from below
- * by lambda_j lo_j (lambda_j > 0) or lambda_j hi_j (lambda_j < 0).  A
- * nonzero lambda_j that needs an infinite bound makes the bound -INFINITY.
- * The computed value is lowered by 2 (K + 4) eps S, with eps = 2^-53,
- * K = n + m + (longest column) and S = sum_i |b_i y_i| +
- * sum_j |bound_j| (|c_j| + sum_i |a_ij y_i|), which exceeds the rounding
- * error of the sums.  out: [0] bound, [1] b'y + sum of bound terms (before
- * the allowance), [2] the allowance, [3] number of infinite terms. */
+/* Dual repair for the bound (reading of the safe-bound row): a column with a
+ * single nonzero a_ij whose bound on one side is infinite (a penalty slack
+ * with no upper limit) constrains y_i: u_j = +inf needs
+ * lambda_j = c_j - a_ij y_i >= 0, l_j = -inf needs lambda_j <= 0.  Each such
+ * constraint is a half-line for y_i with end t = c_j / a_ij, moved inward by
+ * 2^-40 |t| so that the repaired lambda_j clears its rounding error; the
+ * interval of row i is the intersection of its half-lines (and of y_i >= 0
+ * on >= rows).  An empty intersection gives no repair.  lo, hi are the
+ * bounds used for the bound (l, u tightened by the implied ones).  Returns
+ * the number of rows whose interval is narrower than the sign constraint. */
+int64_t orc_bound_repair(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci,
+                         const double *v, const uint8_t *kind, const double *c,
+                         const double *lo, const double *hi, double *ylo, double *yhi) {
+  int64_t *cnt = calloc((size_t)n, sizeof(int64_t));
+  int64_t *row = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  double *val = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int64_t i = 0; i < m; i++)
+    for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+      cnt[ci[k]]++;
+      row[ci[k]] = i;
+      val[ci[k]] = v[k];
+    }
+  for (int64_t i = 0; i < m; i++) {
+    ylo[i] = kind[i] == 1 ? 0.0 : -INFINITY;
+    yhi[i] = INFINITY;
+  }
+  const double margin = ldexp(1.0, -40);
+  for (int64_t j = 0; j < n; j++) {
+    if (cnt[j] != 1 || val[j] == 0.0) continue;
+    const int64_t i = row[j];
+    const double a = val[j], t = c[j] / a;
+    /* u_j = +inf: a y_i <= c_j; l_j = -inf: a y_i >= c_j */
+    if (isinf(hi[j])) {
+      if (a > 0.0) yhi[i] = fmin(yhi[i], t - margin * fabs(t));
+      else ylo[i] = fmax(ylo[i], t + margin * fabs(t));
+    }
+    if (isinf(lo[j])) {
+      if (a > 0.0) ylo[i] = fmax(ylo[i], t + margin * fabs(t));
+      else yhi[i] = fmin(yhi[i], t - margin * fabs(t));
+    }
+  }
+  int64_t fin = 0;
+  for (int64_t i = 0; i < m; i++) {
+    if (ylo[i] > yhi[i]) {
+      ylo[i] = kind[i] == 1 ? 0.0 : -INFINITY;
+      yhi[i] = INFINITY;
+    }
+    if (yhi[i] < INFINITY || ylo[i] > (kind[i] == 1 ? 0.0 : -INFINITY)) fin++;
+  }
+  free(cnt);
+  free(row);
+  free(val);
+  return fin;
+}
+
+/* A lower bound on the LP optimum from any y (weak duality).  With ytil the
+ * y projected on y_i >= 0 for >= rows and clamped into [ylo_i, yhi_i] (any
+ * such ytil will do; ylo/yhi may be NULL), every feasible x has
+ *   c'x = b'ytil + ytil'(Ax - b) + lambda'x >= b'ytil + sum_j lambda_j x_j,
+ * lambda = c - A'ytil, and x_j in [lo_j, hi_j] bounds the last sum from below
+ * by min(lambda_j lo_j, lambda_j hi_j).  lambda_j is computed as
+ * c_j - sum_i a_ij ytil_i in ascending i, each product rounded on its own;
+ * its rounding error is below err_j = 2 (k_j + 2) eps (|c_j| + sum_i
+ * |a_ij ytil_i|) (k_j entries in column j, eps = 2^-53).  Its sign is taken
+ * as known when |lambda_j| > err_j (or err_j = 0): the term is lambda_j times
+ * the bound that sign selects.  Otherwise the term is min(lambda_j lo_j,
+ * lambda_j hi_j) with both bounds finite.  A needed infinite bound makes the
+ * bound -INFINITY.  The computed value is lowered by 2 (K + 4) eps S with
+ * K = n + m + (longest column) and S = sum_i |b_i ytil_i| + sum_j B_j (|c_j|
+ * + sum_i |a_ij ytil_i|), B_j the bound used (both: the larger magnitude),
+ * which exceeds the rounding error of everything summed.  out: [0] bound,
+ * [1] value before the allowance, [2] the allowance, [3] number of needed
+ * infinite bounds, [4] number of rows whose y the repair changed. */
 void orc_safe_bound(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci,
                     const double *v, const uint8_t *kind, const double *b, const double *c,
-                    const double *lo, const double *hi, const double *y, double *out) {
+                    const double *lo, const double *hi, const double *ylo, const double *yhi,
+                    const double *y, double *out) {
   double *aty = calloc((size_t)n, sizeof(double));
   double *atyabs = calloc((size_t)n, sizeof(double));
   int64_t *clen = calloc((size_t)n, sizeof(int64_t));
   double by = 0.0, byabs = 0.0;
+  int64_t repaired = 0;
   for (int64_t i = 0; i < m; i++) {
     double yi = (kind[i] == 1 && y[i] < 0.0) ? 0.0 : y[i];
-    by += b[i] * yi;
-    byabs += fabs(b[i] * yi);
+    if (ylo && yhi) {
+      double yc = fmin(fmax(yi, ylo[i]), yhi[i]);
+      if (yc != yi) repaired++;
+      yi = yc;
+    }
+    double t = b[i] * yi;
+    by += t;
+    byabs += fabs(t);
     for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
-      aty[ci[k]] += v[k] * yi;
-      atyabs[ci[k]] += fabs(v[k] * yi);
+      double p = v[k] * yi;
+      aty[ci[k]] += p;
+      atyabs[ci[k]] += fabs(p);
       clen[ci[k]]++;
     }
   }
+  const double eps = ldexp(1.0, -53);
   double terms = 0.0, sabs = 0.0;
   int64_t ninf = 0, kmax = 0;
   for (int64_t j = 0; j < n; j++) {
-    double lam = c[j] - aty[j];
-    double bnd = lam > 0.0 ? lo[j] : (lam < 0.0 ? hi[j] : 0.0);
     if (clen[j] > kmax) kmax = clen[j];
-    if (lam == 0.0) continue;
-    if (isinf(bnd)) {
+    const double lam = c[j] - aty[j];
+    const double mag = fabs(c[j]) + atyabs[j];
+    const double err = 2.0 * (double)(clen[j] + 2) * eps * mag;
+    if (fabs(lam) > err || err == 0.0) {
+      if (lam == 0.0) continue;
+      const double bnd = lam > 0.0 ? lo[j] : hi[j];
+      if (isinf(bnd)) {
+        ninf++;
+        continue;
+      }
+      terms += lam * bnd;
+      sabs += fabs(bnd) * mag;
+    } else if (isinf(lo[j]) || isinf(hi[j])) {
       ninf++;
-      continue;
+    } else {
+      terms += fmin(lam * lo[j], lam * hi[j]);
+      sabs += fmax(fabs(lo[j]), fabs(hi[j])) * mag;
     }
-    terms += lam * bnd;
-    sabs += fabs(bnd) * (fabs(c[j]) + atyabs[j]);
   }
   double val = by + terms;
-  double allow = 2.0 * (double)(n + m + kmax + 4) * ldexp(1.0, -53) * (byabs + sabs);
+  double allow = 2.0 * (double)(n + m + kmax + 4) * eps * (byabs + sabs);
   out[0] = ninf ? -INFINITY : val - allow;
   out[1] = val;
   out[2] = allow;
   out[3] = (double)ninf;
+  out[4] = (double)repaired;
   free(aty);
   free(atyabs);
   free(clen);

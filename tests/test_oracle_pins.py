@@ -404,3 +404,80 @@ def test_implied_bounds_and_safe_bound_with_free_variables(oracle_mod):
         assert abs(r["bound"] - o2) <= 1e-8 * (1 + abs(o2)), (t, r, o2)
         checked += 1
     assert checked > 100
+
+
+def penalty_row_lp(d):
+    """x1 + s+ - s- = d, 0 <= x1 <= 5 (cost 1), s+, s- >= 0 (cost 100)."""
+    A = np.array([[1.0, 1.0, -1.0]])
+    return ucgen.dense_to_lp(A, np.array([0], np.uint8), np.array([d]), np.array([1.0, 100.0, 100.0]),
+                             np.zeros(3), np.array([5.0, np.inf, np.inf]))
+
+
+def test_bound_repair_closed_form(oracle_mod):
+    """A price above the slack penalty makes the plain bound -inf; the repair
+    clamps y to 100 (1 - 2^-40) and the bound becomes 5 + 2 y~, the optimum
+    205 of d = 7 up to the margin and the allowance.  A price below -100 is
+    clamped to -100 (1 - 2^-40) and stays a valid bound."""
+    lp = penalty_row_lp(7.0)
+    ylo, yhi = oracle_mod.bound_repair(lp)
+    assert yhi[0] == 100.0 - 100.0 * 2.0 ** -40 and ylo[0] == -100.0 + 100.0 * 2.0 ** -40
+    plain = oracle_mod.safe_bound(lp, np.array([150.0]), repair=False)
+    assert plain["bound"] == -np.inf and plain["infinite_terms"] == 1
+    r = oracle_mod.safe_bound(lp, np.array([150.0]))
+    yt = 100.0 - 100.0 * 2.0 ** -40
+    assert r["repaired_rows"] == 1 and r["infinite_terms"] == 0
+    assert abs(r["value"] - (5.0 + 2.0 * yt)) <= 1e-12 * 205
+    assert r["bound"] <= 205.0 and 205.0 - r["bound"] <= 1e-9
+    low = oracle_mod.safe_bound(lp, np.array([-150.0]))
+    assert np.isfinite(low["bound"]) and low["bound"] <= 205.0
+    assert abs(low["value"] - 7.0 * (-yt)) <= 1e-12 * 700
+
+
+def test_bound_sign_certainty(oracle_mod):
+    """x + z1 >= 1, x + z2 >= 1 with x >= 0 unbounded above (cost 1) and
+    z in [0, 1] (cost 2): at y = (1/2, 1/2) lambda_x = 0 within its rounding
+    error, and x has no upper bound, so no finite bound is certain; at
+    y = (1/4, 1/4) lambda_x = 1/2 is certain and the bound is 1/2 <= 1."""
+    A = np.array([[1.0, 1.0, 0.0], [1.0, 0.0, 1.0]])
+    lp = ucgen.dense_to_lp(A, np.array([1, 1], np.uint8), np.ones(2), np.array([1.0, 2.0, 2.0]),
+                           np.zeros(3), np.array([np.inf, 1.0, 1.0]))
+    st, x, opt, y = exact.highs(lp)
+    assert st == exact.OPTIMAL and abs(opt - 1.0) < 1e-12
+    assert oracle_mod.safe_bound(lp, np.array([0.5, 0.5]))["bound"] == -np.inf
+    r = oracle_mod.safe_bound(lp, np.array([0.25, 0.25]))
+    assert abs(r["value"] - 0.5) <= 1e-15 and r["bound"] <= 0.5
+
+
+def test_repaired_bound_below_optimum_on_slack_toys(oracle_mod):
+    """Random toys whose equality rows carry penalty slacks (single-entry
+    columns, no upper bound): for arbitrary y the repaired bound never exceeds
+    HiGHS's optimum, and at HiGHS's duals it is finite and equals it within
+    1e-9 (the duals lie inside the repair intervals)."""
+    rng = np.random.default_rng(41)
+    finite = 0
+    for t in range(150):
+        m, n = int(rng.integers(1, 4)), int(rng.integers(2, 5))
+        A, kind, b, c, lo, hi = ucgen.random_toy_lp(rng, m, n)
+        lo = np.where(np.isfinite(lo), lo, -3.0)
+        hi = np.where(np.isfinite(hi), hi, lo + 4.0)
+        eq = np.nonzero(kind == 0)[0]
+        S = np.zeros((m, 2 * len(eq)))
+        for q, i in enumerate(eq):
+            S[i, 2 * q], S[i, 2 * q + 1] = 1.0, -1.0
+        pen = 50.0
+        lp = ucgen.dense_to_lp(np.hstack([A, S]), kind, b,
+                               np.concatenate([c, np.full(2 * len(eq), pen)]),
+                               np.concatenate([lo, np.zeros(2 * len(eq))]),
+                               np.concatenate([hi, np.full(2 * len(eq), np.inf)]))
+        st, x, opt, yh = exact.highs(lp)
+        if st != exact.OPTIMAL:
+            continue
+        for _ in range(5):
+            y = rng.normal(0.0, 80.0, m)
+            r = oracle_mod.safe_bound(lp, y)
+            assert r["bound"] <= opt + 1e-12 * (1 + abs(opt)), (t, y, r, opt)
+        r = oracle_mod.safe_bound(lp, yh)
+        if np.isfinite(r["bound"]):
+            finite += 1
+            assert abs(r["bound"] - opt) <= 1e-9 * (1 + abs(opt)), (t, r, opt)
+    assert finite >= 60
