@@ -173,6 +173,49 @@ def batch_big_run(args):
                          "5800 lines, 48 periods), mixed, KKT 1e-4" % n)
 
 
+def nodes_run(args):
+    """Branch-and-bound nodes of the 4224-bus, 48-period LP: the root is
+    solved, then the children of its K most fractional commitments (each
+    fixed to 0 and to 1, 2K nodes) are solved as one batch, warm-started from
+    the root's point and, for comparison, cold.  Reports the time, attempts
+    and the safe bound's distance below each child's objective."""
+    import numpy as np
+    import torch
+    from paper_2512_06715_amd import nodes as N, ucgen
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc4224_t48")
+    prob = Problem(lp, tol=args.tol, precision="mixed", max_iter=args.max_iter)
+    ucols = lp.meta["u_cols"].ravel()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    root = N.solve_nodes(prob, [N.root()])[0]
+    t_root = time.perf_counter() - t0
+    picks = N.most_fractional(root, ucols, k=args.nodes)
+    out = dict(workload="children of the %d most fractional commitments of the root of "
+                        "uc4224_t48 (4224 buses, 700 units, 5800 lines, 48 periods), "
+                        "mixed, KKT %g" % (len(picks), args.tol),
+               root_s=round(t_root, 3), root_attempts=root.info["attempts"],
+               root_gap=(root.objective - root.bound) / abs(root.objective))
+    for warm in (True, False):
+        kids = [k for j in picks for k in N.branch(root, int(j))]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        N.solve_nodes(prob, kids, warm=warm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        gaps = np.array([(k.objective - k.bound) / abs(k.objective) for k in kids])
+        att = [k.info["attempts"] for k in kids]
+        out["warm" if warm else "cold"] = dict(
+            nodes=len(kids), solved=sum(k.info["status"] == 1 for k in kids),
+            batch_s=round(dt, 3), nodes_per_s=round(len(kids) / dt, 3),
+            attempts_mean=round(float(np.mean(att)), 1), attempts_max=int(max(att)),
+            bound_gap_median=float(np.median(gaps)), bound_gap_max=float(gaps.max()),
+            bounds_finite=int(np.isfinite([k.bound for k in kids]).sum()))
+    prob.close()
+    out["warm_speedup"] = round(out["cold"]["batch_s"] / out["warm"]["batch_s"], 3)
+    return out
+
+
 def adjoint_run():
     """Unrolled solve (1000 steps, checkpoints every 50) and its adjoint on the
     2000-bus, 24-period differentiable case."""
@@ -210,6 +253,9 @@ def main():
                     help="branch-and-bound variants of the 4224-bus, 48-period LP to batch "
                          "(one shared matrix; 0 skips this run)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--nodes", type=int, default=0,
+                    help="K > 0: branch-and-bound children of the K most fractional "
+                         "commitments of the 4224-bus LP's root, warm against cold")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
     ap.add_argument("--kernel-attempts", type=int, default=200)
@@ -306,6 +352,9 @@ def main():
     if args.batch_small > 0:
         print("[bench] batched solve ...", file=sys.stderr, flush=True)
         extra["batch"] = batch_run(args)
+    if args.nodes > 0:
+        print("[bench] branch-and-bound nodes ...", file=sys.stderr, flush=True)
+        extra["nodes"] = nodes_run(args)
     if args.batch_big > 0:
         print("[bench] batched branch-and-bound variants ...", file=sys.stderr, flush=True)
         extra["batch_big"] = batch_big_run(args)

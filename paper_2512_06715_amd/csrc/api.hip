@@ -150,6 +150,11 @@ struct pdhg_handle {
   double *ilo = nullptr, *ihi = nullptr;
   std::vector<double> h_ilo, h_ihi, h_l, h_u;
   bool impl_valid = false;
+  // the dual bound's repair interval of each row: device (scaled, internal
+  // order) and host (caller's order, original units)
+  double *rylo = nullptr, *ryhi = nullptr;
+  std::vector<double> h_ylo, h_yhi;
+  bool rep_valid = false;
   double bound_allow = 0.0;
   double *scratch;
   int nscratch = 0;
@@ -244,6 +249,8 @@ size_t layout(pdhg_handle *h, void *base) {
   h->perm_buf = h->o.reorder ? cv.take<int32_t>(m + 2 * n) : nullptr;
   h->ilo = cv.take<double>(n);
   h->ihi = cv.take<double>(n);
+  h->rylo = cv.take<double>(m);
+  h->ryhi = cv.take<double>(m);
   if (mixed) {
     h->vf = cv.take<float>(nnz + 2);
     h->vtf = cv.take<float>(nnz + 2);
@@ -452,6 +459,55 @@ int reorder_problem(pdhg_handle *h) {
   return PDHG_OK;
 }
 
+// The dual bound's repair interval of each row, in the caller's order and
+// units: a column with one nonzero a_ij and an infinite bound on a side
+// needs its reduced cost c_j - a_ij y_i to keep a sign (>= 0 for an infinite
+// upper bound, <= 0 for an infinite lower one), a half-line for y_i with end
+// t = c_j / a_ij moved inward by 2^-40 |t|; the row's interval is the
+// intersection of its half-lines with y_i >= 0 on >= rows (no repair when
+// it is empty).  lo, hi: l, u tightened by the implied bounds.
+void repair_intervals(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                      const uint8_t *kind, const double *c, const double *lo, const double *hi,
+                      std::vector<double> &ylo, std::vector<double> &yhi) {
+  std::vector<int32_t> cnt(n, 0);
+  std::vector<int64_t> row(n, 0);
+  std::vector<double> val(n, 0.0);
+  for (int64_t i = 0; i < m; i++)
+    for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
+      cnt[ci[k]]++;
+      row[ci[k]] = i;
+      val[ci[k]] = v[k];
+    }
+  ylo.assign(m, -INFINITY);
+  yhi.assign(m, INFINITY);
+  for (int64_t i = 0; i < m; i++)
+    if (kind[i] == 1) ylo[i] = 0.0;
+  const double margin = std::ldexp(1.0, -40);
+  for (int64_t j = 0; j < n; j++) {
+    if (cnt[j] != 1 || val[j] == 0.0) continue;
+    const int64_t i = row[j];
+    const double a = val[j], t = c[j] / a;
+    const double below = t - margin * std::fabs(t), above = t + margin * std::fabs(t);
+    if (std::isinf(hi[j])) {  // a y_i <= c_j
+      if (a > 0.0)
+        yhi[i] = std::fmin(yhi[i], below);
+      else
+        ylo[i] = std::fmax(ylo[i], above);
+    }
+    if (std::isinf(lo[j])) {  // a y_i >= c_j
+      if (a > 0.0)
+        ylo[i] = std::fmax(ylo[i], above);
+      else
+        yhi[i] = std::fmin(yhi[i], below);
+    }
+  }
+  for (int64_t i = 0; i < m; i++)
+    if (ylo[i] > yhi[i]) {
+      ylo[i] = kind[i] == 1 ? 0.0 : -INFINITY;
+      yhi[i] = INFINITY;
+    }
+}
+
 // Implied bounds of the caller's problem (original order and units), from
 // the host copy of the LP; the longest column sets the rounding allowance of
 // the dual bound.
@@ -495,6 +551,15 @@ int setup_implied_bounds(pdhg_handle *h, const pdhg_lp *lp) {
   h->h_ilo = h->h_l;
   h->h_ihi = h->h_u;
   implied_bounds(m, prp, pci, pv, pk, pb, 64, h->h_ilo.data(), h->h_ihi.data());
+  std::vector<double> hc(n);
+  if (h->on_device) {
+    HC(hipMemcpyAsync(hc.data(), lp->c, sizeof(double) * n, hipMemcpyDeviceToHost, h->hs));
+    HC(hipStreamSynchronize(h->hs));
+  } else {
+    std::copy(lp->c, lp->c + n, hc.begin());
+  }
+  repair_intervals(m, n, prp, pci, pv, pk, hc.data(), h->h_ilo.data(), h->h_ihi.data(), h->h_ylo,
+                   h->h_yhi);
   std::vector<int64_t> clen(n, 0);
   int64_t kmax = 0;
   for (int64_t k = 0; k < nnz; k++) kmax = std::max(kmax, ++clen[pci[k]]);
@@ -517,8 +582,21 @@ int upload_implied_bounds(pdhg_handle *h) {
   // (the scaled-c output of this launcher goes to the free buffer tg)
   launch_scale_vectors(nullptr, tl, tl, tu, h->Dr, h->Dc, 0, n, nullptr, tg, h->ilo, h->ihi, h->hs);
   HK();
-  HC(hipStreamSynchronize(h->hs));  // the host arrays stay, but keep setup ordered
+  // repair intervals: internal order, divided by the row factors (exact)
+  const int64_t m = h->m;
+  std::vector<double> dr(m), lo(m), hi(m);
+  HC(hipMemcpyAsync(dr.data(), h->Dr, sizeof(double) * m, hipMemcpyDeviceToHost, h->hs));
+  HC(hipStreamSynchronize(h->hs));
+  for (int64_t i = 0; i < m; i++) {
+    const int64_t r = h->rperm ? h->h_rperm[i] : i;
+    lo[i] = h->h_ylo[r] / dr[i];
+    hi[i] = h->h_yhi[r] / dr[i];
+  }
+  HC(hipMemcpyAsync(h->rylo, lo.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->hs));
+  HC(hipMemcpyAsync(h->ryhi, hi.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->hs));
+  HC(hipStreamSynchronize(h->hs));  // the host arrays go out of scope; keep setup ordered
   h->impl_valid = true;
+  h->rep_valid = true;
   return PDHG_OK;
 }
 
@@ -649,6 +727,8 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.xbest = sizeof(T) == 4 ? b.X[0] : nullptr;
   e.ilo = h->impl_valid ? h->ilo : nullptr;
   e.ihi = h->impl_valid ? h->ihi : nullptr;
+  e.rylo = h->rep_valid ? h->rylo : nullptr;
+  e.ryhi = h->rep_valid ? h->ryhi : nullptr;
   e.bound_allow = h->bound_allow;
   e.ybest = sizeof(T) == 4 ? b.Y[0] : nullptr;
   e.use_average = h->o.use_average;
@@ -952,6 +1032,31 @@ int solve_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
 }
 
 // Unscale every instance's result from the precision its solve ended in.
+// The safe dual bound of each instance's reported point, computed once after
+// the solve in the precision the instance finished in, into fin[].
+int bound_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
+                std::vector<Inst<float>> &i32, const std::vector<int> &final_fp32,
+                std::vector<CtlState> &fin) {
+  std::vector<int> a64, a32;
+  for (int i = 0; i < (int)i64.size(); i++) (final_fp32[i] ? a32 : a64).push_back(i);
+  Groups g{};
+  for (int pass = 0; pass < 2; pass++) {
+    const std::vector<int> &act = pass ? a32 : a64;
+    if (act.empty()) continue;
+    if (pass) {
+      RC(upload_group<float>(h, gd, i32, act, g));
+      launch_bound<float>(gd.d32, g, h->hs);
+    } else {
+      RC(upload_group<double>(h, gd, i64, act, g));
+      launch_bound<double>(gd.d64, g, h->hs);
+    }
+    HK();
+    RC(read_states(h, gd, (int)act.size(), pass == 1));
+    for (size_t k = 0; k < act.size(); k++) fin[act[k]].dual_bound = gd.hstates[k].dual_bound;
+  }
+  return PDHG_OK;
+}
+
 int unscale_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
                   std::vector<Inst<float>> &i32, const std::vector<int> &final_fp32) {
   std::vector<int> a64, a32;
@@ -1441,6 +1546,7 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, do
   std::vector<CtlState> fin;
   std::vector<int64_t> att32;
   RC(solve_group(h, h->grp, i64, i32, h->graph, true, t0, status, fin, att32, final_fp32));
+  RC(bound_group(h, h->grp, i64, i32, final_fp32, fin));
   RC(unscale_group(h, h->grp, i64, i32, final_fp32));
   if (!h->on_device) {
     HC(hipMemcpyAsync(x, xo, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->hs));
@@ -1671,6 +1777,10 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
       i64[k].e.ilo = i64[k].e.ihi = nullptr;
       i32[k].e.ilo = i32[k].e.ihi = nullptr;
     }
+    if (q.b || q.c || q.l || q.u) {  // and its repair intervals those and its c
+      i64[k].e.rylo = i64[k].e.ryhi = nullptr;
+      i32[k].e.rylo = i32[k].e.ryhi = nullptr;
+    }
     const double *wx = q.x0, *wy = q.y0;  // warm start, caller's order
     if (!hb->on_device) {
       if (q.x0) {
@@ -1697,6 +1807,7 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
   for (auto &g : gs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (rc) return rc;
+  RC(bound_group(h, P.gd, i64, i32, final_fp32, fin));
   RC(unscale_group(h, P.gd, i64, i32, final_fp32));
   for (int k = 0; k < batch; k++) {
     pdhg_handle *hb = handles[inst[k].base];
@@ -1735,8 +1846,12 @@ int pdhg_update(pdhg_handle *h, const double *b, const double *c) {
   if (b) {
     RC(to_internal(h, h->b0, b, h->on_device, h->rperm, h->m, h->it.YA));
     h->impl_valid = false;  // they were derived from the old right-hand side
+    h->rep_valid = false;
   }
-  if (c) RC(to_internal(h, h->c0, c, h->on_device, h->cperm, h->n, h->it.XA));
+  if (c) {
+    RC(to_internal(h, h->c0, c, h->on_device, h->cperm, h->n, h->it.XA));
+    h->rep_valid = false;  // the repair intervals come from the old costs
+  }
   launch_scale_vectors(h->b0, h->c0, h->l0, h->u0, h->Dr, h->Dc, h->m, h->n, h->b, h->c, h->l,
                        h->u, h->hs);
   launch_init_ctl(h->v, h->nnz, h->b, h->c, h->b0, h->c0, h->m, h->n, h->scratch, h->nscratch,

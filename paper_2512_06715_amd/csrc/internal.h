@@ -105,6 +105,9 @@ struct EvalView {
   double *xbest, *ybest;
   // implied bounds (scaled, internal order) for the dual bound; null: use l, u
   const double *ilo, *ihi;
+  // the dual bound's repair interval of each row (scaled, internal order);
+  // null: no repair
+  const double *rylo, *ryhi;
   double bound_allow;            // rounding allowance factor 2 (n + m + longest column + 4) 2^-53
   int use_average, restart;
   double pw_theta;               // 0 keeps the primal weight
@@ -113,8 +116,8 @@ struct EvalView {
   const int32_t *rperm, *cperm;
 };
 
-#define EV_ROWQ 12
-#define EV_COLQ 18
+#define EV_ROWQ 10
+#define EV_COLQ 12
 
 // ---------------------------------------------------------------------------
 // launchers (setup.hip)
@@ -212,6 +215,8 @@ void launch_attempt(const Inst<T> *I, const Groups &g, hipStream_t s);
 template <typename T>
 void launch_evaluate(const Inst<T> *I, const Groups &g, double tol, int64_t max_iter,
                      hipStream_t s);
+template <typename T>
+void launch_bound(const Inst<T> *I, const Groups &g, hipStream_t s);
 template <typename T>
 void launch_init_point(const Inst<T> *I, const Groups &g, hipStream_t s);
 void launch_switch_to_fp64(const Inst<float> *If, const Inst<double> *Id, const Groups &g,

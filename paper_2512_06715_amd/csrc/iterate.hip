@@ -258,7 +258,7 @@ template <typename X0>
 __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, const double *v_,
                                     const X0 *x0_, const double *x1_, int64_t i, bool valid,
                                     int base, int top, int long_seg, double *lds, double &s0,
-                                    double &s1, double &a0, double &a1, bool &mine) {
+                                    double &s1, bool &mine) {
   const AS_G int32_t *ptr = gin(ptr_), *idx = gin(idx_);
   const AS_G double *v = gin(v_), *x1 = gin(x1_);
   const AS_G X0 *x0 = gin(x0_);
@@ -266,7 +266,7 @@ __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, co
   const bool two = x1_ != nullptr;
   double *lds1 = lds + EV_TILE_CAP + PDHG_BLOCK;
   int rs = 0, re = 0;
-  s0 = s1 = a0 = a1 = 0.0;
+  s0 = s1 = 0.0;
   if (cnt <= EV_TILE_CAP) {
     for (int k0 = 0; k0 < cnt; k0 += 4 * PDHG_BLOCK) {
       int id[4];
@@ -297,15 +297,9 @@ __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, co
     __syncthreads();
     mine = valid && (re - rs <= long_seg);
     if (mine) {
-      for (int k = rs - base; k < re - base; k++) {
-        s0 += lds[k];
-        a0 += fabs(lds[k]);
-      }
+      for (int k = rs - base; k < re - base; k++) s0 += lds[k];
       if (two)
-        for (int k = rs - base; k < re - base; k++) {
-          s1 += lds1[k];
-          a1 += fabs(lds1[k]);
-        }
+        for (int k = rs - base; k < re - base; k++) s1 += lds1[k];
     }
     __syncthreads();
   } else {
@@ -316,14 +310,8 @@ __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, co
     mine = valid && (re - rs <= long_seg);
     if (mine)
       for (int k = rs; k < re; k++) {
-        double p0 = __dmul_rn(v[k], (double)x0[idx[k]]);
-        s0 += p0;
-        a0 += fabs(p0);
-        if (two) {
-          double p1 = __dmul_rn(v[k], x1[idx[k]]);
-          s1 += p1;
-          a1 += fabs(p1);
-        }
+        s0 += __dmul_rn(v[k], (double)x0[idx[k]]);
+        if (two) s1 += __dmul_rn(v[k], x1[idx[k]]);
       }
   }
 }
@@ -331,8 +319,7 @@ __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, co
 // Row-space KKT pieces for the current point and the average, with A x_avg
 // computed here (and kept for a restart to the average):
 // [0] ||r_p||^2 scaled [1] ||r_p||^2 unscaled [2] ||r_p||_inf unscaled
-// [3] b'y [4] ||y - y_last||^2, then the same five for the average;
-// [10], [11] sum |b_i y_i| (current, average) for the dual bound's allowance.
+// [3] b'y [4] ||y - y_last||^2, then the same five for the average.
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ double lds[2 * (EV_TILE_CAP + PDHG_BLOCK)];
@@ -342,10 +329,10 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(const Inst<T> *__restr
   double axa = 0.0;
   if (avg) {
     int64_t r0 = (int64_t)lb * PDHG_BLOCK, rend = r0 + PDHG_BLOCK < e.m ? r0 + PDHG_BLOCK : e.m;
-    double unused[3];
+    double unused;
     bool mine;
     eval_rowdots<double>(e.rp, e.ci, e.v, e.XA, nullptr, i, i < e.m, e.rp[r0], e.rp[rend],
-                         e.long_seg, lds, axa, unused[0], unused[1], unused[2], mine);
+                         e.long_seg, lds, axa, unused, mine);
     if (i < e.m) {
       if (mine)
         e.AXA[i] = axa;
@@ -373,7 +360,6 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_rows(const Inst<T> *__restr
       q[5 * p + 2] = fabs(ru);
       q[5 * p + 3] = bi * yi;
       q[5 * p + 4] = (yi - yl) * (yi - yl);
-      q[10 + p] = fabs(bi * yi);
     }
   }
   double out[EV_ROWQ];
@@ -399,31 +385,22 @@ __device__ inline double bound_term(uint8_t vk, double lam, double l, double u) 
 // Column-space KKT pieces, with A'y and A'y_avg computed here:
 // [0] ||r_d||^2 scaled [1] ||r_d||^2 unscaled
 // [2] ||r_d||_inf unscaled [3] bound part of the dual objective [4] c'x
-// [5] ||x - x_last||^2, then the same six for the average; then for the
-// dual bound [12] sum of lambda_j times the bound the sign of lambda_j
-// selects (finite ones), [13] count of infinite ones, [14] allowance part
-// sum |bound_j| (|c_j| + sum_i |a_ij y_i|); [15..17] the same for the average.
+// [5] ||x - x_last||^2, then the same six for the average.
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ double lds[2 * (EV_TILE_CAP + PDHG_BLOCK)];
   GROUP_BLOCK(p_cols)
   int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   bool avg = have_avg(st, e.use_average);
-  double aty[2], atyabs[2];
+  double aty[2];
   {
     int64_t c0 = (int64_t)lb * PDHG_BLOCK, cend = c0 + PDHG_BLOCK < e.n ? c0 + PDHG_BLOCK : e.n;
     bool mine;
     eval_rowdots<T>(e.cp, e.ri, e.vt, e.Y[st->cur], avg ? e.YA : nullptr, j, j < e.n, e.cp[c0],
-                    e.cp[cend], e.long_seg, lds, aty[0], aty[1], atyabs[0], atyabs[1], mine);
+                    e.cp[cend], e.long_seg, lds, aty[0], aty[1], mine);
     if (j < e.n && !mine) {  // long column: its own workgroup computed the sums
       aty[0] = e.ATY[j];
       if (avg) aty[1] = e.ATYA[j];
-      atyabs[0] = atyabs[1] = 0.0;
-      const T *yc = e.Y[st->cur];
-      for (int k = e.cp[j]; k < e.cp[j + 1]; k++) {
-        atyabs[0] += fabs(__dmul_rn(e.vt[k], (double)yc[e.ri[k]]));
-        if (avg) atyabs[1] += fabs(__dmul_rn(e.vt[k], e.YA[e.ri[k]]));
-      }
     }
   }
   double q[EV_COLQ];
@@ -434,12 +411,6 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(const Inst<T> *__restr
     double cj = gin(e.c)[j], dc = gin(e.Dc)[j], lj = gin(e.l)[j], uj = gin(e.u)[j];
     double xl = gin((const double *)e.XL)[j];
     uint8_t vk = gin(e.vk)[j];
-    // bounds for the dual bound: l, u, tightened by the implied ones
-    double blo = lj, bhi = uj;
-    if (e.ilo) {
-      blo = fmax(blo, gin(e.ilo)[j]);
-      bhi = fmin(bhi, gin(e.ihi)[j]);
-    }
 #pragma unroll
     for (int p = 0; p < 2; p++) {  // constant indices keep q in registers
       if (p == 1 && !avg) break;
@@ -454,13 +425,6 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_cols(const Inst<T> *__restr
       q[6 * p + 3] = bound_term(vk, pl, lj, uj);
       q[6 * p + 4] = cj * xj;
       q[6 * p + 5] = (xj - xl) * (xj - xl);
-      double bnd = lam > 0.0 ? blo : (lam < 0.0 ? bhi : 0.0);
-      if (lam != 0.0 && isinf(bnd)) {
-        q[12 + 3 * p + 1] = 1.0;
-      } else if (lam != 0.0) {
-        q[12 + 3 * p + 0] = lam * bnd;
-        q[12 + 3 * p + 2] = fabs(bnd) * (fabs(cj) + atyabs[p]);
-      }
     }
   }
   double out[EV_COLQ];
@@ -620,12 +584,6 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const Inst<T> *__re
     }
   }
   st->which = which;
-  {  // weak-duality bound of the reported point's y
-    const bool at_avg = rep == &pa && avg;
-    const double *r = rq + (at_avg ? 5 : 0), *cc = cq + (at_avg ? 15 : 12);
-    const double byabs = rq[at_avg ? 11 : 10];
-    st->dual_bound = cc[1] > 0.0 ? -INFINITY : (r[3] + cc[0]) - e.bound_allow * (byabs + cc[2]);
-  }
   st->stash = 0;
   if (e.xbest && rep->rel_kkt < st->best_kkt) {  // FP32 phase: new best point
     st->stash = 1;
@@ -690,6 +648,113 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_restart_rows(const Inst<T> *__re
   e.YL[i] = (double)y[i];
 }
 
+// ---------------------------------------------------------------------------
+// safe dual bound of the reported point, once after the solve (FP64)
+//
+// Weak duality: for any y~ with y~_i >= 0 on >= rows, every feasible x has
+// c'x >= b'y~ + sum_j lambda_j x_j >= b'y~ + sum_j min(lambda_j lo_j,
+// lambda_j hi_j), lambda = c - A'y~, with [lo, hi] = [l, u] tightened by the
+// implied bounds.  y~ is the reported y, projected on >= rows and clamped
+// into the row's repair interval (which keeps the reduced costs of
+// single-entry columns with an infinite bound sign-feasible).  In the scaled
+// problem every term equals its unscaled counterpart exactly (power-of-two
+// factors).
+
+// Rows: y~ into YL (the restart anchor, unused after the solve); partials
+// [0] b'y~, [1] sum |b_i y~_i|.
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_bound_rows(const Inst<T> *__restrict__ I,
+                                                           Groups g) {
+  GROUP_BLOCK(p_rows)
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  double q[2] = {0.0, 0.0};
+  if (i < e.m) {
+    double yi = st->which ? gin((const double *)e.YA)[i] : (double)gin((const T *)e.Y[st->cur])[i];
+    if (gin(e.kind)[i] == 1 && yi < 0.0) yi = 0.0;
+    if (e.rylo) yi = fmin(fmax(yi, gin(e.rylo)[i]), gin(e.ryhi)[i]);
+    gout(e.YL)[i] = yi;
+    double t = __dmul_rn(gin(e.b)[i], yi);
+    q[0] = t;
+    q[1] = fabs(t);
+  }
+  double out[2];
+  block_reduce<2>(q, 0u, out);
+  if (threadIdx.x == 0) {
+    e.part_rows[lb] = out[0];
+    e.part_rows[(int64_t)e.nblk_rows + lb] = out[1];
+  }
+}
+
+// Columns, one lane per column: lambda_j = c_j - sum_i a_ij y~_i in the
+// stored transpose's (ascending row) order, each product rounded on its
+// own, and its rounding error bound err = 2 (k + 2) 2^-53 (|c_j| +
+// sum_i |a_ij y~_i|) over the column's k entries.  With |lambda_j| > err (or
+// err = 0) its sign is certain and the term is lambda_j times the bound that
+// sign selects; otherwise the term is min(lambda_j lo_j, lambda_j hi_j) with
+// both bounds finite.  A needed infinite bound is counted.  Partials [0] sum
+// of terms, [1] sum of B_j (|c_j| + sum_i |a_ij y~_i|) with B_j the bound
+// used (the larger magnitude when both), [2] count of needed infinite bounds.
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_bound_cols(const Inst<T> *__restrict__ I,
+                                                           Groups g) {
+  GROUP_BLOCK(p_cols)
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  double q[3] = {0.0, 0.0, 0.0};
+  if (j < e.n) {
+    const AS_G int32_t *cp = gin(e.cp), *ri = gin(e.ri);
+    const AS_G double *vt = gin(e.vt), *yt = gin((const double *)e.YL);
+    const int a = cp[j], z = cp[j + 1];
+    double s = 0.0, sa = 0.0;
+    for (int k = a; k < z; k++) {
+      double pr = __dmul_rn(vt[k], yt[ri[k]]);
+      s += pr;
+      sa += fabs(pr);
+    }
+    const double cj = gin(e.c)[j];
+    const double lam = cj - s, mag = fabs(cj) + sa;
+    const double err = 2.0 * (double)(z - a + 2) * 0x1p-53 * mag;
+    double lo = gin(e.l)[j], hi = gin(e.u)[j];
+    if (e.ilo) {
+      lo = fmax(lo, gin(e.ilo)[j]);
+      hi = fmin(hi, gin(e.ihi)[j]);
+    }
+    if (fabs(lam) > err || err == 0.0) {
+      if (lam != 0.0) {
+        double bnd = lam > 0.0 ? lo : hi;
+        if (isinf(bnd)) {
+          q[2] = 1.0;
+        } else {
+          q[0] = __dmul_rn(lam, bnd);
+          q[1] = fabs(bnd) * mag;
+        }
+      }
+    } else if (isinf(lo) || isinf(hi)) {
+      q[2] = 1.0;
+    } else {
+      q[0] = fmin(__dmul_rn(lam, lo), __dmul_rn(lam, hi));
+      q[1] = fmax(fabs(lo), fabs(hi)) * mag;
+    }
+  }
+  double out[3];
+  block_reduce<3>(q, 0u, out);
+  if (threadIdx.x == 0)
+    for (int t = 0; t < 3; t++) e.part_cols[(int64_t)t * e.nblk_cols + lb] = out[t];
+}
+
+// One workgroup per instance: the partials in fixed order, then
+// bound = b'y~ + sum of terms - bound_allow (sum |b_i y~_i| + sum of the
+// magnitudes), or -infinity when a needed bound is infinite.
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_bound_finish(const Inst<T> *__restrict__ I) {
+  const EvalView<T> &e = I[blockIdx.x].e;
+  CtlState *st = I[blockIdx.x].st;
+  double r[2], c[3];
+  reduce_partials<2, PDHG_BLOCK>(e.part_rows, e.nblk_rows, e.nblk_rows, 0u, r);
+  reduce_partials<3, PDHG_BLOCK>(e.part_cols, e.nblk_cols, e.nblk_cols, 0u, c);
+  if (threadIdx.x == 0)
+    st->dual_bound = c[2] > 0.0 ? -INFINITY : (r[0] + c[0]) - e.bound_allow * (r[1] + c[1]);
+}
+
 // Start point: x = proj_[l,u](x0 / Dc) (0 if no x0), y = proj_Y(y0 / Dr).
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_init_cols(const Inst<T> *__restrict__ I, Groups g) {
@@ -743,6 +808,7 @@ __global__ void k_init_state(const Inst<T> *__restrict__ I) {
   st->init_pending = 1;
   st->ticket = 0;
   st->best_kkt = INFINITY;
+  st->dual_bound = -INFINITY;  // computed after the solve
   st->stash = 0;
   st->eta = st->eta0;
   st->omega = st->omega0;
@@ -1070,6 +1136,13 @@ void launch_evaluate(const Inst<T> *I, const Groups &g, double tol, int64_t max_
 }
 
 template <typename T>
+void launch_bound(const Inst<T> *I, const Groups &g, hipStream_t s) {
+  k_bound_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
+  k_bound_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
+  k_bound_finish<T><<<grid_of(g.ninst), PDHG_BLOCK, 0, s>>>(I);
+}
+
+template <typename T>
 void launch_init_point(const Inst<T> *I, const Groups &g, hipStream_t s) {
   k_init_state<T><<<grid_of(g.ninst), 1, 0, s>>>(I);
   k_init_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
@@ -1155,6 +1228,7 @@ void launch_spmv(const int32_t *rp, const int32_t *ci, const double *v, int64_t 
   template void launch_evaluate<T>(const Inst<T> *, const Groups &, double, int64_t,       \
                                    hipStream_t);                                           \
   template void launch_init_point<T>(const Inst<T> *, const Groups &, hipStream_t);        \
+  template void launch_bound<T>(const Inst<T> *, const Groups &, hipStream_t);             \
   template void launch_unscale<T>(const Inst<T> *, const Groups &, hipStream_t);            \
   template void launch_gather_states<T>(const Inst<T> *, int, CtlState *, hipStream_t);        \
   template void launch_checkpoint<T>(const Inst<T> *, const Groups &, double *, double *,    \

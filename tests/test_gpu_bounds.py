@@ -85,3 +85,31 @@ def test_warm_started_nodes_keep_valid_bounds(gpu, oracle_mod):
         assert ik["dual_bound"] <= opt and cold[k][2]["dual_bound"] <= opt, k
         assert oracle_mod.kkt(lpk[k], xk, yk)["rel_kkt"] <= 1.001e-5
     assert sum(w[2]["attempts"] for w in warm) <= sum(c[2]["attempts"] for c in cold)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_dual_bound_finite_at_scale(gpu, oracle_mod, precision):
+    """The 1000-bus, 48-period UC relaxation at tolerance 1e-4: its penalty
+    slacks (single-entry columns without an upper bound) would make the plain
+    bound -inf at an approximate y; with the repair the bound is finite, below
+    the reference optimum, within 1e-3 of it, and equal to the oracle's bound
+    at the returned y within the allowances."""
+    import json
+    import os
+    from paper_2512_06715_amd.solver import Problem
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lp_refs.json")))
+    opt = ref["uc1000_t48"]["objective"]
+    lp = ucgen.workload("uc1000_t48")
+    print("case bound at scale", precision, flush=True)
+    p = Problem(lp, tol=1e-4, precision=precision)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 1
+    db = info["dual_bound"]
+    r = oracle_mod.safe_bound(lp, y)
+    plain = oracle_mod.safe_bound(lp, y, repair=False)
+    print("bound", db, "oracle", r["bound"], "repaired rows", r["repaired_rows"],
+          "plain", plain["bound"], "gap", (opt - db) / abs(opt), flush=True)
+    assert np.isfinite(db) and db <= opt + 1e-9 * abs(opt)
+    assert (opt - db) <= 1e-3 * abs(opt)
+    assert abs(db - r["bound"]) <= 4 * r["allowance"] + 1e-12 * abs(r["value"])

@@ -1,0 +1,52 @@
+"""The node driver on the GPU: two levels of children of the 14-bus UC
+relaxation, solved as warm-started batches, against HiGHS and the oracle."""
+import numpy as np
+import pytest
+
+from oracle import exact
+from paper_2512_06715_amd import ucgen
+
+pytestmark = pytest.mark.gpu
+
+
+def node_lp(lp, nd):
+    q = lp.copy()
+    q.l[nd.fix_idx] = nd.fix_val
+    q.u[nd.fix_idx] = nd.fix_val
+    return q
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_levels_of_nodes(gpu, oracle_mod, precision):
+    """Root, its two children (most fractional commitment) and their four
+    children: every node reaches its tolerance (oracle KKT), its safe bound
+    is below its HiGHS optimum and within 1e-3 of it, children never beat
+    their parent's optimum, and pruning against an incumbent drops only
+    nodes whose optimum is above it."""
+    from paper_2512_06715_amd import nodes as N
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc14_t24")
+    ucols = lp.meta["u_cols"].ravel()
+    print("case nodes", precision, flush=True)
+    p = Problem(lp, tol=1e-5, precision=precision, max_iter=1000000)
+    root = N.solve_nodes(p, [N.root()])[0]
+    level1 = list(N.branch(root, int(N.most_fractional(root, ucols)[0])))
+    N.solve_nodes(p, level1)
+    level2 = [k for nd in level1 for k in N.branch(nd, int(N.most_fractional(nd, ucols)[0]))]
+    N.solve_nodes(p, level2)
+    p.close()
+    opt = {}
+    for nd in [root] + level1 + level2:
+        st, xh, o, yh = exact.highs(node_lp(lp, nd))
+        assert st == exact.OPTIMAL and nd.info["status"] == 1
+        assert oracle_mod.kkt(node_lp(lp, nd), nd.x, nd.y)["rel_kkt"] <= 1.001e-5
+        assert nd.bound <= o and o - nd.bound <= 1e-3 * (1 + abs(o)), (nd.fixed(), nd.bound, o)
+        opt[id(nd)] = o
+    for parent, kids in ((root, level1), (level1[0], level2[:2]), (level1[1], level2[2:])):
+        for k in kids:
+            assert opt[id(k)] >= opt[id(parent)] - 1e-9 * abs(opt[id(parent)])
+    incumbent = float(np.median([opt[id(n)] for n in level2]))
+    kept, cut = N.prune(level2, incumbent)
+    assert all(opt[id(n)] > incumbent for n in cut)
+    print("bounds", [round(n.bound, 3) for n in level2], "incumbent", incumbent,
+          "pruned", len(cut), flush=True)
