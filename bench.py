@@ -177,8 +177,9 @@ def nodes_run(args):
     """Branch-and-bound nodes of the 4224-bus, 48-period LP: the root is
     solved, then the children of its K most fractional commitments (each
     fixed to 0 and to 1, 2K nodes) are solved as one batch, warm-started from
-    the root's point and, for comparison, cold.  Reports the time, attempts
-    and the safe bound's distance below each child's objective."""
+    the root's point, primal weight and step size; for comparison from the
+    point alone, and cold.  Reports the time, attempts and the safe bound's
+    distance below each child's objective."""
     import numpy as np
     import torch
     from paper_2512_06715_amd import nodes as N, ucgen
@@ -196,16 +197,16 @@ def nodes_run(args):
                         "mixed, KKT %g" % (len(picks), args.tol),
                root_s=round(t_root, 3), root_attempts=root.info["attempts"],
                root_gap=(root.objective - root.bound) / abs(root.objective))
-    for warm in (True, False):
+    for mode in ("warm", "warm_point_only", "cold"):
         kids = [k for j in picks for k in N.branch(root, int(j))]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        N.solve_nodes(prob, kids, warm=warm)
+        N.solve_nodes(prob, kids, warm=mode != "cold", weights=mode == "warm")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         gaps = np.array([(k.objective - k.bound) / abs(k.objective) for k in kids])
         att = [k.info["attempts"] for k in kids]
-        out["warm" if warm else "cold"] = dict(
+        out[mode] = dict(
             nodes=len(kids), solved=sum(k.info["status"] == 1 for k in kids),
             batch_s=round(dt, 3), nodes_per_s=round(len(kids) / dt, 3),
             attempts_mean=round(float(np.mean(att)), 1), attempts_max=int(max(att)),

@@ -160,9 +160,15 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x,
  * non-null (original space, same memory kind as the base LP), and the n_fix
  * (index, value) pairs fix variables (l = u = value) on top of the bounds.
  * x0[n], y0[m] (nullable, same memory kind) warm-start the instance, e.g.
- * a child node from its parent's solution.  The dual bound of an instance
- * uses the base's implied bounds only when b, l and u are not overridden
- * (fixings only tighten the bounds the implied ones were derived from). */
+ * a child node from its parent's solution; omega0, eta0 > 0 replace the
+ * initial primal weight and step size (scaled-space values, as pdhg_info
+ * reports them: a child can continue with its parent's), 0 keeps the
+ * defaults; fix_omega != 0 keeps the primal weight at its initial value (no
+ * update at restarts), which suits a start close to the optimum.  The dual
+ * bound of an instance uses the base's implied bounds
+ * only when b, l and u are not overridden (fixings only tighten the bounds
+ * the implied ones were derived from), and its repair intervals only when
+ * b, c, l and u are not overridden. */
 typedef struct {
   int32_t base;
   const double *b, *c, *l, *u;
@@ -170,6 +176,8 @@ typedef struct {
   const double *fix_val;
   int64_t n_fix;
   const double *x0, *y0;
+  double omega0, eta0;
+  int32_t fix_omega;
 } pdhg_instance;
 
 /* Device workspace bytes for pdhg_solve_batch with these instances. */

@@ -54,7 +54,8 @@ class PdhgInfo(ctypes.Structure):
 
 class PdhgInstance(ctypes.Structure):
     _fields_ = [("base", ctypes.c_int32), ("b", vp), ("c", vp), ("l", vp), ("u", vp),
-                ("fix_idx", vp), ("fix_val", vp), ("n_fix", c_i64), ("x0", vp), ("y0", vp)]
+                ("fix_idx", vp), ("fix_val", vp), ("n_fix", c_i64), ("x0", vp), ("y0", vp),
+                ("omega0", c_dbl), ("eta0", c_dbl), ("fix_omega", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes)

@@ -1645,6 +1645,9 @@ int check_batch(pdhg_handle *const *handles, int n_handles, const pdhg_instance 
       return fail(PDHG_ERR_ARG, "instance %d: base %d out of range", k, inst[k].base);
     if (inst[k].n_fix < 0 || (inst[k].n_fix > 0 && (!inst[k].fix_idx || !inst[k].fix_val)))
       return fail(PDHG_ERR_ARG, "instance %d: bad fixings", k);
+    if (!(inst[k].omega0 >= 0.0 && std::isfinite(inst[k].omega0)) ||
+        !(inst[k].eta0 >= 0.0 && std::isfinite(inst[k].eta0)))
+      return fail(PDHG_ERR_ARG, "instance %d: omega0 and eta0 must be finite and >= 0", k);
     const pdhg_handle *h = handles[inst[k].base];
     if (!h->on_device)
       for (int64_t q = 0; q < inst[k].n_fix; q++)
@@ -1766,9 +1769,10 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
     }
     HK();
     // initial step size, primal weight and the norms of this instance's b and c
+    const double eta0 = q.eta0 > 0.0 ? q.eta0 : (hb->o.step_mode == 1 ? hb->o.fixed_eta : 0.0);
+    const double omega0 = q.omega0 > 0.0 ? q.omega0 : hb->o.fixed_omega;
     launch_init_ctl(hb->v, hb->nnz, d.b, d.c, q.b ? P.b0[k] : hb->b0, q.c ? P.c0[k] : hb->c0, m, n,
-                    hb->scratch, hb->nscratch, ib.st, hb->o.step_mode,
-                    hb->o.step_mode == 1 ? hb->o.fixed_eta : 0.0, hb->o.fixed_omega, h->hs);
+                    hb->scratch, hb->nscratch, ib.st, hb->o.step_mode, eta0, omega0, h->hs);
     HK();
     HC(hipStreamSynchronize(h->hs));  // the base's scratch is reused by the next instance
     i64[k] = make_inst<double>(hb, d, ib);
@@ -1777,6 +1781,7 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
       i64[k].e.ilo = i64[k].e.ihi = nullptr;
       i32[k].e.ilo = i32[k].e.ihi = nullptr;
     }
+    if (q.fix_omega) i64[k].e.pw_theta = i32[k].e.pw_theta = 0.0;  // no weight updates
     if (q.b || q.c || q.l || q.u) {  // and its repair intervals those and its c
       i64[k].e.rylo = i64[k].e.ryhi = nullptr;
       i32[k].e.rylo = i32[k].e.ryhi = nullptr;

@@ -35,6 +35,8 @@ class Node:
     depth: int = 0
     x0: Optional[np.ndarray] = None
     y0: Optional[np.ndarray] = None
+    omega0: float = 0.0   # parent's final primal weight and step size (0: defaults)
+    eta0: float = 0.0
     x: Optional[np.ndarray] = None
     y: Optional[np.ndarray] = None
     info: Optional[dict] = None
@@ -64,14 +66,16 @@ def branch(node: Node, col: int) -> Tuple[Node, Node]:
     """The two children of a solved node that fix column `col` to 0 and to 1,
     both warm-started from the node's point."""
     if not node.solved:
-        raise ValueError("branch on a solved node")
+        raise ValueError("branch needs a solved node")
     if col in set(node.fix_idx.tolist()):
         raise ValueError(f"column {col} is already fixed at this node")
     kids = []
     for v in (0.0, 1.0):
         idx = np.append(node.fix_idx, np.int32(col)).astype(np.int32)
         val = np.append(node.fix_val, v).astype(np.float64)
-        kids.append(Node(idx, val, node.depth + 1, x0=node.x, y0=node.y))
+        kids.append(Node(idx, val, node.depth + 1, x0=node.x, y0=node.y,
+                         omega0=float(node.info.get("omega", 0.0)),
+                         eta0=float(node.info.get("eta", 0.0))))
     return kids[0], kids[1]
 
 
@@ -88,10 +92,15 @@ def most_fractional(node: Node, cols: Sequence[int], k: int = 1) -> np.ndarray:
     return free[order[:k]]
 
 
-def solve_nodes(problem, nodes: List[Node], warm: bool = True) -> List[Node]:
+def solve_nodes(problem, nodes: List[Node], warm: bool = True,
+                weights: bool = True) -> List[Node]:
     """Solve the nodes' LPs in one batched run on `problem` (a solver.Problem
     of the base LP).  With `warm`, each node starts from its x0, y0 when it
-    has them.  Fills x, y and info of every node and returns the list."""
+    has them; with `weights` also from its parent's step size and primal
+    weight, which then stays fixed (near the optimum the restarts' weight
+    updates see little primal movement and drive the weight up by a factor
+    of about 1.5 per restart, stalling the primal iterate).  Fills x, y and
+    info of every node and returns the list."""
     if not nodes:
         return nodes
     insts = []
@@ -101,6 +110,8 @@ def solve_nodes(problem, nodes: List[Node], warm: bool = True) -> List[Node]:
         if warm and nd.x0 is not None and nd.y0 is not None:
             d["x0"] = _like(problem, nd.x0, np.float64)
             d["y0"] = _like(problem, nd.y0, np.float64)
+            if weights:
+                d["omega0"], d["eta0"], d["fix_omega"] = nd.omega0, nd.eta0, True
         insts.append(d)
     for nd, (x, y, info) in zip(nodes, solve_batch([problem], insts)):
         nd.x, nd.y, nd.info = x, y, info

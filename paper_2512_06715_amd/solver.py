@@ -197,8 +197,10 @@ def solve_batch(problems, instances, stream=None):
     problems: list of Problem (the bases; same precision).
     instances: list of dicts with key 'base' (index into problems) and optional
     'b', 'c', 'l', 'u' (original-space overrides), 'fix_idx', 'fix_val'
-    (variables fixed to a value) and 'x0', 'y0' (warm start).  Host problems take numpy arrays, device
-    problems torch CUDA tensors.  Returns a list of (x, y, info dict).
+    (variables fixed to a value), 'x0', 'y0' (warm start), 'omega0',
+    'eta0' (initial primal weight and step size, scaled space; 0 or absent:
+    the defaults) and 'fix_omega' (true: no primal-weight updates).  Host problems take numpy arrays, device problems torch
+    CUDA tensors.  Returns a list of (x, y, info dict).
     """
     import torch
     lib = L.load()
@@ -227,7 +229,9 @@ def solve_batch(problems, instances, stream=None):
                                 _ptr(conv(d.get("l"), np.float64)),
                                 _ptr(conv(d.get("u"), np.float64)), _ptr(fi), _ptr(fv), nfix,
                                 _ptr(conv(d.get("x0"), np.float64)),
-                                _ptr(conv(d.get("y0"), np.float64)))
+                                _ptr(conv(d.get("y0"), np.float64)),
+                                float(d.get("omega0", 0.0)), float(d.get("eta0", 0.0)),
+                                1 if d.get("fix_omega", False) else 0)
         if base.device:
             x = torch.empty(base.n, dtype=torch.float64, device="cuda")
             y = torch.empty(base.m, dtype=torch.float64, device="cuda")

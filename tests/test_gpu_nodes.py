@@ -50,3 +50,17 @@ def test_two_levels_of_nodes(gpu, oracle_mod, precision):
     assert all(opt[id(n)] > incumbent for n in cut)
     print("bounds", [round(n.bound, 3) for n in level2], "incumbent", incumbent,
           "pruned", len(cut), flush=True)
+
+
+def test_batch_rejects_bad_weights(gpu):
+    """omega0, eta0 must be finite and >= 0; the batch fails before any solve."""
+    from paper_2512_06715_amd import _lib as L
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    p = Problem(ucgen.workload("uc14_t24"), tol=1e-3)
+    print("case bad weights", flush=True)
+    for bad in (dict(omega0=float("nan")), dict(eta0=-1.0), dict(omega0=float("inf"))):
+        with pytest.raises(L.PdhgError):
+            solve_batch([p], [dict(base=0, **bad)])
+    x, y, info = solve_batch([p], [dict(base=0, omega0=3.0, eta0=0.5)])[0]
+    p.close()
+    assert info["status"] == 1
