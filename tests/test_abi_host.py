@@ -178,3 +178,47 @@ def test_locality_order_rejects_bad_csr():
     rc = lib.pdhg_locality_order(2, 2, rp.ctypes.data, ci.ctypes.data, ro.ctypes.data,
                                  co.ctypes.data)
     assert rc == -2  # PDHG_ERR_CSR
+
+
+def _c_struct_fields(name):
+    """Field names of `typedef struct {...} name;` in the header, in order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    end = re.search(r"\}\s*" + name + r";", text).start()
+    body = text[text.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        decl = re.sub(r"^(const\s+)?\w+\s*", "", decl)   # the type
+        fields += [f.strip().lstrip("*").strip() for f in decl.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("cname,pytype", [("pdhg_lp", "PdhgLP"), ("pdhg_opts", "PdhgOpts"),
+                                          ("pdhg_info", "PdhgInfo"),
+                                          ("pdhg_instance", "PdhgInstance")])
+def test_struct_layouts_match_the_header(cname, pytype, tmp_path):
+    """Size and every field offset of the ABI structs, as a C compiler lays
+    them out from the header, equal the binding's ctypes definitions."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    fields = _c_struct_fields(cname)
+    src = tmp_path / "layout.c"
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pdhg.h"', "int main(void) {",
+             f'  printf("size %zu\\n", sizeof({cname}));']
+    lines += [f'  printf("{f} %zu\\n", offsetof({cname}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    py = getattr(L, pytype)
+    assert [f[0] for f in py._fields_] == fields
+    assert int(got["size"]) == ctypes.sizeof(py)
+    for f in fields:
+        assert int(got[f]) == getattr(py, f).offset, f
