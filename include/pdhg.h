@@ -113,6 +113,9 @@ typedef struct {
                              when every tile of A and A' has at most 65535 nonzeros and an
                              index span of at most 65535; otherwise, and with 0, the 32-bit
                              CSR.  The results do not depend on it */
+  int polish_pw_update;   /* mixed precision: 1 (default) updates the primal weight at the
+                             FP64 phase's restarts as in the FP32 phase; 0 keeps the weight
+                             the FP32 phase ended with (faster on some LPs, stalls on others) */
 } pdhg_opts;
 
 typedef struct {
@@ -163,9 +166,10 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x,
  * a child node from its parent's solution; omega0, eta0 > 0 replace the
  * initial primal weight and step size (scaled-space values, as pdhg_info
  * reports them: a child can continue with its parent's), 0 keeps the
- * defaults; fix_omega != 0 keeps the primal weight at its initial value (no
- * update at restarts), which suits a start close to the optimum.  The dual
- * bound of an instance uses the base's implied bounds
+ * defaults; the primal weight keeps its initial value (no update at
+ * restarts) during the first hold_omega attempts, which suits a start close
+ * to the optimum, and is updated as usual after them (0: from the start).
+ * The dual bound of an instance uses the base's implied bounds
  * only when b, l and u are not overridden (fixings only tighten the bounds
  * the implied ones were derived from), and its repair intervals only when
  * b, c, l and u are not overridden. */
@@ -177,7 +181,7 @@ typedef struct {
   int64_t n_fix;
   const double *x0, *y0;
   double omega0, eta0;
-  int32_t fix_omega;
+  int64_t hold_omega;
 } pdhg_instance;
 
 /* Device workspace bytes for pdhg_solve_batch with these instances. */

@@ -35,7 +35,7 @@ class PdhgOpts(ctypes.Structure):
                 ("verbose", c_int), ("polish_tol", c_dbl), ("pw_update", c_int),
                 ("pw_theta", c_dbl), ("tiles_per_block", c_int), ("autotune", c_int),
                 ("spmv_direct", c_int), ("long_seg", c_int), ("reorder", c_int),
-                ("compact_index", c_int)]
+                ("compact_index", c_int), ("polish_pw_update", c_int)]
 
 
 class PdhgInfo(ctypes.Structure):
@@ -55,7 +55,7 @@ class PdhgInfo(ctypes.Structure):
 class PdhgInstance(ctypes.Structure):
     _fields_ = [("base", ctypes.c_int32), ("b", vp), ("c", vp), ("l", vp), ("u", vp),
                 ("fix_idx", vp), ("fix_val", vp), ("n_fix", c_i64), ("x0", vp), ("y0", vp),
-                ("omega0", c_dbl), ("eta0", c_dbl), ("fix_omega", ctypes.c_int32)]
+                ("omega0", c_dbl), ("eta0", c_dbl), ("hold_omega", c_i64)]
 
 
 # name -> (restype, argtypes)

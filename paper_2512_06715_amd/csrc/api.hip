@@ -301,6 +301,8 @@ int check_opts(const pdhg_opts *o) {
   if (o->reorder != 0 && o->reorder != 1) return fail(PDHG_ERR_ARG, "reorder must be 0 or 1");
   if (o->compact_index != 0 && o->compact_index != 1)
     return fail(PDHG_ERR_ARG, "compact_index must be 0 or 1");
+  if (o->polish_pw_update != 0 && o->polish_pw_update != 1)
+    return fail(PDHG_ERR_ARG, "polish_pw_update must be 0 or 1");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -734,6 +736,7 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.use_average = h->o.use_average;
   e.restart = h->o.restart;
   e.pw_theta = h->o.pw_update ? h->o.pw_theta : 0.0;
+  e.hold_k = 0;
   I.st = b.st;
   I.x0 = I.y0 = nullptr;
   I.xout = I.yout = nullptr;
@@ -1013,7 +1016,11 @@ int solve_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
     if (status[i] == 0 || (status[i] == PDHG_OPTIMAL && tol32 > h->o.tol)) polish.push_back(i);
   }
   if (polish.empty()) return PDHG_OK;
-  // FP64 refinement from the FP32 iterates (both tables describe the same instances)
+  // FP64 refinement from the FP32 iterates (both tables describe the same
+  // instances); optionally with the primal weight held where the FP32 phase
+  // left it
+  if (!h->o.polish_pw_update)
+    for (int i : polish) i64[i].e.pw_theta = 0.0;
   RC(upload_group<float>(h, gd, i32, polish, g));
   Groups g64{};
   RC(upload_group<double>(h, gd, i64, polish, g64));
@@ -1191,6 +1198,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->long_seg = 0;
   o->reorder = 1;
   o->compact_index = 1;
+  o->polish_pw_update = 1;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -1648,6 +1656,7 @@ int check_batch(pdhg_handle *const *handles, int n_handles, const pdhg_instance 
     if (!(inst[k].omega0 >= 0.0 && std::isfinite(inst[k].omega0)) ||
         !(inst[k].eta0 >= 0.0 && std::isfinite(inst[k].eta0)))
       return fail(PDHG_ERR_ARG, "instance %d: omega0 and eta0 must be finite and >= 0", k);
+    if (inst[k].hold_omega < 0) return fail(PDHG_ERR_ARG, "instance %d: hold_omega < 0", k);
     const pdhg_handle *h = handles[inst[k].base];
     if (!h->on_device)
       for (int64_t q = 0; q < inst[k].n_fix; q++)
@@ -1781,7 +1790,7 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
       i64[k].e.ilo = i64[k].e.ihi = nullptr;
       i32[k].e.ilo = i32[k].e.ihi = nullptr;
     }
-    if (q.fix_omega) i64[k].e.pw_theta = i32[k].e.pw_theta = 0.0;  // no weight updates
+    i64[k].e.hold_k = i32[k].e.hold_k = q.hold_omega;  // weight held for these attempts
     if (q.b || q.c || q.l || q.u) {  // and its repair intervals those and its c
       i64[k].e.rylo = i64[k].e.ryhi = nullptr;
       i32[k].e.rylo = i32[k].e.ryhi = nullptr;

@@ -111,6 +111,7 @@ struct EvalView {
   double bound_allow;            // rounding allowance factor 2 (n + m + longest column + 4) 2^-53
   int use_average, restart;
   double pw_theta;               // 0 keeps the primal weight
+  long long hold_k;              // no primal-weight update before this attempt
   int long_seg;
   // caller's index of each internal row / column (null: same order)
   const int32_t *rperm, *cperm;

@@ -570,7 +570,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const Inst<T> *__re
     if (do_restart) {
       st->restart_flag = cand_avg ? 2 : 1;
       double dx = cd->dl_x, dy = cd->dl_y;
-      double th = e.pw_theta;
+      double th = k < e.hold_k ? 0.0 : e.pw_theta;
       if (th > 0.0 && dx > 1e-10 && dy > 1e-10)
         omega = exp(th * log(dy / dx) + (1.0 - th) * log(omega));
       st->omega = omega;

@@ -37,6 +37,7 @@ class Node:
     y0: Optional[np.ndarray] = None
     omega0: float = 0.0   # parent's final primal weight and step size (0: defaults)
     eta0: float = 0.0
+    hold: int = 0         # attempts the weight is held (the parent's attempt count)
     x: Optional[np.ndarray] = None
     y: Optional[np.ndarray] = None
     info: Optional[dict] = None
@@ -75,7 +76,8 @@ def branch(node: Node, col: int) -> Tuple[Node, Node]:
         val = np.append(node.fix_val, v).astype(np.float64)
         kids.append(Node(idx, val, node.depth + 1, x0=node.x, y0=node.y,
                          omega0=float(node.info.get("omega", 0.0)),
-                         eta0=float(node.info.get("eta", 0.0))))
+                         eta0=float(node.info.get("eta", 0.0)),
+                         hold=int(node.info.get("attempts", 0))))
     return kids[0], kids[1]
 
 
@@ -97,9 +99,10 @@ def solve_nodes(problem, nodes: List[Node], warm: bool = True,
     """Solve the nodes' LPs in one batched run on `problem` (a solver.Problem
     of the base LP).  With `warm`, each node starts from its x0, y0 when it
     has them; with `weights` also from its parent's step size and primal
-    weight, which then stays fixed (near the optimum the restarts' weight
-    updates see little primal movement and drive the weight up by a factor
-    of about 1.5 per restart, stalling the primal iterate).  Fills x, y and
+    weight, the weight held for as many attempts as the parent took (near
+    the optimum the restarts' weight updates see little primal movement and
+    drive the weight up by a factor of about 1.5 per restart, stalling the
+    primal iterate; past that budget the updates resume).  Fills x, y and
     info of every node and returns the list."""
     if not nodes:
         return nodes
@@ -111,7 +114,7 @@ def solve_nodes(problem, nodes: List[Node], warm: bool = True,
             d["x0"] = _like(problem, nd.x0, np.float64)
             d["y0"] = _like(problem, nd.y0, np.float64)
             if weights:
-                d["omega0"], d["eta0"], d["fix_omega"] = nd.omega0, nd.eta0, True
+                d["omega0"], d["eta0"], d["hold_omega"] = nd.omega0, nd.eta0, nd.hold
         insts.append(d)
     for nd, (x, y, info) in zip(nodes, solve_batch([problem], insts)):
         nd.x, nd.y, nd.info = x, y, info

@@ -199,7 +199,8 @@ def solve_batch(problems, instances, stream=None):
     'b', 'c', 'l', 'u' (original-space overrides), 'fix_idx', 'fix_val'
     (variables fixed to a value), 'x0', 'y0' (warm start), 'omega0',
     'eta0' (initial primal weight and step size, scaled space; 0 or absent:
-    the defaults) and 'fix_omega' (true: no primal-weight updates).  Host problems take numpy arrays, device problems torch
+    the defaults) and 'hold_omega' (attempts during which the primal weight
+    keeps its initial value).  Host problems take numpy arrays, device problems torch
     CUDA tensors.  Returns a list of (x, y, info dict).
     """
     import torch
@@ -231,7 +232,7 @@ def solve_batch(problems, instances, stream=None):
                                 _ptr(conv(d.get("x0"), np.float64)),
                                 _ptr(conv(d.get("y0"), np.float64)),
                                 float(d.get("omega0", 0.0)), float(d.get("eta0", 0.0)),
-                                1 if d.get("fix_omega", False) else 0)
+                                int(d.get("hold_omega", 0)))
         if base.device:
             x = torch.empty(base.n, dtype=torch.float64, device="cuda")
             y = torch.empty(base.m, dtype=torch.float64, device="cuda")

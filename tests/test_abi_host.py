@@ -35,6 +35,7 @@ def test_default_opts():
     assert o.tol == 1e-4 and o.eval_period == 64 and o.scaling_iters == 10
     assert o.pock_chambolle == 1 and o.restart == 1 and o.use_average == 1
     assert o.step_mode == 0 and o.precision == L.PDHG_FP64 and o.pw_theta == 0.5
+    assert o.reorder == 1 and o.compact_index == 1 and o.polish_pw_update == 1
 
 
 def _lp_struct(lp):
@@ -105,6 +106,9 @@ def test_setup_rejects_bad_options_and_small_workspace():
     assert _setup_rc(lp, dict(eval_period=0))[0] == -1
     assert _setup_rc(lp, dict(precision=7))[0] == -1
     assert _setup_rc(lp, dict(pw_theta=2.0))[0] == -1
+    for bad in (dict(reorder=2), dict(compact_index=-1), dict(polish_pw_update=3)):
+        rc, msg = _setup_rc(lp, bad)
+        assert rc == -1 and list(bad)[0] in msg, (bad, msg)
     lib = L.load()
     s, keep = _lp_struct(lp)
     o = L.PdhgOpts()

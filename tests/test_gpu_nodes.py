@@ -58,9 +58,10 @@ def test_batch_rejects_bad_weights(gpu):
     from paper_2512_06715_amd.solver import Problem, solve_batch
     p = Problem(ucgen.workload("uc14_t24"), tol=1e-3)
     print("case bad weights", flush=True)
-    for bad in (dict(omega0=float("nan")), dict(eta0=-1.0), dict(omega0=float("inf"))):
+    for bad in (dict(omega0=float("nan")), dict(eta0=-1.0), dict(omega0=float("inf")),
+                dict(hold_omega=-1)):
         with pytest.raises(L.PdhgError):
             solve_batch([p], [dict(base=0, **bad)])
-    x, y, info = solve_batch([p], [dict(base=0, omega0=3.0, eta0=0.5)])[0]
+    x, y, info = solve_batch([p], [dict(base=0, omega0=3.0, eta0=0.5, hold_omega=200)])[0]
     p.close()
     assert info["status"] == 1

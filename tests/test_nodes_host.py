@@ -9,7 +9,7 @@ from paper_2512_06715_amd import nodes as N
 def solved(fix_idx, fix_val, x, bound=0.0, obj=1.0):
     nd = N.Node(np.asarray(fix_idx, np.int32), np.asarray(fix_val, np.float64))
     nd.x, nd.y = np.asarray(x, float), np.zeros(2)
-    nd.info = dict(dual_bound=bound, primal_obj=obj, omega=12.5, eta=0.75)
+    nd.info = dict(dual_bound=bound, primal_obj=obj, omega=12.5, eta=0.75, attempts=640)
     return nd
 
 
@@ -19,7 +19,7 @@ def test_branch_adds_one_fixing_and_warm_starts_from_parent():
     assert a.fixed() == {4: 1.0, 2: 0.0} and b.fixed() == {4: 1.0, 2: 1.0}
     assert a.depth == b.depth == 1
     assert a.x0 is p.x and b.y0 is p.y and not a.solved
-    assert a.omega0 == b.omega0 == 12.5 and a.eta0 == b.eta0 == 0.75
+    assert a.omega0 == b.omega0 == 12.5 and a.eta0 == b.eta0 == 0.75 and a.hold == b.hold == 640
     with pytest.raises(ValueError):
         N.branch(p, 4)                      # already fixed here
     with pytest.raises(ValueError):
