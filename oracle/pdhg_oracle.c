@@ -436,7 +436,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   if (o->step_mode == 1)
     eta = o->fixed_eta > 0.0 ? o->fixed_eta : 0.9 / orc_power_norm(m, n, rp0, ci0, v, 50);
   else
-    eta = 1.0 / amax;
+    eta = amax > 0.0 ? 1.0 / amax : 1.0;  /* no nonzero: 1 */
   double omega;
   if (o->omega0 > 0.0)
     omega = o->omega0;

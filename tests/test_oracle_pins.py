@@ -481,3 +481,25 @@ def test_repaired_bound_below_optimum_on_slack_toys(oracle_mod):
             finite += 1
             assert abs(r["bound"] - opt) <= 1e-9 * (1 + abs(opt)), (t, r, opt)
     assert finite >= 60
+
+
+@pytest.mark.parametrize("name", ["one_by_one", "empty_row_and_columns", "all_fixed", "zero_matrix",
+                                  "duplicate_rows", "free_empty_column"])
+def test_oracle_on_degenerate_lps(oracle_mod, name):
+    """Degenerate shapes (a 1x1 LP, an empty row and empty columns, every
+    variable fixed, no nonzero at all, duplicated rows, a free empty column):
+    the oracle reaches HiGHS's optimum, its KKT error is below the tolerance,
+    and the safe bound at its y is below the optimum and within 1e-6 of it."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from edge_lps import CASES
+    lp = CASES[name]()
+    st, xh, opt, yh = exact.highs(lp)
+    assert st == exact.OPTIMAL
+    x, y, info = oracle_mod.pdhg(lp, tol=1e-8, max_iter=200000)
+    assert info["status"] == 1, info
+    k = oracle_mod.kkt(lp, x, y)
+    assert k["rel_kkt"] <= 1e-8 and abs(k["pobj"] - opt) <= 1e-6 * (1 + abs(opt))
+    b = oracle_mod.safe_bound(lp, y)["bound"]
+    assert b <= opt + 1e-12 * (1 + abs(opt)) and opt - b <= 1e-6 * (1 + abs(opt))
