@@ -129,11 +129,17 @@ typedef struct {
   double eta, omega;      /* final step size and primal weight (scaled space) */
   double setup_s, solve_s;
   /* A lower bound on the LP optimum that holds whatever the accuracy of the
-   * returned y (weak duality): b'y + sum_j min over x_j in [lo_j, hi_j] of
-   * lambda_j x_j with lambda = c - A'y, lowered by an allowance that exceeds
-   * the rounding of the sums; [lo, hi] are l, u with infinite ends replaced
-   * by implied bounds (pdhg_implied_bounds) where the LP's rows give them.
-   * -INFINITY when a nonzero lambda_j needs an infinite bound. */
+   * returned y (weak duality; the LP relaxation bounds of the paper's
+   * "PDHG Execution & Crossover Refinement" discussion), computed once after
+   * the solve: b'y~ + sum_j min over x_j in [lo_j, hi_j] of lambda_j x_j with
+   * lambda = c - A'y~, lowered by an allowance that exceeds the rounding of
+   * the sums.  y~ is y projected on >= rows and clamped so that the reduced
+   * costs of single-entry columns with an infinite bound (penalty slacks)
+   * keep their sign; [lo, hi] are l, u with infinite ends replaced by
+   * implied bounds (pdhg_implied_bounds) where the LP's rows give them.  A
+   * lambda_j whose sign is within its rounding error counts with both bounds.
+   * -INFINITY when a bound that is needed is infinite; -INFINITY in the
+   * unrolled mode. */
   double dual_bound;
 } pdhg_info;
 
