@@ -48,7 +48,8 @@ class _Opts(ctypes.Structure):
                 ("fixed_eta", ctypes.c_double), ("ruiz_iters", ctypes.c_int),
                 ("pock_chambolle", ctypes.c_int), ("restart", ctypes.c_int),
                 ("use_average", ctypes.c_int), ("omega0", ctypes.c_double),
-                ("pw_theta", ctypes.c_double)]
+                ("pw_theta", ctypes.c_double), ("infeas_every", ctypes.c_int),
+                ("ilo", ctypes.c_void_p), ("ihi", ctypes.c_void_p)]
 
 
 def lib():
@@ -208,12 +209,18 @@ INFO_FIELDS = ("status", "attempts", "accepted", "restarts", "pobj", "dobj", "re
 
 def pdhg(lp, tol=1e-4, max_iter=100000, eval_period=64, step_mode=0, fixed_eta=0.0,
          ruiz_iters=10, pock_chambolle=True, restart=True, use_average=True,
-         omega0=0.0, pw_theta=0.5, x0=None, y0=None):
-    """Restarted PDHG in FP64.  Returns (x, y, info dict) in the original space."""
+         omega0=0.0, pw_theta=0.5, x0=None, y0=None, infeas_every=4):
+    """Restarted PDHG in FP64.  Returns (x, y, info dict) in the original space.
+    Every `infeas_every` evaluations (0: never) the current y is tested as a
+    certificate of primal infeasibility over the implied bounds (status 5)."""
     a = _arrs(lp)
+    ilo = ihi = None
+    if infeas_every > 0:
+        ilo, ihi = implied_bounds(lp)
     o = _Opts(tol, int(max_iter), int(eval_period), int(step_mode), float(fixed_eta),
               int(ruiz_iters), int(bool(pock_chambolle)), int(bool(restart)),
-              int(bool(use_average)), float(omega0), float(pw_theta))
+              int(bool(use_average)), float(omega0), float(pw_theta), int(infeas_every),
+              _p(ilo), _p(ihi))
     x = np.zeros(lp.n)
     y = np.zeros(lp.m)
     info = np.zeros(len(INFO_FIELDS))

@@ -31,6 +31,7 @@
 #define ST_OPTIMAL 1
 #define ST_ITER_LIMIT 2
 #define ST_NUMERICAL 4
+#define ST_PRIMAL_INFEASIBLE 5
 
 enum { VK_FREE = 0, VK_LOWER = 1, VK_UPPER = 2, VK_BOXED = 3, VK_FIXED = 4 };
 
@@ -306,6 +307,10 @@ typedef struct {
   int use_average;     /* 1: weighted average is a restart/termination candidate */
   double omega0;       /* <= 0: ||c||/||b|| rule */
   double pw_theta;     /* primal-weight smoothing; 0 keeps omega */
+  int infeas_every;    /* > 0: every this many evaluations, test y for a
+                          certificate of primal infeasibility */
+  const double *ilo, *ihi;  /* bounds every feasible x satisfies (original
+                               space; NULL: l, u) for that test */
 } orc_opts;
 
 /* info: [0] status [1] attempts [2] accepted [3] restarts [4] pobj [5] dobj
@@ -381,6 +386,59 @@ double orc_power_norm(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci
   return est;
 }
 
+/* Certificate of primal infeasibility (Farkas): for y with y_i >= 0 on >= rows
+ * and a box [lo, hi] that holds every feasible x, feasibility would give
+ * b'y <= y'Ax = sum_j (A'y)_j x_j <= sum_j max over [lo_j, hi_j] of
+ * (A'y)_j x_j; so b'y + sum_j min(lambda_j lo_j, lambda_j hi_j) > 0 with
+ * lambda = -A'y proves that no feasible x exists.  This is the safe bound's
+ * sum for c = 0 (same sign rule and allowance), on the scaled problem, with
+ * y used as it is (no repair).  Returns the value lowered by the allowance,
+ * or -INFINITY when a needed bound is infinite. */
+static double homogeneous_certificate(const scaled_lp *P, const double *y, const double *lo,
+                                      const double *hi) {
+  const int64_t m = P->m, n = P->n;
+  const double eps = ldexp(1.0, -53);
+  double by = 0.0, byabs = 0.0, terms = 0.0, sabs = 0.0;
+  int64_t kmax = 0, ninf = 0;
+  for (int64_t i = 0; i < m; i++) {
+    double yi = (P->kind[i] == 1 && y[i] < 0.0) ? 0.0 : y[i];
+    double t = P->b[i] * yi;
+    by += t;
+    byabs += fabs(t);
+  }
+  for (int64_t j = 0; j < n; j++) {
+    double s = 0.0, sa = 0.0;
+    for (int32_t k = P->cp[j]; k < P->cp[j + 1]; k++) {
+      int32_t i = P->ri[k];
+      double yi = (P->kind[i] == 1 && y[i] < 0.0) ? 0.0 : y[i];
+      double pr = P->vt[k] * yi;
+      s += pr;
+      sa += fabs(pr);
+    }
+    int64_t len = P->cp[j + 1] - P->cp[j];
+    if (len > kmax) kmax = len;
+    const double lam = 0.0 - s;
+    const double err = 2.0 * (double)(len + 2) * eps * sa;
+    if (fabs(lam) > err || err == 0.0) {
+      if (lam == 0.0) continue;
+      const double bnd = lam > 0.0 ? lo[j] : hi[j];
+      if (isinf(bnd)) {
+        ninf++;
+        continue;
+      }
+      terms += lam * bnd;
+      sabs += fabs(bnd) * sa;
+    } else if (isinf(lo[j]) || isinf(hi[j])) {
+      ninf++;
+    } else {
+      terms += fmin(lam * lo[j], lam * hi[j]);
+      sabs += fmax(fabs(lo[j]), fabs(hi[j])) * sa;
+    }
+  }
+  if (ninf) return -INFINITY;
+  return (by + terms) - 2.0 * (double)(n + m + kmax + 4) * eps * (byabs + sabs);
+}
+
 int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
              const double *v0, const uint8_t *kind, const double *b0, const double *c0,
              const double *l0, const double *u0, const orc_opts *o, const double *x0,
@@ -447,6 +505,12 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   info[13] = eta;
   info[14] = omega;
 
+  /* the box of the infeasibility test, scaled */
+  double *blo = (double *)malloc(N8), *bhi = (double *)malloc(N8);
+  for (int64_t j = 0; j < n; j++) {
+    blo[j] = (o->ilo ? o->ilo[j] : l0[j]) / Dc[j];
+    bhi[j] = (o->ihi ? o->ihi[j] : u0[j]) / Dc[j];
+  }
   double ev[10], eva[10];
   evaluate(&P, x, y, Ax, ATy, omega, ev);
   double kkt_last = ev[0], kkt_prev = INFINITY;
@@ -490,6 +554,12 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
       }
       if (k >= o->max_iter) {
         status = ST_ITER_LIMIT;
+        which = 0;
+        break;
+      }
+      if (o->infeas_every > 0 && k > 0 && (k / P_eval) % o->infeas_every == 0 &&
+          homogeneous_certificate(&P, y, blo, bhi) > 0.0) {
+        status = ST_PRIMAL_INFEASIBLE;
         which = 0;
         break;
       }
@@ -594,6 +664,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   free(b); free(c); free(l); free(u); free(vk);
   free(x); free(y); free(Ax); free(ATy); free(xn); free(yn); free(Axn);
   free(xs); free(ys); free(xa); free(ya); free(Axa); free(ATya); free(xl); free(yl);
+  free(blo); free(bhi);
   return ORC_OK;
 }
 

@@ -503,3 +503,61 @@ def test_oracle_on_degenerate_lps(oracle_mod, name):
     assert k["rel_kkt"] <= 1e-8 and abs(k["pobj"] - opt) <= 1e-6 * (1 + abs(opt))
     b = oracle_mod.safe_bound(lp, y)["bound"]
     assert b <= opt + 1e-12 * (1 + abs(opt)) and opt - b <= 1e-6 * (1 + abs(opt))
+
+
+def homogeneous_value(oracle_mod, lp, y):
+    """The certificate's sum at y: the safe bound of the LP with c = 0, over
+    the implied bounds, without repair (> 0 proves primal infeasibility)."""
+    q = lp.copy()
+    q.c = np.zeros(lp.n)
+    lo, hi = oracle_mod.implied_bounds(lp)
+    return oracle_mod.safe_bound(q, y, lo, hi, repair=False)["bound"]
+
+
+def test_infeasibility_certificate_closed_form(oracle_mod):
+    """x >= 1 with 0 <= x <= 1/2: y = 1 gives b'y + min(-1 * 0, -1 * 1/2) = 1/2
+    (Farkas), y = 0 gives 0 (no proof); the oracle stops with status 5 and a
+    y whose value is positive."""
+    lp = ucgen.dense_to_lp(np.array([[1.0]]), np.array([1], np.uint8), np.array([1.0]),
+                           np.array([1.0]), np.array([0.0]), np.array([0.5]))
+    v = homogeneous_value(oracle_mod, lp, np.array([1.0]))
+    assert 0.5 - 1e-14 <= v < 0.5
+    assert homogeneous_value(oracle_mod, lp, np.array([0.0])) <= 0.0
+    x, y, info = oracle_mod.pdhg(lp, tol=1e-8, max_iter=10000)
+    assert info["status"] == 5 and homogeneous_value(oracle_mod, lp, y) > 0.0
+
+
+def test_infeasibility_detected_on_toys(oracle_mod):
+    """Every toy HiGHS calls infeasible ends with status 5 and a y whose
+    certificate value is positive; no feasible toy ever does."""
+    rng = np.random.default_rng(7)
+    n_inf = n_feas = 0
+    for t in range(300):
+        m, n = int(rng.integers(1, 4)), int(rng.integers(1, 4))
+        A, kind, b, c, lo, hi = ucgen.random_toy_lp(rng, m, n)
+        lp = ucgen.dense_to_lp(A, kind, b, c, lo, hi)
+        st, xh, opt, yh = exact.highs(lp)
+        x, y, info = oracle_mod.pdhg(lp, tol=1e-8, max_iter=50000)
+        if st == exact.INFEASIBLE:
+            n_inf += 1
+            assert info["status"] == 5, (t, info)
+            assert homogeneous_value(oracle_mod, lp, y) > 0.0
+        else:
+            n_feas += 1
+            assert info["status"] != 5, (t, st, info)
+    assert n_inf >= 100 and n_feas >= 100
+
+
+def test_infeasible_uc_node(oracle_mod):
+    """The 14-bus relaxation without its penalty slacks and with every unit of
+    period 5 switched off cannot meet that period's load (HiGHS: infeasible);
+    the oracle proves it: status 5, positive certificate value."""
+    lp = ucgen.workload("uc14_t24")
+    N, G, L = 14, 5, 20
+    pos = np.arange(lp.n) % (4 * G + 3 * N + L + 1)
+    q = lp.copy()
+    q.u[pos >= 4 * G + N + L] = 0.0                      # s+, s-, r
+    q.l[lp.meta["u_cols"][5]] = q.u[lp.meta["u_cols"][5]] = 0.0
+    assert exact.highs(q)[0] == exact.INFEASIBLE
+    x, y, info = oracle_mod.pdhg(q, tol=1e-6, max_iter=100000)
+    assert info["status"] == 5 and homogeneous_value(oracle_mod, q, y) > 0.0
