@@ -56,7 +56,10 @@ enum {
   PDHG_OPTIMAL = 1,        /* relative KKT error <= tol */
   PDHG_ITER_LIMIT = 2,
   PDHG_TIME_LIMIT = 3,
-  PDHG_NUMERICAL = 4       /* NaN or Inf reached the iterates */
+  PDHG_NUMERICAL = 4,      /* NaN or Inf reached the iterates */
+  PDHG_PRIMAL_INFEASIBLE = 5 /* y is a certificate: with lambda = -A'y and y >= 0 on >= rows,
+                              b'y + sum_j min(lambda_j lo_j, lambda_j hi_j) > 0 over the
+                              implied bounds, beyond its rounding allowance (Farkas) */
 };
 
 enum { PDHG_ROW_EQ = 0, PDHG_ROW_GE = 1 };
@@ -113,6 +116,9 @@ typedef struct {
                              when every tile of A and A' has at most 65535 nonzeros and an
                              index span of at most 65535; otherwise, and with 0, the 32-bit
                              CSR.  The results do not depend on it */
+  int infeas_every;       /* every this many evaluations (default 4; 0: never) the current y
+                             is tested as a certificate of primal infeasibility; a proof
+                             ends the solve with PDHG_PRIMAL_INFEASIBLE and returns it */
   int polish_pw_update;   /* mixed precision: 1 (default) updates the primal weight at the
                              FP64 phase's restarts as in the FP32 phase; 0 keeps the weight
                              the FP32 phase ended with (faster on some LPs, stalls on others) */

@@ -301,6 +301,7 @@ int check_opts(const pdhg_opts *o) {
   if (o->reorder != 0 && o->reorder != 1) return fail(PDHG_ERR_ARG, "reorder must be 0 or 1");
   if (o->compact_index != 0 && o->compact_index != 1)
     return fail(PDHG_ERR_ARG, "compact_index must be 0 or 1");
+  if (o->infeas_every < 0) return fail(PDHG_ERR_ARG, "infeas_every must be >= 0");
   if (o->polish_pw_update != 0 && o->polish_pw_update != 1)
     return fail(PDHG_ERR_ARG, "polish_pw_update must be 0 or 1");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
@@ -737,6 +738,7 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.restart = h->o.restart;
   e.pw_theta = h->o.pw_update ? h->o.pw_theta : 0.0;
   e.hold_k = 0;
+  e.infeas_period = (long long)h->o.eval_period * h->o.infeas_every;
   I.st = b.st;
   I.x0 = I.y0 = nullptr;
   I.xout = I.yout = nullptr;
@@ -1198,6 +1200,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->long_seg = 0;
   o->reorder = 1;
   o->compact_index = 1;
+  o->infeas_every = 4;
   o->polish_pw_update = 1;
 }
 

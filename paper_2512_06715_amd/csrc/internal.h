@@ -112,6 +112,7 @@ struct EvalView {
   int use_average, restart;
   double pw_theta;               // 0 keeps the primal weight
   long long hold_k;              // no primal-weight update before this attempt
+  long long infeas_period;       // attempts between infeasibility tests (0: none)
   int long_seg;
   // caller's index of each internal row / column (null: same order)
   const int32_t *rperm, *cperm;

@@ -649,6 +649,121 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_restart_rows(const Inst<T> *__re
 }
 
 // ---------------------------------------------------------------------------
+// certificate of primal infeasibility, every infeas_period attempts (FP64)
+//
+// Farkas: with y_i >= 0 on >= rows and a box [lo, hi] holding every feasible
+// x (l, u tightened by the implied bounds), a feasible x would give
+// b'y <= sum_j (A'y)_j x_j <= sum_j max over [lo_j, hi_j] of (A'y)_j x_j.
+// So b'y + sum_j min(lambda_j lo_j, lambda_j hi_j) > 0 with lambda = -A'y,
+// beyond its rounding allowance, proves that no feasible x exists.  The sum
+// is the safe bound's for c = 0 (same sign rule and allowance), taken at the
+// current y, which the iteration keeps projected.  The test runs after the
+// evaluation's decisions and before its restart copies, and is skipped
+// (uniformly) when the instance is done or k is not a multiple of the period.
+
+template <typename T>
+__device__ inline bool infeas_due(const EvalView<T> &e, const CtlState *st) {
+  return e.infeas_period > 0 && !st->done && st->k > 0 && st->k % e.infeas_period == 0;
+}
+
+// Rows: partials [0] b'y, [1] sum |b_i y_i|.
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_rows(const Inst<T> *__restrict__ I,
+                                                            Groups g) {
+  GROUP_BLOCK(p_rows)
+  if (!infeas_due(e, st)) return;
+  int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  double q[2] = {0.0, 0.0};
+  if (i < e.m) {
+    double yi = (double)gin((const T *)e.Y[st->cur])[i];
+    if (gin(e.kind)[i] == 1 && yi < 0.0) yi = 0.0;
+    double t = __dmul_rn(gin(e.b)[i], yi);
+    q[0] = t;
+    q[1] = fabs(t);
+  }
+  double out[2];
+  block_reduce<2>(q, 0u, out);
+  if (threadIdx.x == 0) {
+    e.part_rows[lb] = out[0];
+    e.part_rows[(int64_t)e.nblk_rows + lb] = out[1];
+  }
+}
+
+// Columns, one lane per column: lambda_j = -sum_i a_ij y_i in ascending row
+// order, its error bound, and the term as in the safe bound (c = 0).
+// Partials [0] terms, [1] magnitudes, [2] needed infinite bounds.
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_cols(const Inst<T> *__restrict__ I,
+                                                            Groups g) {
+  GROUP_BLOCK(p_cols)
+  if (!infeas_due(e, st)) return;
+  int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
+  double q[3] = {0.0, 0.0, 0.0};
+  if (j < e.n) {
+    const AS_G int32_t *cp = gin(e.cp), *ri = gin(e.ri);
+    const AS_G double *vt = gin(e.vt);
+    const AS_G T *y = gin((const T *)e.Y[st->cur]);
+    const AS_G uint8_t *kind = gin(e.kind);
+    const int a = cp[j], z = cp[j + 1];
+    double s = 0.0, sa = 0.0;
+    for (int k = a; k < z; k++) {
+      const int32_t i = ri[k];
+      double yi = (double)y[i];
+      if (kind[i] == 1 && yi < 0.0) yi = 0.0;
+      double pr = __dmul_rn(vt[k], yi);
+      s += pr;
+      sa += fabs(pr);
+    }
+    const double lam = 0.0 - s;
+    const double err = 2.0 * (double)(z - a + 2) * 0x1p-53 * sa;
+    double lo = gin(e.l)[j], hi = gin(e.u)[j];
+    if (e.ilo) {
+      lo = fmax(lo, gin(e.ilo)[j]);
+      hi = fmin(hi, gin(e.ihi)[j]);
+    }
+    if (fabs(lam) > err || err == 0.0) {
+      if (lam != 0.0) {
+        double bnd = lam > 0.0 ? lo : hi;
+        if (isinf(bnd)) {
+          q[2] = 1.0;
+        } else {
+          q[0] = __dmul_rn(lam, bnd);
+          q[1] = fabs(bnd) * sa;
+        }
+      }
+    } else if (isinf(lo) || isinf(hi)) {
+      q[2] = 1.0;
+    } else {
+      q[0] = fmin(__dmul_rn(lam, lo), __dmul_rn(lam, hi));
+      q[1] = fmax(fabs(lo), fabs(hi)) * sa;
+    }
+  }
+  double out[3];
+  block_reduce<3>(q, 0u, out);
+  if (threadIdx.x == 0)
+    for (int t = 0; t < 3; t++) e.part_cols[(int64_t)t * e.nblk_cols + lb] = out[t];
+}
+
+// One workgroup per instance: the value in fixed order; a positive one ends
+// the solve with the current iterate as the certificate.
+template <typename T>
+__global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_finish(const Inst<T> *__restrict__ I) {
+  const EvalView<T> &e = I[blockIdx.x].e;
+  CtlState *st = I[blockIdx.x].st;
+  if (!infeas_due(e, st)) return;
+  double r[2], c[3];
+  reduce_partials<2, PDHG_BLOCK>(e.part_rows, e.nblk_rows, e.nblk_rows, 0u, r);
+  reduce_partials<3, PDHG_BLOCK>(e.part_cols, e.nblk_cols, e.nblk_cols, 0u, c);
+  if (threadIdx.x == 0 && c[2] == 0.0 &&
+      (r[0] + c[0]) - e.bound_allow * (r[1] + c[1]) > 0.0) {
+    st->done = 1;
+    st->status = 5;  // PDHG_PRIMAL_INFEASIBLE
+    st->which = 0;
+    st->restart_flag = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // safe dual bound of the reported point, once after the solve (FP64)
 //
 // Weak duality: for any y~ with y~_i >= 0 on >= rows, every feasible x has
@@ -1127,6 +1242,9 @@ void launch_evaluate(const Inst<T> *I, const Groups &g, double tol, int64_t max_
   k_eval_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
   k_eval_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
   k_eval_control<T><<<grid_of(g.ninst * PDHG_CTL_SPLIT), PDHG_BLOCK, 0, s>>>(I, tol, (long long)max_iter);
+  k_infeas_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
+  k_infeas_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
+  k_infeas_finish<T><<<grid_of(g.ninst), PDHG_BLOCK, 0, s>>>(I);
   k_restart_cols<T><<<grid_of(g.n_cols), PDHG_BLOCK, 0, s>>>(I, g);
   k_restart_rows<T><<<grid_of(g.n_rows), PDHG_BLOCK, 0, s>>>(I, g);
   if (sizeof(T) == 4) {

@@ -1,0 +1,97 @@
+"""Certificates of primal infeasibility on the GPU (status 5), checked with
+the oracle's Farkas sum at the returned y."""
+import numpy as np
+import pytest
+
+from oracle import exact
+from paper_2512_06715_amd import ucgen
+
+pytestmark = pytest.mark.gpu
+
+
+def farkas_value(oracle_mod, lp, y):
+    q = lp.copy()
+    q.c = np.zeros(lp.n)
+    lo, hi = oracle_mod.implied_bounds(lp)
+    return oracle_mod.safe_bound(q, y, lo, hi, repair=False)["bound"]
+
+
+def infeasible_node():
+    """The 14-bus relaxation without its penalty slacks, every unit of period
+    5 switched off (HiGHS: infeasible)."""
+    lp = ucgen.workload("uc14_t24")
+    N, G, L = 14, 5, 20
+    pos = np.arange(lp.n) % (4 * G + 3 * N + L + 1)
+    q = lp.copy()
+    q.u[pos >= 4 * G + N + L] = 0.0
+    q.l[lp.meta["u_cols"][5]] = q.u[lp.meta["u_cols"][5]] = 0.0
+    return q
+
+
+def test_closed_form_and_toys(gpu, oracle_mod):
+    """x >= 1 with x in [0, 1/2], and 20 random toys HiGHS calls infeasible:
+    status 5 and a positive Farkas value at the returned y."""
+    from paper_2512_06715_amd.solver import Problem
+    lps = [ucgen.dense_to_lp(np.array([[1.0]]), np.array([1], np.uint8), np.array([1.0]),
+                             np.array([1.0]), np.array([0.0]), np.array([0.5]))]
+    rng = np.random.default_rng(7)
+    while len(lps) < 21:
+        m, n = int(rng.integers(1, 4)), int(rng.integers(1, 4))
+        lp = ucgen.dense_to_lp(*ucgen.random_toy_lp(rng, m, n))
+        if exact.highs(lp)[0] == exact.INFEASIBLE:
+            lps.append(lp)
+    print("case infeasible toys", flush=True)
+    for t, lp in enumerate(lps):
+        p = Problem(lp, tol=1e-8, max_iter=50000)
+        x, y, info = p.solve()
+        p.close()
+        assert info["status"] == 5, (t, info)
+        assert farkas_value(oracle_mod, lp, y) > 0.0, t
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_infeasible_uc_node(gpu, oracle_mod, precision):
+    from paper_2512_06715_amd.solver import Problem
+    q = infeasible_node()
+    print("case infeasible node", precision, flush=True)
+    p = Problem(q, tol=1e-6, precision=precision, max_iter=100000)
+    x, y, info = p.solve()
+    p.close()
+    xo, yo, io = oracle_mod.pdhg(q, tol=1e-6, max_iter=100000)
+    print("gpu attempts", info["attempts"], "oracle", io["attempts"], flush=True)
+    assert info["status"] == 5 and io["status"] == 5
+    assert farkas_value(oracle_mod, q, y) > 0.0
+
+
+def test_infeasible_node_in_a_batch(gpu, oracle_mod):
+    """An infeasible child (slacks and period 5's units fixed to 0) next to
+    feasible ones: each instance gets its own status, the feasible ones their
+    tolerance.  Fixings keep the base's implied bounds (they only shrink the
+    feasible set), which the certificate needs for the free bus angles."""
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    lp = ucgen.workload("uc14_t24")
+    q = infeasible_node()
+    fixed = np.nonzero((q.l == q.u) & (lp.l != lp.u))[0].astype(np.int32)
+    print("case infeasible in batch", len(fixed), flush=True)
+    p = Problem(lp, tol=1e-4, max_iter=400000)
+    insts = [dict(base=0), dict(base=0, fix_idx=fixed, fix_val=q.l[fixed]),
+             dict(base=0, fix_idx=lp.meta["u_cols"][3].astype(np.int32),
+                  fix_val=np.ones(5))]
+    res = solve_batch([p], insts)
+    p.close()
+    print("statuses", [r[2]["status"] for r in res], "attempts", [r[2]["attempts"] for r in res],
+          flush=True)
+    assert [r[2]["status"] for r in res] == [1, 5, 1]
+    assert farkas_value(oracle_mod, q, res[1][1]) > 0.0
+    assert oracle_mod.kkt(lp, res[0][0], res[0][1])["rel_kkt"] <= 1.001e-4
+
+
+def test_no_test_when_disabled(gpu):
+    """infeas_every = 0 never reports infeasibility (the solve runs to its
+    attempt limit)."""
+    from paper_2512_06715_amd.solver import Problem
+    p = Problem(infeasible_node(), tol=1e-6, max_iter=4096, infeas_every=0)
+    print("case infeasibility test off", flush=True)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 2 and info["attempts"] == 4096
