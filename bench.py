@@ -212,6 +212,27 @@ def nodes_run(args):
             attempts_mean=round(float(np.mean(att)), 1), attempts_max=int(max(att)),
             bound_gap_median=float(np.median(gaps)), bound_gap_max=float(gaps.max()),
             bounds_finite=int(np.isfinite([k.bound for k in kids]).sum()))
+    # an infeasible child: the penalty slacks and every unit of period 5
+    # fixed to 0 (the load of that period cannot be met); fixings keep the
+    # base's implied bounds, which the certificate needs for the bus angles
+    n_unit, n_bus, n_line = 700, 4224, 5800
+    pos = np.arange(lp.n) % (4 * n_unit + 3 * n_bus + n_line + 1)
+    cols = np.concatenate([np.nonzero(pos >= 4 * n_unit + n_bus + n_line)[0],
+                           lp.meta["u_cols"][5]])
+    bad = N.Node(cols.astype(np.int32), np.zeros(len(cols)), 1, x0=root.x, y0=root.y,
+                 omega0=float(root.info["omega"]), eta0=float(root.info["eta"]),
+                 hold=int(root.info["attempts"]))
+    for mode in ("warm", "cold"):
+        nd = N.Node(bad.fix_idx, bad.fix_val)
+        if mode == "warm":
+            nd = bad
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        N.solve_nodes(prob, [nd], warm=mode == "warm")
+        torch.cuda.synchronize()
+        out["infeasible_child_" + mode] = dict(
+            status=nd.info["status_name"], attempts=nd.info["attempts"],
+            seconds=round(time.perf_counter() - t0, 3))
     prob.close()
     out["warm_speedup"] = round(out["cold"]["batch_s"] / out["warm"]["batch_s"], 3)
     return out
