@@ -253,7 +253,10 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_spmv_long(const Inst<T> *__
 // per-lane loops).  `mine` is false for rows longer than long_seg, whose
 // products a workgroup of their own computes beforehand.  Every lane must
 // call it; lds holds 2 (EV_TILE_CAP + PDHG_BLOCK) doubles.
-#define EV_TILE_CAP (8 * PDHG_BLOCK)
+// 1024 staged products per tile keep the two buffers at 20 KB, which allows
+// 7 workgroups per CU (2048 products, 37 KB, allowed 4 and was 10-19% slower
+// on 7.2M nonzeros, although fewer tiles fell back to per-lane loops)
+#define EV_TILE_CAP (4 * PDHG_BLOCK)
 template <typename X0>
 __device__ inline void eval_rowdots(const int32_t *ptr_, const int32_t *idx_, const double *v_,
                                     const X0 *x0_, const double *x1_, int64_t i, bool valid,
