@@ -65,3 +65,33 @@ def test_batch_rejects_bad_weights(gpu):
     x, y, info = solve_batch([p], [dict(base=0, omega0=3.0, eta0=0.5, hold_omega=200)])[0]
     p.close()
     assert info["status"] == 1
+
+
+def test_nodes_on_a_device_resident_problem(gpu, oracle_mod):
+    """The driver with the LP in device memory (fixings, warm starts and
+    results as CUDA tensors): same statuses and bounds below HiGHS's optima."""
+    import torch
+    from paper_2512_06715_amd import nodes as N
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc14_t24")
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).cuda()
+
+    class DevLP:
+        m, n = lp.m, lp.n
+        row_ptr = dev(lp.row_ptr, torch.int32)
+        col_idx = dev(lp.col_idx, torch.int32)
+        val = dev(lp.val, torch.float64)
+        row_kind = dev(lp.row_kind, torch.uint8)
+        b, c, l, u = (dev(a, torch.float64) for a in (lp.b, lp.c, lp.l, lp.u))
+    print("case device-resident nodes", flush=True)
+    p = Problem(DevLP, device=True, tol=1e-4, max_iter=400000)
+    root = N.solve_nodes(p, [N.root()])[0]
+    j = int(N.most_fractional(root, lp.meta["u_cols"].ravel())[0])
+    kids = N.solve_nodes(p, list(N.branch(root, j)))
+    p.close()
+    for nd in [root] + kids:
+        assert isinstance(nd.x, torch.Tensor) and nd.info["status"] == 1
+        st, xh, opt, yh = exact.highs(node_lp(lp, nd))
+        assert nd.bound <= opt
+        x, y = nd.x.cpu().numpy(), nd.y.cpu().numpy()
+        assert oracle_mod.kkt(node_lp(lp, nd), x, y)["rel_kkt"] <= 1.001e-4
