@@ -177,7 +177,8 @@ def nodes_run(args):
     """Branch-and-bound nodes of the 4224-bus, 48-period LP: the root is
     solved, then the children of its K most fractional commitments (each
     fixed to 0 and to 1, 2K nodes) are solved as one batch, warm-started from
-    the root's point, primal weight and step size; for comparison from the
+    the root's point, primal weight and step size (in mixed precision, and
+    in FP64 on a second handle of the same LP); for comparison from the
     point alone, and cold.  Reports the time, attempts and the safe bound's
     distance below each child's objective."""
     import numpy as np
@@ -197,11 +198,13 @@ def nodes_run(args):
                         "mixed, KKT %g" % (len(picks), args.tol),
                root_s=round(t_root, 3), root_attempts=root.info["attempts"],
                root_gap=(root.objective - root.bound) / abs(root.objective))
-    for mode in ("warm", "warm_point_only", "cold"):
+    prob64 = Problem(lp, tol=args.tol, precision="fp64", max_iter=args.max_iter)
+    for mode in ("warm", "warm_fp64", "warm_point_only", "cold"):
         kids = [k for j in picks for k in N.branch(root, int(j))]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        N.solve_nodes(prob, kids, warm=mode != "cold", weights=mode == "warm")
+        N.solve_nodes(prob64 if mode == "warm_fp64" else prob, kids, warm=mode != "cold",
+                      weights=mode in ("warm", "warm_fp64"))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         gaps = np.array([(k.objective - k.bound) / abs(k.objective) for k in kids])
@@ -234,7 +237,9 @@ def nodes_run(args):
             status=nd.info["status_name"], attempts=nd.info["attempts"],
             seconds=round(time.perf_counter() - t0, 3))
     prob.close()
+    prob64.close()
     out["warm_speedup"] = round(out["cold"]["batch_s"] / out["warm"]["batch_s"], 3)
+    out["warm_fp64_speedup"] = round(out["cold"]["batch_s"] / out["warm_fp64"]["batch_s"], 3)
     return out
 
 
