@@ -19,6 +19,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no multiply-add contraction: every product is rounded on its own, as in
+    # the oracle, so the LDS-staged and per-lane sums give the same bits
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

@@ -253,3 +253,23 @@ def test_repeat_runs_bit_identical(gpu, precision):
     assert res[0][2]["omega"] == res[1][2]["omega"]
     assert np.array_equal(res[0][0].view(np.uint64), res[1][0].view(np.uint64))
     assert np.array_equal(res[0][1].view(np.uint64), res[1][1].view(np.uint64))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lds_and_per_row_partitions_bit_identical(gpu, precision):
+    """Every product is rounded on its own (no multiply-add contraction), so
+    the LDS-staged tiles and the per-row loops give the same bits: 300
+    attempts with either partition, evaluations and restarts included."""
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc1000_t48")
+    print("case lds vs per-row", precision, flush=True)
+    res = []
+    for direct in (0, 1):
+        p = Problem(lp, max_iter=300, tol=1e-12, precision=precision, spmv_direct=direct)
+        assert p.partition()["direct"] == direct
+        res.append(p.solve())
+        p.close()
+    (x0, y0, i0), (x1, y1, i1) = res
+    assert i0["attempts"] == i1["attempts"] and i0["accepted"] == i1["accepted"]
+    assert np.array_equal(x0.view(np.uint64), x1.view(np.uint64))
+    assert np.array_equal(y0.view(np.uint64), y1.view(np.uint64))
