@@ -122,6 +122,9 @@ typedef struct {
   int polish_pw_update;   /* mixed precision: 1 (default) updates the primal weight at the
                              FP64 phase's restarts as in the FP32 phase; 0 keeps the weight
                              the FP32 phase ended with (faster on some LPs, stalls on others) */
+  int fp32_stall_evals;   /* mixed precision: the FP32 phase hands over to FP64 when the
+                             relative KKT error has not fallen below 0.9 of its best value
+                             for this many evaluations (default 300); 0: only at polish_tol */
 } pdhg_opts;
 
 typedef struct {

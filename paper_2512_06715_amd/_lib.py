@@ -36,7 +36,7 @@ class PdhgOpts(ctypes.Structure):
                 ("pw_theta", c_dbl), ("tiles_per_block", c_int), ("autotune", c_int),
                 ("spmv_direct", c_int), ("long_seg", c_int), ("reorder", c_int),
                 ("compact_index", c_int), ("infeas_every", c_int),
-                ("polish_pw_update", c_int)]
+                ("polish_pw_update", c_int), ("fp32_stall_evals", c_int)]
 
 
 class PdhgInfo(ctypes.Structure):

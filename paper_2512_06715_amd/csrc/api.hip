@@ -304,6 +304,7 @@ int check_opts(const pdhg_opts *o) {
   if (o->infeas_every < 0) return fail(PDHG_ERR_ARG, "infeas_every must be >= 0");
   if (o->polish_pw_update != 0 && o->polish_pw_update != 1)
     return fail(PDHG_ERR_ARG, "polish_pw_update must be 0 or 1");
+  if (o->fp32_stall_evals < 0) return fail(PDHG_ERR_ARG, "fp32_stall_evals must be >= 0");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -1009,7 +1010,7 @@ int solve_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
   RC(upload_group<float>(h, gd, i32, all, g));
   launch_init_point<float>(gd.d32, g, h->hs);
   HK();
-  RC(run_group<float>(h, gd, i32, all, tol32, h->o.max_iter, t0, 300, gslots[1], reuse, status,
+  RC(run_group<float>(h, gd, i32, all, tol32, h->o.max_iter, t0, h->o.fp32_stall_evals, gslots[1], reuse, status,
                       fin));
   std::vector<int> polish;
   for (int i = 0; i < B; i++) {
@@ -1202,6 +1203,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->compact_index = 1;
   o->infeas_every = 4;
   o->polish_pw_update = 1;
+  o->fp32_stall_evals = 300;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
