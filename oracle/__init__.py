@@ -49,7 +49,8 @@ class _Opts(ctypes.Structure):
                 ("pock_chambolle", ctypes.c_int), ("restart", ctypes.c_int),
                 ("use_average", ctypes.c_int), ("omega0", ctypes.c_double),
                 ("pw_theta", ctypes.c_double), ("infeas_every", ctypes.c_int),
-                ("ilo", ctypes.c_void_p), ("ihi", ctypes.c_void_p)]
+                ("ilo", ctypes.c_void_p), ("ihi", ctypes.c_void_p),
+                ("dinf_eps", ctypes.c_double)]
 
 
 def lib():
@@ -209,10 +210,12 @@ INFO_FIELDS = ("status", "attempts", "accepted", "restarts", "pobj", "dobj", "re
 
 def pdhg(lp, tol=1e-4, max_iter=100000, eval_period=64, step_mode=0, fixed_eta=0.0,
          ruiz_iters=10, pock_chambolle=True, restart=True, use_average=True,
-         omega0=0.0, pw_theta=0.5, x0=None, y0=None, infeas_every=4):
+         omega0=0.0, pw_theta=0.5, x0=None, y0=None, infeas_every=4, dinf_eps=1e-8):
     """Restarted PDHG in FP64.  Returns (x, y, info dict) in the original space.
     Every `infeas_every` evaluations (0: never) the current y is tested as a
-    certificate of primal infeasibility over the implied bounds (status 5)."""
+    certificate of primal infeasibility over the implied bounds (status 5),
+    then (dinf_eps > 0) the primal displacement since the last restart as a
+    ray certifying dual infeasibility (status 6; x is then the ray)."""
     a = _arrs(lp)
     ilo = ihi = None
     if infeas_every > 0:
@@ -220,7 +223,7 @@ def pdhg(lp, tol=1e-4, max_iter=100000, eval_period=64, step_mode=0, fixed_eta=0
     o = _Opts(tol, int(max_iter), int(eval_period), int(step_mode), float(fixed_eta),
               int(ruiz_iters), int(bool(pock_chambolle)), int(bool(restart)),
               int(bool(use_average)), float(omega0), float(pw_theta), int(infeas_every),
-              _p(ilo), _p(ihi))
+              _p(ilo), _p(ihi), float(dinf_eps))
     x = np.zeros(lp.n)
     y = np.zeros(lp.m)
     info = np.zeros(len(INFO_FIELDS))

@@ -32,6 +32,7 @@
 #define ST_ITER_LIMIT 2
 #define ST_NUMERICAL 4
 #define ST_PRIMAL_INFEASIBLE 5
+#define ST_DUAL_INFEASIBLE 6
 
 enum { VK_FREE = 0, VK_LOWER = 1, VK_UPPER = 2, VK_BOXED = 3, VK_FIXED = 4 };
 
@@ -310,7 +311,10 @@ typedef struct {
   int infeas_every;    /* > 0: every this many evaluations, test y for a
                           certificate of primal infeasibility */
   const double *ilo, *ihi;  /* bounds every feasible x satisfies (original
-                               space; NULL: l, u) for that test */
+                               space; NULL: l, u) for that test and the next */
+  double dinf_eps;     /* > 0: at the same evaluations, test the primal
+                          displacement since the last restart as a ray
+                          certifying dual infeasibility, with this tolerance */
 } orc_opts;
 
 /* info: [0] status [1] attempts [2] accepted [3] restarts [4] pobj [5] dobj
@@ -439,6 +443,50 @@ static double homogeneous_certificate(const scaled_lp *P, const double *y, const
   return (by + terms) - 2.0 * (double)(n + m + kmax + 4) * eps * (byabs + sabs);
 }
 
+/* Certificate of dual infeasibility (the primal has an improving ray): a
+ * direction d with c'd < 0 along which every constraint stays satisfied,
+ * i.e. (A d)_i = 0 on = rows, (A d)_i >= 0 on >= rows, and d_j in the
+ * recession cone of [lo_j, hi_j] (d_j = 0 where both ends are finite,
+ * d_j >= 0 where only lo_j is, d_j <= 0 where only hi_j is).  This is the
+ * test of PDLP, the PDHG variant the paper builds on; an approximate one:
+ * d passes when c'd < 0 and the largest violation is at most eps (-c'd),
+ * both homogeneous in d.  It is evaluated on the original problem.  The
+ * candidate is the primal iterate's displacement since the last restart,
+ * d^ = x - xl in the scaled space, d = Dc d^; on an unbounded LP the
+ * iterates move by a fixed ray per step once the projections stop changing.
+ * In the original space (A d)_i = (sum_k a^_ik d^_k) / Dr_i and
+ * c_j d_j = c^_j d^_j (power-of-two factors).  lo, hi: the scaled box of
+ * the infeasibility test (only their finiteness matters).  On success the
+ * unscaled d is written to ray and 1 is returned. */
+static int ray_certificate(const scaled_lp *P, const double *x, const double *xl,
+                           const double *lo, const double *hi, double eps, double *ray) {
+  const int64_t m = P->m, n = P->n;
+  double cd = 0.0, worst = 0.0;
+  for (int64_t j = 0; j < n; j++) {
+    const double dh = x[j] - xl[j];
+    const double d = P->Dc[j] * dh;
+    cd += P->c[j] * dh;
+    double viol = 0.0;
+    if (isfinite(lo[j]) && isfinite(hi[j]))
+      viol = fabs(d);
+    else if (isfinite(lo[j]))
+      viol = d < 0.0 ? -d : 0.0;
+    else if (isfinite(hi[j]))
+      viol = d > 0.0 ? d : 0.0;
+    if (viol > worst) worst = viol;
+  }
+  for (int64_t i = 0; i < m; i++) {
+    double s = 0.0;
+    for (int32_t k = P->rp[i]; k < P->rp[i + 1]; k++) s += P->v[k] * (x[P->ci[k]] - xl[P->ci[k]]);
+    const double r = s / P->Dr[i];
+    const double viol = P->kind[i] == 0 ? fabs(r) : (r < 0.0 ? -r : 0.0);
+    if (viol > worst) worst = viol;
+  }
+  if (!(cd < 0.0) || !(worst <= eps * -cd)) return 0;
+  for (int64_t j = 0; j < n; j++) ray[j] = P->Dc[j] * (x[j] - xl[j]);
+  return 1;
+}
+
 int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
              const double *v0, const uint8_t *kind, const double *b0, const double *c0,
              const double *l0, const double *u0, const orc_opts *o, const double *x0,
@@ -475,6 +523,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   double *xs = malloc(N8), *ys = malloc(M8);
   double *xa = malloc(N8), *ya = malloc(M8), *Axa = malloc(M8), *ATya = malloc(N8);
   double *xl = malloc(N8), *yl = malloc(M8);
+  double *ray = malloc(N8);
 
   /* start point: clamp(0 or x0) into the box; y0 projected onto the cone */
   for (int64_t j = 0; j < n; j++) x[j] = clampd(x0 ? x0[j] / Dc[j] : 0.0, l[j], u[j]);
@@ -563,6 +612,12 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
         which = 0;
         break;
       }
+      if (o->infeas_every > 0 && o->dinf_eps > 0.0 && k > 0 && (k / P_eval) % o->infeas_every == 0 &&
+          ray_certificate(&P, x, xl, blo, bhi, o->dinf_eps, ray)) {
+        status = ST_DUAL_INFEASIBLE;
+        which = 0;
+        break;
+      }
       /* ---- restart decision on the scaled KKT_omega ---- */
       if (o->restart && k > 0) {
         int cand_avg = have_avg && eva[0] < ev[0];
@@ -644,7 +699,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
 
   const double *xr = which ? xa : x, *yr = which ? ya : y;
   const double *er = which ? eva : ev;
-  for (int64_t j = 0; j < n; j++) x_out[j] = Dc[j] * xr[j];
+  for (int64_t j = 0; j < n; j++) x_out[j] = status == ST_DUAL_INFEASIBLE ? ray[j] : Dc[j] * xr[j];
   for (int64_t i = 0; i < m; i++) y_out[i] = Dr[i] * yr[i];
   info[0] = status;
   info[1] = (double)k;
@@ -664,7 +719,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   free(b); free(c); free(l); free(u); free(vk);
   free(x); free(y); free(Ax); free(ATy); free(xn); free(yn); free(Axn);
   free(xs); free(ys); free(xa); free(ya); free(Axa); free(ATya); free(xl); free(yl);
-  free(blo); free(bhi);
+  free(ray); free(blo); free(bhi);
   return ORC_OK;
 }
 

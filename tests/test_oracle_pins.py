@@ -561,3 +561,53 @@ def test_infeasible_uc_node(oracle_mod):
     assert exact.highs(q)[0] == exact.INFEASIBLE
     x, y, info = oracle_mod.pdhg(q, tol=1e-6, max_iter=100000)
     assert info["status"] == 5 and homogeneous_value(oracle_mod, q, y) > 0.0
+
+
+def test_ray_certificate_closed_forms(oracle_mod):
+    """Four unbounded LPs with known cones of improving rays: the oracle stops
+    with status 6 and returns a ray that passes the exact check and lies in
+    the closed-form cone; the same LP with a finite upper bound is solved
+    (optimum -10 at x = (10, 10)), never certified."""
+    from ray_check import is_ray, unbounded_toys
+    toys = unbounded_toys()
+    rays = []
+    for t, lp in enumerate(toys):
+        assert exact.highs(lp)[0] == exact.UNBOUNDED
+        x, y, info = oracle_mod.pdhg(lp, tol=1e-8, max_iter=100000)
+        assert info["status"] == 6, (t, info)
+        assert is_ray(lp, x), (t, x)
+        rays.append(x)
+    d = rays[0]
+    assert d[0] > 0 and abs(d[0] / d[1] - 1.0) <= 1e-8
+    assert rays[1][0] < 0
+    d = rays[2]
+    assert d[1] > 0 and d[0] - d[1] >= -1e-8 * d[1]
+    d = rays[3]
+    assert d.min() >= 0 and d[0] - 2 * d[1] < 0
+    q = toys[0].copy()
+    q.u[:] = 10.0
+    x, y, info = oracle_mod.pdhg(q, tol=1e-8, max_iter=100000)
+    assert info["status"] == 1 and abs(info["pobj"] + 10.0) <= 1e-6
+
+
+def test_dual_infeasibility_detected_on_toys(oracle_mod):
+    """Random toys: status 6 exactly for those HiGHS calls unbounded, each
+    with a ray that passes the exact check; 1 for the optimal ones; 5 for the
+    infeasible ones, or the attempt limit where the Farkas proof would need
+    (A'y)_j = 0 exactly on a column with an infinite bound on the needed side
+    (toy 480 of this stream: two free columns), never a wrong certificate."""
+    from ray_check import is_ray
+    rng = np.random.default_rng(11)
+    seen = {}
+    for t in range(500):
+        m, n = int(rng.integers(1, 4)), int(rng.integers(1, 4))
+        lp = ucgen.dense_to_lp(*ucgen.random_toy_lp(rng, m, n))
+        st = exact.highs(lp)[0]
+        x, y, info = oracle_mod.pdhg(lp, tol=1e-8, max_iter=100000)
+        want = {exact.OPTIMAL: (1,), exact.INFEASIBLE: (5, 2), exact.UNBOUNDED: (6,)}[st]
+        assert info["status"] in want, (t, st, info)
+        if info["status"] == 6:
+            assert is_ray(lp, x), (t, x)
+        seen[info["status"]] = seen.get(info["status"], 0) + 1
+    assert seen.get(6, 0) >= 15 and seen.get(1, 0) >= 50 and seen.get(5, 0) >= 50, seen
+    assert seen.get(2, 0) <= 2, seen
