@@ -122,14 +122,18 @@ def batch_run(args):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     ok = sum(1 for r in res if r[2]["status"] == 1)
+    print(f"[bench] batch of {len(lps)}: {tb:.2f}s, {ok} solved; now one at a time",
+          file=sys.stderr, flush=True)
     ts = 0.0
-    for p in probs:
+    for k, p in enumerate(probs):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         p.solve()
         torch.cuda.synchronize()
         ts += time.perf_counter() - t0
         p.close()
+        if k % 8 == 7:
+            print(f"[bench] {k + 1} solved one at a time, {ts:.2f}s", file=sys.stderr, flush=True)
     n = len(lps)
     return dict(instances=n, solved=ok, lps_per_s=round(n / tb, 4),
                 sequential_lps_per_s=round(n / ts, 4), speedup=round(ts / tb, 3),

@@ -57,9 +57,14 @@ enum {
   PDHG_ITER_LIMIT = 2,
   PDHG_TIME_LIMIT = 3,
   PDHG_NUMERICAL = 4,      /* NaN or Inf reached the iterates */
-  PDHG_PRIMAL_INFEASIBLE = 5 /* y is a certificate: with lambda = -A'y and y >= 0 on >= rows,
+  PDHG_PRIMAL_INFEASIBLE = 5, /* y is a certificate: with lambda = -A'y and y >= 0 on >= rows,
                               b'y + sum_j min(lambda_j lo_j, lambda_j hi_j) > 0 over the
                               implied bounds, beyond its rounding allowance (Farkas) */
+  PDHG_DUAL_INFEASIBLE = 6 /* x is a ray d (caller's order): c'd < 0, and the largest
+                              violation of (A d)_i = 0 on = rows, (A d)_i >= 0 on >= rows
+                              and of d_j in the recession cone of [lo_j, hi_j] (implied
+                              bounds) is at most dinf_tol (-c'd): a tolerance test, not a
+                              proof.  The LP is unbounded if it is feasible. */
 };
 
 enum { PDHG_ROW_EQ = 0, PDHG_ROW_GE = 1 };
@@ -124,7 +129,11 @@ typedef struct {
                              the FP32 phase ended with (faster on some LPs, stalls on others) */
   int fp32_stall_evals;   /* mixed precision: the FP32 phase hands over to FP64 when the
                              relative KKT error has not fallen below 0.9 of its best value
-                             for this many evaluations (default 300); 0: only at polish_tol */
+                             for this many evaluations (default 300); 0: only at polish_tol.
+                             NaN or Inf in the FP32 phase also hands over */
+  double dinf_tol;        /* at the infeasibility tests (infeas_every), the primal iterate's
+                             displacement since the last restart is tested as a ray with this
+                             tolerance (default 1e-8; 0: never): PDHG_DUAL_INFEASIBLE */
 } pdhg_opts;
 
 typedef struct {

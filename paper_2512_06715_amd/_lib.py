@@ -11,7 +11,8 @@ PDHG_OK = 0
 ERRORS = {-1: "PDHG_ERR_ARG", -2: "PDHG_ERR_CSR", -3: "PDHG_ERR_BOUNDS",
           -4: "PDHG_ERR_NONFINITE", -5: "PDHG_ERR_OOM", -6: "PDHG_ERR_HIP",
           -7: "PDHG_ERR_STATE"}
-STATUS = {1: "OPTIMAL", 2: "ITER_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL", 5: "PRIMAL_INFEASIBLE"}
+STATUS = {1: "OPTIMAL", 2: "ITER_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL", 5: "PRIMAL_INFEASIBLE",
+          6: "DUAL_INFEASIBLE"}
 PDHG_FP64, PDHG_MIXED = 0, 1
 
 c_i64 = ctypes.c_int64
@@ -36,7 +37,8 @@ class PdhgOpts(ctypes.Structure):
                 ("pw_theta", c_dbl), ("tiles_per_block", c_int), ("autotune", c_int),
                 ("spmv_direct", c_int), ("long_seg", c_int), ("reorder", c_int),
                 ("compact_index", c_int), ("infeas_every", c_int),
-                ("polish_pw_update", c_int), ("fp32_stall_evals", c_int)]
+                ("polish_pw_update", c_int), ("fp32_stall_evals", c_int),
+                ("dinf_tol", c_dbl)]
 
 
 class PdhgInfo(ctypes.Structure):

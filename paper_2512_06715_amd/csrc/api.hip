@@ -155,6 +155,9 @@ struct pdhg_handle {
   double *rylo = nullptr, *ryhi = nullptr;
   std::vector<double> h_ylo, h_yhi;
   bool rep_valid = false;
+  // c'x is bounded below on the implied box (setup's b, c): no direction of
+  // its recession cone improves the objective, so the ray test is skipped
+  bool obj_bounded = false;
   double bound_allow = 0.0;
   double *scratch;
   int nscratch = 0;
@@ -305,6 +308,8 @@ int check_opts(const pdhg_opts *o) {
   if (o->polish_pw_update != 0 && o->polish_pw_update != 1)
     return fail(PDHG_ERR_ARG, "polish_pw_update must be 0 or 1");
   if (o->fp32_stall_evals < 0) return fail(PDHG_ERR_ARG, "fp32_stall_evals must be >= 0");
+  if (!(o->dinf_tol >= 0.0) || !isfinite(o->dinf_tol))
+    return fail(PDHG_ERR_ARG, "dinf_tol must be finite and >= 0");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -564,6 +569,15 @@ int setup_implied_bounds(pdhg_handle *h, const pdhg_lp *lp) {
   }
   repair_intervals(m, n, prp, pci, pv, pk, hc.data(), h->h_ilo.data(), h->h_ihi.data(), h->h_ylo,
                    h->h_yhi);
+  // every feasible x lies in the implied box, so every ray of the feasible
+  // set lies in the box's recession cone; c'd >= 0 there when each term
+  // c_j x_j is bounded below on [lo_j, hi_j]
+  h->obj_bounded = true;
+  for (int64_t j = 0; j < n && h->obj_bounded; j++) {
+    const bool flo = isfinite(h->h_ilo[j]), fhi = isfinite(h->h_ihi[j]);
+    const double cj = hc[j];
+    h->obj_bounded = (flo && fhi) || cj == 0.0 || (cj > 0.0 && flo) || (cj < 0.0 && fhi);
+  }
   std::vector<int64_t> clen(n, 0);
   int64_t kmax = 0;
   for (int64_t k = 0; k < nnz; k++) kmax = std::max(kmax, ++clen[pci[k]]);
@@ -740,6 +754,7 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.pw_theta = h->o.pw_update ? h->o.pw_theta : 0.0;
   e.hold_k = 0;
   e.infeas_period = (long long)h->o.eval_period * h->o.infeas_every;
+  e.dinf_tol = h->obj_bounded ? 0.0 : h->o.dinf_tol;
   I.st = b.st;
   I.x0 = I.y0 = nullptr;
   I.xout = I.yout = nullptr;
@@ -1016,7 +1031,12 @@ int solve_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
   for (int i = 0; i < B; i++) {
     att32[i] = fin[i].k;
     final_fp32[i] = 1;
-    if (status[i] == 0 || (status[i] == PDHG_OPTIMAL && tol32 > h->o.tol)) polish.push_back(i);
+    // stalled, reached polish_tol, or NaN / Inf in the FP32 iterates (an
+    // overflow, e.g. on an unbounded LP): the FP64 phase goes on from the
+    // best point
+    if (status[i] == 0 || status[i] == PDHG_NUMERICAL ||
+        (status[i] == PDHG_OPTIMAL && tol32 > h->o.tol))
+      polish.push_back(i);
   }
   if (polish.empty()) return PDHG_OK;
   // FP64 refinement from the FP32 iterates (both tables describe the same
@@ -1204,6 +1224,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->infeas_every = 4;
   o->polish_pw_update = 1;
   o->fp32_stall_evals = 300;
+  o->dinf_tol = 1e-8;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -1799,6 +1820,7 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
     if (q.b || q.c || q.l || q.u) {  // and its repair intervals those and its c
       i64[k].e.rylo = i64[k].e.ryhi = nullptr;
       i32[k].e.rylo = i32[k].e.ryhi = nullptr;
+      i64[k].e.dinf_tol = i32[k].e.dinf_tol = hb->o.dinf_tol;  // and so does the ray-test skip
     }
     const double *wx = q.x0, *wy = q.y0;  // warm start, caller's order
     if (!hb->on_device) {
@@ -1866,10 +1888,12 @@ int pdhg_update(pdhg_handle *h, const double *b, const double *c) {
     RC(to_internal(h, h->b0, b, h->on_device, h->rperm, h->m, h->it.YA));
     h->impl_valid = false;  // they were derived from the old right-hand side
     h->rep_valid = false;
+    h->obj_bounded = false;
   }
   if (c) {
     RC(to_internal(h, h->c0, c, h->on_device, h->cperm, h->n, h->it.XA));
     h->rep_valid = false;  // the repair intervals come from the old costs
+    h->obj_bounded = false;
   }
   launch_scale_vectors(h->b0, h->c0, h->l0, h->u0, h->Dr, h->Dc, h->m, h->n, h->b, h->c, h->l,
                        h->u, h->hs);

@@ -113,6 +113,7 @@ struct EvalView {
   double pw_theta;               // 0 keeps the primal weight
   long long hold_k;              // no primal-weight update before this attempt
   long long infeas_period;       // attempts between infeasibility tests (0: none)
+  double dinf_tol;               // tolerance of the ray test at those (0: no ray test)
   int long_seg;
   // caller's index of each internal row / column (null: same order)
   const int32_t *rperm, *cperm;

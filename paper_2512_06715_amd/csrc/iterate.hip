@@ -663,45 +663,69 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_restart_rows(const Inst<T> *__re
 // current y, which the iteration keeps projected.  The test runs after the
 // evaluation's decisions and before its restart copies, and is skipped
 // (uniformly) when the instance is done or k is not a multiple of the period.
+//
+// Dual infeasibility (PDLP's ray test, a tolerance test): the primal
+// displacement since the last restart, d = Dc (x - XL), certifies an
+// improving ray when c'd < 0 and the largest violation of (A d)_i = 0 on =
+// rows, (A d)_i >= 0 on >= rows and of d_j in the recession cone of
+// [lo_j, hi_j] is at most dinf_tol (-c'd).  In the scaled problem
+// (A d)_i = (A^ d^)_i / Dr_i and c_j d_j = c^_j d^_j exactly.  On an
+// unbounded LP the iterates move by a fixed ray per step once their
+// projections stop changing, and a restart inside that phase makes d an
+// exact multiple of it.  Tested after the primal certificate.
 
 template <typename T>
 __device__ inline bool infeas_due(const EvalView<T> &e, const CtlState *st) {
   return e.infeas_period > 0 && !st->done && st->k > 0 && st->k % e.infeas_period == 0;
 }
 
-// Rows: partials [0] b'y, [1] sum |b_i y_i|.
+// Rows: partials [0] b'y, [1] sum |b_i y_i|, [2] largest violation of the
+// row's cone by A d (ray test; one lane per row over the FP64 matrix).
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_rows(const Inst<T> *__restrict__ I,
                                                             Groups g) {
   GROUP_BLOCK(p_rows)
   if (!infeas_due(e, st)) return;
   int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
-  double q[2] = {0.0, 0.0};
+  double q[3] = {0.0, 0.0, 0.0};
   if (i < e.m) {
+    const uint8_t ki = gin(e.kind)[i];
     double yi = (double)gin((const T *)e.Y[st->cur])[i];
-    if (gin(e.kind)[i] == 1 && yi < 0.0) yi = 0.0;
+    if (ki == 1 && yi < 0.0) yi = 0.0;
     double t = __dmul_rn(gin(e.b)[i], yi);
     q[0] = t;
     q[1] = fabs(t);
+    if (e.dinf_tol > 0.0) {
+      const AS_G int32_t *rp = gin(e.rp), *ci = gin(e.ci);
+      const AS_G double *v = gin(e.v), *xl = gin((const double *)e.XL);
+      const AS_G T *x = gin((const T *)e.X[st->cur]);
+      double s = 0.0;
+      for (int k = rp[i]; k < rp[i + 1]; k++) {
+        const int32_t j = ci[k];
+        s += __dmul_rn(v[k], (double)x[j] - xl[j]);
+      }
+      const double r = s / gin(e.Dr)[i];
+      q[2] = ki == 0 ? fabs(r) : fmax(-r, 0.0);
+    }
   }
-  double out[2];
-  block_reduce<2>(q, 0u, out);
-  if (threadIdx.x == 0) {
-    e.part_rows[lb] = out[0];
-    e.part_rows[(int64_t)e.nblk_rows + lb] = out[1];
-  }
+  double out[3];
+  block_reduce<3>(q, 4u, out);
+  if (threadIdx.x == 0)
+    for (int t = 0; t < 3; t++) e.part_rows[(int64_t)t * e.nblk_rows + lb] = out[t];
 }
 
 // Columns, one lane per column: lambda_j = -sum_i a_ij y_i in ascending row
 // order, its error bound, and the term as in the safe bound (c = 0).
-// Partials [0] terms, [1] magnitudes, [2] needed infinite bounds.
+// Partials [0] terms, [1] magnitudes, [2] needed infinite bounds; for the
+// ray test [3] c'd and [4] the largest violation of the bounds' recession
+// cones by d.
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_cols(const Inst<T> *__restrict__ I,
                                                             Groups g) {
   GROUP_BLOCK(p_cols)
   if (!infeas_due(e, st)) return;
   int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
-  double q[3] = {0.0, 0.0, 0.0};
+  double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (j < e.n) {
     const AS_G int32_t *cp = gin(e.cp), *ri = gin(e.ri);
     const AS_G double *vt = gin(e.vt);
@@ -740,27 +764,40 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_cols(const Inst<T> *__res
       q[0] = fmin(__dmul_rn(lam, lo), __dmul_rn(lam, hi));
       q[1] = fmax(fabs(lo), fabs(hi)) * sa;
     }
+    if (e.dinf_tol > 0.0) {
+      const double dh = (double)gin((const T *)e.X[st->cur])[j] - gin((const double *)e.XL)[j];
+      const double d = __dmul_rn(gin(e.Dc)[j], dh);
+      q[3] = __dmul_rn(gin(e.c)[j], dh);
+      const bool flo = isfinite(lo), fhi = isfinite(hi);
+      q[4] = flo && fhi ? fabs(d) : flo ? fmax(-d, 0.0) : fhi ? fmax(d, 0.0) : 0.0;
+    }
   }
-  double out[3];
-  block_reduce<3>(q, 0u, out);
+  double out[5];
+  block_reduce<5>(q, 16u, out);
   if (threadIdx.x == 0)
-    for (int t = 0; t < 3; t++) e.part_cols[(int64_t)t * e.nblk_cols + lb] = out[t];
+    for (int t = 0; t < 5; t++) e.part_cols[(int64_t)t * e.nblk_cols + lb] = out[t];
 }
 
-// One workgroup per instance: the value in fixed order; a positive one ends
-// the solve with the current iterate as the certificate.
+// One workgroup per instance: the values in fixed order.  A positive Farkas
+// value ends the solve with the current iterate as the certificate; else a
+// passing ray test ends it with the ray (returned as x).
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_finish(const Inst<T> *__restrict__ I) {
   const EvalView<T> &e = I[blockIdx.x].e;
   CtlState *st = I[blockIdx.x].st;
   if (!infeas_due(e, st)) return;
-  double r[2], c[3];
-  reduce_partials<2, PDHG_BLOCK>(e.part_rows, e.nblk_rows, e.nblk_rows, 0u, r);
-  reduce_partials<3, PDHG_BLOCK>(e.part_cols, e.nblk_cols, e.nblk_cols, 0u, c);
-  if (threadIdx.x == 0 && c[2] == 0.0 &&
-      (r[0] + c[0]) - e.bound_allow * (r[1] + c[1]) > 0.0) {
+  double r[3], c[5];
+  reduce_partials<3, PDHG_BLOCK>(e.part_rows, e.nblk_rows, e.nblk_rows, 4u, r);
+  reduce_partials<5, PDHG_BLOCK>(e.part_cols, e.nblk_cols, e.nblk_cols, 16u, c);
+  if (threadIdx.x != 0) return;
+  int status = 0;
+  if (c[2] == 0.0 && (r[0] + c[0]) - e.bound_allow * (r[1] + c[1]) > 0.0)
+    status = 5;  // PDHG_PRIMAL_INFEASIBLE
+  else if (e.dinf_tol > 0.0 && c[3] < 0.0 && fmax(r[2], c[4]) <= e.dinf_tol * -c[3])
+    status = 6;  // PDHG_DUAL_INFEASIBLE
+  if (status) {
     st->done = 1;
-    st->status = 5;  // PDHG_PRIMAL_INFEASIBLE
+    st->status = status;
     st->which = 0;
     st->restart_flag = 0;
   }
@@ -980,6 +1017,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_unscale_cols(const Inst<T> *__re
   int64_t j = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (j >= e.n) return;
   double xv = st->which ? e.XA[j] : (double)e.X[st->cur][j];
+  if (st->status == 6) xv = (double)e.X[st->cur][j] - e.XL[j];  // the ray
   I[inst].xout[e.cperm ? e.cperm[j] : j] = e.Dc[j] * xv;
 }
 

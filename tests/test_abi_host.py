@@ -36,7 +36,7 @@ def test_default_opts():
     assert o.pock_chambolle == 1 and o.restart == 1 and o.use_average == 1
     assert o.step_mode == 0 and o.precision == L.PDHG_FP64 and o.pw_theta == 0.5
     assert o.reorder == 1 and o.compact_index == 1 and o.polish_pw_update == 1
-    assert o.fp32_stall_evals == 300
+    assert o.fp32_stall_evals == 300 and o.dinf_tol == 1e-8
 
 
 def _lp_struct(lp):
@@ -108,7 +108,7 @@ def test_setup_rejects_bad_options_and_small_workspace():
     assert _setup_rc(lp, dict(precision=7))[0] == -1
     assert _setup_rc(lp, dict(pw_theta=2.0))[0] == -1
     for bad in (dict(reorder=2), dict(compact_index=-1), dict(polish_pw_update=3),
-                dict(fp32_stall_evals=-1)):
+                dict(fp32_stall_evals=-1), dict(dinf_tol=-1.0)):
         rc, msg = _setup_rc(lp, bad)
         assert rc == -1 and list(bad)[0] in msg, (bad, msg)
     lib = L.load()

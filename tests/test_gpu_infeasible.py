@@ -95,3 +95,44 @@ def test_no_test_when_disabled(gpu):
     x, y, info = p.solve()
     p.close()
     assert info["status"] == 2 and info["attempts"] == 4096
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_unbounded_toys(gpu, oracle_mod, precision):
+    """The four closed-form unbounded LPs and ten random toys HiGHS calls
+    unbounded end with status 6, as in the oracle, and the returned x is a ray
+    that passes the exact check.  In mixed precision the FP32 phase hands
+    over (stall or overflow) and the FP64 phase certifies."""
+    from paper_2512_06715_amd.solver import Problem
+    from ray_check import is_ray, random_unbounded_toys, unbounded_toys
+    lps = unbounded_toys() + random_unbounded_toys(10)
+    for t, lp in enumerate(lps):
+        print("case unbounded toy", precision, t, flush=True)
+        p = Problem(lp, tol=1e-8, precision=precision, max_iter=200000)
+        x, y, info = p.solve()
+        p.close()
+        xo, yo, io = oracle_mod.pdhg(lp, tol=1e-8, max_iter=200000)
+        assert io["status"] == 6 and is_ray(lp, xo)
+        assert info["status"] == 6, (t, info)
+        assert is_ray(lp, x), (t, x)
+        print("attempts", info["attempts"], "fp32", info["attempts_fp32"], "oracle", io["attempts"],
+              flush=True)
+
+
+def test_batch_bounded_and_unbounded(gpu):
+    """One batch over one matrix: min -x1 with x1 = x2 and 0 <= x <= 10
+    (optimum -10), and the same LP without upper bounds through a per-instance
+    override: statuses 1 and 6, the second with a valid ray."""
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    from ray_check import is_ray, unbounded_toys
+    lp = unbounded_toys()[0].copy()
+    lp.u[:] = 10.0
+    print("case batch bounded + unbounded", flush=True)
+    p = Problem(lp, tol=1e-8, max_iter=200000)
+    res = solve_batch([p], [dict(base=0), dict(base=0, u=np.array([np.inf, np.inf]))])
+    p.close()
+    assert res[0][2]["status"] == 1 and abs(res[0][2]["primal_obj"] + 10.0) <= 1e-6, res[0][2]
+    assert res[1][2]["status"] == 6, res[1][2]
+    q = lp.copy()
+    q.u[:] = np.inf
+    assert is_ray(q, res[1][0])
