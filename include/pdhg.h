@@ -123,7 +123,8 @@ typedef struct {
                              CSR.  The results do not depend on it */
   int infeas_every;       /* every this many evaluations (default 4; 0: never) the current y
                              is tested as a certificate of primal infeasibility; a proof
-                             ends the solve with PDHG_PRIMAL_INFEASIBLE and returns it */
+                             ends the solve with PDHG_PRIMAL_INFEASIBLE and returns it.
+                             The ray test of dinf_tol runs at the same evaluations */
   int polish_pw_update;   /* mixed precision: 1 (default) updates the primal weight at the
                              FP64 phase's restarts as in the FP32 phase; 0 keeps the weight
                              the FP32 phase ended with (faster on some LPs, stalls on others) */
@@ -133,7 +134,10 @@ typedef struct {
                              NaN or Inf in the FP32 phase also hands over */
   double dinf_tol;        /* at the infeasibility tests (infeas_every), the primal iterate's
                              displacement since the last restart is tested as a ray with this
-                             tolerance (default 1e-8; 0: never): PDHG_DUAL_INFEASIBLE */
+                             tolerance (default 1e-8; 0: never): PDHG_DUAL_INFEASIBLE.
+                             Skipped where c'x is bounded below on the implied box (every
+                             column bounded on both sides, or its cost of the sign that the
+                             one finite bound limits, or zero): no ray can improve there */
 } pdhg_opts;
 
 typedef struct {
