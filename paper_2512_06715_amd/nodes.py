@@ -29,6 +29,8 @@ import numpy as np
 
 from .solver import solve_batch
 
+PRIMAL_INFEASIBLE = 5   # pdhg_info.status of a proved-infeasible LP
+
 
 @dataclasses.dataclass
 class Node:
@@ -52,8 +54,14 @@ class Node:
 
     @property
     def bound(self) -> float:
-        """Lower bound on this node's LP optimum (-inf before solving)."""
-        return float(self.info["dual_bound"]) if self.info else -np.inf
+        """Lower bound on this node's LP optimum: -inf before solving, +inf
+        when the solve proved the LP infeasible (a Farkas certificate: no
+        feasible point, so its subtree is empty), else the safe bound."""
+        if not self.info:
+            return -np.inf
+        if int(self.info.get("status", 0)) == PRIMAL_INFEASIBLE:
+            return np.inf
+        return float(self.info["dual_bound"])
 
     @property
     def objective(self) -> float:
@@ -128,7 +136,7 @@ def solve_nodes(problem, nodes: List[Node], warm: bool = True,
 def prune(nodes: Sequence[Node], incumbent: float) -> Tuple[List[Node], List[Node]]:
     """Split solved nodes into (kept, pruned): a node is pruned when its safe
     bound is above the incumbent's objective, so its subtree holds nothing
-    better."""
+    better; a node proved infeasible always is (its bound is +inf)."""
     kept, cut = [], []
     for nd in nodes:
         (cut if nd.bound > incumbent else kept).append(nd)

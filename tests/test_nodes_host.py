@@ -39,3 +39,17 @@ def test_prune_uses_the_bound_strictly():
     assert [n.bound for n in kept] == [1.0, 2.0, -np.inf]
     assert [n.bound for n in cut] == [3.0]
     assert N.root().bound == -np.inf
+
+
+def test_prune_drops_nodes_proved_infeasible():
+    """A Farkas certificate (status 5) empties the subtree whatever the
+    computed bound; an unbounded relaxation (status 6) keeps its -inf."""
+    inf = solved([], [], [0.0], bound=-np.inf)
+    inf.info["status"] = 5
+    unb = solved([], [], [0.0], bound=-np.inf)
+    unb.info["status"] = 6
+    ok = solved([], [], [0.0], bound=1.0)
+    ok.info["status"] = 1
+    kept, cut = N.prune([inf, unb, ok], 1e30)
+    assert [id(n) for n in cut] == [id(inf)] and [id(n) for n in kept] == [id(unb), id(ok)]
+    assert inf.bound == np.inf and unb.bound == -np.inf and ok.bound == 1.0
