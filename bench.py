@@ -217,6 +217,7 @@ def nodes_run(args):
             nodes=len(kids), solved=sum(k.info["status"] == 1 for k in kids),
             batch_s=round(dt, 3), nodes_per_s=round(len(kids) / dt, 3),
             attempts_mean=round(float(np.mean(att)), 1), attempts_max=int(max(att)),
+            attempts_fp32_mean=round(float(np.mean([k.info["attempts_fp32"] for k in kids])), 1),
             bound_gap_median=float(np.median(gaps)), bound_gap_max=float(gaps.max()),
             bounds_finite=int(np.isfinite([k.bound for k in kids]).sum()))
     # an infeasible child: the penalty slacks and every unit of period 5

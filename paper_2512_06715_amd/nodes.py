@@ -15,10 +15,9 @@ objective can therefore be pruned exactly.
 
 The search itself (node selection, incumbent heuristics, branching rules
 beyond the most fractional commitment) belongs to the caller.  Warm-started
-children start near their optimum, where an FP32 phase adds little but
-rounding: an FP64 handle of the same LP solves them in about half the
-attempts of a mixed-precision one (16 children of the 4224-bus root: 4.7 s
-against 7.8 s), so the root may use mixed precision and its children FP64.
+children may be solved on a mixed-precision or an FP64 handle of the same LP
+at about the same cost (16 children of the 4224-bus root: 4.67 s in mixed
+precision, 13.2k attempts mean, against 4.72 s and 10.2k in FP64).
 """
 from __future__ import annotations
 
