@@ -611,3 +611,24 @@ def test_dual_infeasibility_detected_on_toys(oracle_mod):
         seen[info["status"]] = seen.get(info["status"], 0) + 1
     assert seen.get(6, 0) >= 15 and seen.get(1, 0) >= 50 and seen.get(5, 0) >= 50, seen
     assert seen.get(2, 0) <= 2, seen
+
+
+def test_ray_checker_hand_cases():
+    """The exact checker itself, on hand-made directions of the four toys:
+    rays of their closed-form cones pass, and each way of leaving the cone
+    (an equality row broken, a >= row gone negative, a lower-bounded column
+    decreasing, a non-improving direction) fails."""
+    from fractions import Fraction
+    from ray_check import is_ray, ray_violation, unbounded_toys
+    t0, t1, t2, t3 = unbounded_toys()
+    assert is_ray(t0, np.array([1.0, 1.0])) and is_ray(t0, np.array([3.0, 3.0]))
+    assert ray_violation(t0, np.array([1.0, 1.0])) == (Fraction(-1), Fraction(0))
+    assert not is_ray(t0, np.array([1.0, 0.5]))          # x1 - x2 = 0 broken
+    assert not is_ray(t0, np.array([-1.0, -1.0]))        # leaves x >= 0, c'd > 0
+    assert is_ray(t1, np.array([-2.0])) and not is_ray(t1, np.array([2.0]))
+    assert is_ray(t2, np.array([2.0, 1.0])) and is_ray(t2, np.array([1.0, 1.0]))
+    assert not is_ray(t2, np.array([0.5, 1.0]))          # x1 - x2 >= 0 violated
+    assert not is_ray(t2, np.array([-1.0, 1.0]))         # x1 >= 0 decreasing
+    assert is_ray(t3, np.array([0.0, 1.0])) and is_ray(t3, np.array([1.0, 1.0]))
+    assert not is_ray(t3, np.array([2.0, 1.0]))          # c'd = 0: not improving
+    assert not is_ray(t3, np.array([-0.5, 1.0]))         # x1 >= 0 decreasing
