@@ -181,7 +181,10 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace,
 
 /* Solve from x0, y0 (nullable; original space, device pointers if the LP
  * was given on the device, else host) and write x[n], y[m] (same memory
- * kind).  info is host memory. */
+ * kind).  info is host memory.  x, y are the returned point (info.which);
+ * with PDHG_PRIMAL_INFEASIBLE y is the certificate, with
+ * PDHG_DUAL_INFEASIBLE x is the ray (y then the current iterate).  The same
+ * holds per instance for pdhg_solve_batch. */
 int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x,
                double *y, pdhg_info *info);
 
