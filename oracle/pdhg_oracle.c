@@ -467,7 +467,9 @@ static int ray_certificate(const scaled_lp *P, const double *x, const double *xl
     const double d = P->Dc[j] * dh;
     cd += P->c[j] * dh;
     double viol = 0.0;
-    if (isfinite(lo[j]) && isfinite(hi[j]))
+    if (!isfinite(d))
+      viol = INFINITY;  /* an overflowed direction is no certificate */
+    else if (isfinite(lo[j]) && isfinite(hi[j]))
       viol = fabs(d);
     else if (isfinite(lo[j]))
       viol = d < 0.0 ? -d : 0.0;
@@ -479,7 +481,7 @@ static int ray_certificate(const scaled_lp *P, const double *x, const double *xl
     double s = 0.0;
     for (int32_t k = P->rp[i]; k < P->rp[i + 1]; k++) s += P->v[k] * (x[P->ci[k]] - xl[P->ci[k]]);
     const double r = s / P->Dr[i];
-    const double viol = P->kind[i] == 0 ? fabs(r) : (r < 0.0 ? -r : 0.0);
+    const double viol = !isfinite(r) ? INFINITY : P->kind[i] == 0 ? fabs(r) : (r < 0.0 ? -r : 0.0);
     if (viol > worst) worst = viol;
   }
   if (!(cd < 0.0) || !(worst <= eps * -cd)) return 0;
