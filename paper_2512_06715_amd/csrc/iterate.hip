@@ -705,7 +705,8 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_rows(const Inst<T> *__res
         s += __dmul_rn(v[k], (double)x[j] - xl[j]);
       }
       const double r = s / gin(e.Dr)[i];
-      q[2] = ki == 0 ? fabs(r) : fmax(-r, 0.0);
+      // non-finite counts as infinite (fmax would drop a NaN)
+      q[2] = !isfinite(r) ? INFINITY : ki == 0 ? fabs(r) : fmax(-r, 0.0);
     }
   }
   double out[3];
@@ -769,7 +770,11 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_cols(const Inst<T> *__res
       const double d = __dmul_rn(gin(e.Dc)[j], dh);
       q[3] = __dmul_rn(gin(e.c)[j], dh);
       const bool flo = isfinite(lo), fhi = isfinite(hi);
-      q[4] = flo && fhi ? fabs(d) : flo ? fmax(-d, 0.0) : fhi ? fmax(d, 0.0) : 0.0;
+      q[4] = !isfinite(d)  ? INFINITY
+             : flo && fhi ? fabs(d)
+             : flo        ? fmax(-d, 0.0)
+             : fhi        ? fmax(d, 0.0)
+                          : 0.0;
     }
   }
   double out[5];
