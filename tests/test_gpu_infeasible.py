@@ -136,3 +136,33 @@ def test_batch_bounded_and_unbounded(gpu):
     q = lp.copy()
     q.u[:] = np.inf
     assert is_ray(q, res[1][0])
+
+
+def test_ray_test_skip_follows_the_costs(gpu):
+    """min x1 with x1 = x2 and x >= 0 has c'x bounded below on its box, so
+    the ray test is skipped for it (optimum 0).  A cost override in a batch
+    (c = (-1, 0)) and an update of c on the handle each make it unbounded,
+    and each turns the test back on: status 6 with a valid ray.  With the
+    tolerance at 0 the test never runs and the unbounded copy does not end
+    with status 6."""
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    from ray_check import is_ray, unbounded_toys
+    lp = unbounded_toys()[0].copy()
+    lp.c = np.array([1.0, 0.0])
+    neg = lp.copy()
+    neg.c = np.array([-1.0, 0.0])
+    print("case ray-test skip", flush=True)
+    p = Problem(lp, tol=1e-8, max_iter=20000)
+    x, y, info = p.solve()
+    assert info["status"] == 1 and abs(info["primal_obj"]) <= 1e-6, info
+    res = solve_batch([p], [dict(base=0), dict(base=0, c=neg.c)])
+    assert res[0][2]["status"] == 1 and res[1][2]["status"] == 6, (res[0][2], res[1][2])
+    assert is_ray(neg, res[1][0])
+    p.update(c=neg.c)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 6 and is_ray(neg, x), info
+    q = Problem(neg, tol=1e-8, max_iter=20000, dinf_tol=0.0)
+    x, y, info = q.solve()
+    q.close()
+    assert info["status"] != 6, info
