@@ -680,7 +680,12 @@ __device__ inline bool infeas_due(const EvalView<T> &e, const CtlState *st) {
 }
 
 // Rows: partials [0] b'y, [1] sum |b_i y_i|, [2] largest violation of the
-// row's cone by A d (ray test; one lane per row over the FP64 matrix).
+// row's cone by A d (ray test, over the FP64 matrix).  A row of up to
+// INFEAS_LANE_ROW entries is summed by its own lane; a longer one by the
+// whole wave, one such row after the other (lanes stride its entries, a
+// butterfly sums them), so a few thousand-entry rows do not hold a wave
+// for thousands of dependent loads.
+#define INFEAS_LANE_ROW 64
 template <typename T>
 __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_rows(const Inst<T> *__restrict__ I,
                                                             Groups g) {
@@ -688,22 +693,48 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_rows(const Inst<T> *__res
   if (!infeas_due(e, st)) return;
   int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   double q[3] = {0.0, 0.0, 0.0};
+  const bool ray = e.dinf_tol > 0.0;
+  const AS_G int32_t *rp = gin(e.rp), *ci = gin(e.ci);
+  const AS_G double *v = gin(e.v), *xl = gin((const double *)e.XL);
+  const AS_G T *x = gin((const T *)e.X[st->cur]);
+  int a = 0, z = 0;
+  uint8_t ki = 0;
+  double s = 0.0;
   if (i < e.m) {
-    const uint8_t ki = gin(e.kind)[i];
+    ki = gin(e.kind)[i];
     double yi = (double)gin((const T *)e.Y[st->cur])[i];
     if (ki == 1 && yi < 0.0) yi = 0.0;
     double t = __dmul_rn(gin(e.b)[i], yi);
     q[0] = t;
     q[1] = fabs(t);
-    if (e.dinf_tol > 0.0) {
-      const AS_G int32_t *rp = gin(e.rp), *ci = gin(e.ci);
-      const AS_G double *v = gin(e.v), *xl = gin((const double *)e.XL);
-      const AS_G T *x = gin((const T *)e.X[st->cur]);
-      double s = 0.0;
-      for (int k = rp[i]; k < rp[i + 1]; k++) {
+    if (ray) {
+      a = rp[i];
+      z = rp[i + 1];
+      if (z - a <= INFEAS_LANE_ROW)
+        for (int k = a; k < z; k++) {
+          const int32_t j = ci[k];
+          s += __dmul_rn(v[k], (double)x[j] - xl[j]);
+        }
+    }
+  }
+  if (ray) {
+    // long rows of this wave, in lane order (the loop is uniform per wave)
+    uint64_t pend = __ballot(i < e.m && z - a > INFEAS_LANE_ROW);
+    const int lane = threadIdx.x & 63;
+    while (pend) {
+      const int src = __ffsll((unsigned long long)pend) - 1;
+      pend &= pend - 1;
+      const int ra = __shfl(a, src), rz = __shfl(z, src);
+      double part = 0.0;
+      for (int k = ra + lane; k < rz; k += 64) {
         const int32_t j = ci[k];
-        s += __dmul_rn(v[k], (double)x[j] - xl[j]);
+        part += __dmul_rn(v[k], (double)x[j] - xl[j]);
       }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+      if (lane == src) s = part;
+    }
+    if (i < e.m) {
       const double r = s / gin(e.Dr)[i];
       // non-finite counts as infinite (fmax would drop a NaN)
       q[2] = !isfinite(r) ? INFINITY : ki == 0 ? fabs(r) : fmax(-r, 0.0);

@@ -166,3 +166,31 @@ def test_ray_test_skip_follows_the_costs(gpu):
     x, y, info = q.solve()
     q.close()
     assert info["status"] != 6, info
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_unbounded_with_long_rows(gpu, oracle_mod, precision):
+    """Rows longer than one lane's share of the ray test, summed by the whole
+    wave: min -x0 with x0 equal to the mean of x1..x199 (a 200-entry row) and
+    a >= row over all 1000 columns, x >= 0.  Unbounded along d = 1 on
+    x0..x199: status 6 with a valid ray, as in the oracle."""
+    from paper_2512_06715_amd.solver import Problem
+    from ray_check import is_ray
+    n = 1000
+    A = np.zeros((2, n))
+    A[0, 0] = 1.0
+    A[0, 1:200] = -1.0 / 199.0
+    A[1, :] = 1.0
+    c = np.zeros(n)
+    c[0] = -1.0
+    lp = ucgen.dense_to_lp(A, np.array([0, 1], np.uint8), np.array([0.0, 1.0]), c,
+                           np.zeros(n), np.full(n, np.inf))
+    print("case unbounded long rows", precision, flush=True)
+    xo, yo, io = oracle_mod.pdhg(lp, tol=1e-8, max_iter=200000)
+    assert io["status"] == 6 and is_ray(lp, xo)
+    p = Problem(lp, tol=1e-8, precision=precision, max_iter=200000)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 6, info
+    assert is_ray(lp, x)
+    print("attempts", info["attempts"], "oracle", io["attempts"], flush=True)
