@@ -390,22 +390,31 @@ double orc_power_norm(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci
   return est;
 }
 
+int64_t orc_bound_repair(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci,
+                         const double *v, const uint8_t *kind, const double *c,
+                         const double *lo, const double *hi, double *ylo, double *yhi);
+
 /* Certificate of primal infeasibility (Farkas): for y with y_i >= 0 on >= rows
  * and a box [lo, hi] that holds every feasible x, feasibility would give
  * b'y <= y'Ax = sum_j (A'y)_j x_j <= sum_j max over [lo_j, hi_j] of
  * (A'y)_j x_j; so b'y + sum_j min(lambda_j lo_j, lambda_j hi_j) > 0 with
  * lambda = -A'y proves that no feasible x exists.  This is the safe bound's
- * sum for c = 0 (same sign rule and allowance), on the scaled problem, with
- * y used as it is (no repair).  Returns the value lowered by the allowance,
- * or -INFINITY when a needed bound is infinite. */
+ * sum for c = 0 (same sign rule and allowance), on the scaled problem.  Any
+ * such y will do, so y is first clamped into the safe bound's repair
+ * intervals for c = 0 (ylo, yhi; nullable): a row whose single-entry column
+ * has an infinite bound on the side lambda_j would need gets the sign (or
+ * the zero) that keeps lambda_j usable.  The intervals' ends are 0 or
+ * infinite, so the scaling leaves them unchanged.  Returns the value lowered
+ * by the allowance, or -INFINITY when a needed bound is infinite. */
 static double homogeneous_certificate(const scaled_lp *P, const double *y, const double *lo,
-                                      const double *hi) {
+                                      const double *hi, const double *ylo, const double *yhi) {
   const int64_t m = P->m, n = P->n;
   const double eps = ldexp(1.0, -53);
   double by = 0.0, byabs = 0.0, terms = 0.0, sabs = 0.0;
   int64_t kmax = 0, ninf = 0;
   for (int64_t i = 0; i < m; i++) {
     double yi = (P->kind[i] == 1 && y[i] < 0.0) ? 0.0 : y[i];
+    if (ylo) yi = fmin(fmax(yi, ylo[i]), yhi[i]);
     double t = P->b[i] * yi;
     by += t;
     byabs += fabs(t);
@@ -415,6 +424,7 @@ static double homogeneous_certificate(const scaled_lp *P, const double *y, const
     for (int32_t k = P->cp[j]; k < P->cp[j + 1]; k++) {
       int32_t i = P->ri[k];
       double yi = (P->kind[i] == 1 && y[i] < 0.0) ? 0.0 : y[i];
+      if (ylo) yi = fmin(fmax(yi, ylo[i]), yhi[i]);
       double pr = P->vt[k] * yi;
       s += pr;
       sa += fabs(pr);
@@ -558,6 +568,14 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
 
   /* the box of the infeasibility test, scaled */
   double *blo = (double *)malloc(N8), *bhi = (double *)malloc(N8);
+  /* the repair intervals of the Farkas test (c = 0) over the same box */
+  double *fylo = (double *)malloc(M8 > 0 ? M8 : 8), *fyhi = (double *)malloc(M8 > 0 ? M8 : 8);
+  {
+    double *zero = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    orc_bound_repair(m, n, rp0, ci0, v0, kind, zero, o->ilo ? o->ilo : l0,
+                     o->ihi ? o->ihi : u0, fylo, fyhi);
+    free(zero);
+  }
   for (int64_t j = 0; j < n; j++) {
     blo[j] = (o->ilo ? o->ilo[j] : l0[j]) / Dc[j];
     bhi[j] = (o->ihi ? o->ihi[j] : u0[j]) / Dc[j];
@@ -609,7 +627,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
         break;
       }
       if (o->infeas_every > 0 && k > 0 && (k / P_eval) % o->infeas_every == 0 &&
-          homogeneous_certificate(&P, y, blo, bhi) > 0.0) {
+          homogeneous_certificate(&P, y, blo, bhi, fylo, fyhi) > 0.0) {
         status = ST_PRIMAL_INFEASIBLE;
         which = 0;
         break;
@@ -702,7 +720,14 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   const double *xr = which ? xa : x, *yr = which ? ya : y;
   const double *er = which ? eva : ev;
   for (int64_t j = 0; j < n; j++) x_out[j] = status == ST_DUAL_INFEASIBLE ? ray[j] : Dc[j] * xr[j];
-  for (int64_t i = 0; i < m; i++) y_out[i] = Dr[i] * yr[i];
+  for (int64_t i = 0; i < m; i++) {
+    double yv = yr[i];
+    if (status == ST_PRIMAL_INFEASIBLE) {  /* the certificate as the test took it */
+      if (kind[i] == 1 && yv < 0.0) yv = 0.0;
+      yv = fmin(fmax(yv, fylo[i]), fyhi[i]);
+    }
+    y_out[i] = Dr[i] * yv;
+  }
   info[0] = status;
   info[1] = (double)k;
   info[2] = (double)accepted;
@@ -721,7 +746,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   free(b); free(c); free(l); free(u); free(vk);
   free(x); free(y); free(Ax); free(ATy); free(xn); free(yn); free(Axn);
   free(xs); free(ys); free(xa); free(ya); free(Axa); free(ATya); free(xl); free(yl);
-  free(ray); free(blo); free(bhi);
+  free(ray); free(blo); free(bhi); free(fylo); free(fyhi);
   return ORC_OK;
 }
 

@@ -593,9 +593,9 @@ def test_ray_certificate_closed_forms(oracle_mod):
 def test_dual_infeasibility_detected_on_toys(oracle_mod):
     """Random toys: status 6 exactly for those HiGHS calls unbounded, each
     with a ray that passes the exact check; 1 for the optimal ones; 5 for the
-    infeasible ones, or the attempt limit where the Farkas proof would need
-    (A'y)_j = 0 exactly on a column with an infinite bound on the needed side
-    (toy 480 of this stream: two free columns), never a wrong certificate."""
+    infeasible ones, with a returned y whose Farkas value is positive (toy 480
+    of this stream needs the certificate's repair: two single-entry columns
+    without a lower bound)."""
     from ray_check import is_ray
     rng = np.random.default_rng(11)
     seen = {}
@@ -604,13 +604,14 @@ def test_dual_infeasibility_detected_on_toys(oracle_mod):
         lp = ucgen.dense_to_lp(*ucgen.random_toy_lp(rng, m, n))
         st = exact.highs(lp)[0]
         x, y, info = oracle_mod.pdhg(lp, tol=1e-8, max_iter=100000)
-        want = {exact.OPTIMAL: (1,), exact.INFEASIBLE: (5, 2), exact.UNBOUNDED: (6,)}[st]
-        assert info["status"] in want, (t, st, info)
-        if info["status"] == 6:
+        want = {exact.OPTIMAL: 1, exact.INFEASIBLE: 5, exact.UNBOUNDED: 6}[st]
+        assert info["status"] == want, (t, st, info)
+        if want == 6:
             assert is_ray(lp, x), (t, x)
-        seen[info["status"]] = seen.get(info["status"], 0) + 1
+        if want == 5:
+            assert homogeneous_value(oracle_mod, lp, y) > 0.0, t
+        seen[want] = seen.get(want, 0) + 1
     assert seen.get(6, 0) >= 15 and seen.get(1, 0) >= 50 and seen.get(5, 0) >= 50, seen
-    assert seen.get(2, 0) <= 2, seen
 
 
 def test_ray_checker_hand_cases():
@@ -632,3 +633,34 @@ def test_ray_checker_hand_cases():
     assert is_ray(t3, np.array([0.0, 1.0])) and is_ray(t3, np.array([1.0, 1.0]))
     assert not is_ray(t3, np.array([2.0, 1.0]))          # c'd = 0: not improving
     assert not is_ray(t3, np.array([-0.5, 1.0]))         # x1 >= 0 decreasing
+
+
+def farkas_repair_toy():
+    """2 x3 = -5 with x3 in [-1, 2] cannot hold; -x1 + x2 + 4 x3 = 5 ties two
+    columns that have no lower bound (x1 <= 3, x2 <= 1) to the same row."""
+    INF = np.inf
+    return ucgen.dense_to_lp(np.array([[0.0, 0.0, 2.0], [-1.0, 1.0, 4.0]]),
+                             np.array([0, 0], np.uint8), np.array([-5.0, 5.0]),
+                             np.array([0.0, -2.0, -5.0]), np.array([-INF, -INF, -1.0]),
+                             np.array([3.0, 1.0, 2.0]))
+
+
+def test_farkas_repair_closed_form(oracle_mod):
+    """y = (-1, 0) proves the toy infeasible: b'y = 5 and lambda = -A'y =
+    (0, 0, 2) adds min(2 * -1, 2 * 2) = -2, so the value is 3 (less the
+    allowance).  Any y_2 != 0 gives -inf, since lambda_1 = y_2 and
+    lambda_2 = -y_2 then need a lower bound that x1 or x2 lacks.  The repair
+    intervals for c = 0 pin y_2 to 0 and leave y_1 free, and the oracle ends
+    with status 5 and a returned y whose value is positive."""
+    lp = farkas_repair_toy()
+    assert exact.highs(lp)[0] == exact.INFEASIBLE
+    v = homogeneous_value(oracle_mod, lp, np.array([-1.0, 0.0]))
+    assert 3.0 - 1e-13 <= v < 3.0
+    assert homogeneous_value(oracle_mod, lp, np.array([-1.0, 1e-6])) == -np.inf
+    q = lp.copy()
+    q.c = np.zeros(lp.n)
+    ylo, yhi = oracle_mod.bound_repair(q, lp.l, lp.u)
+    assert ylo[0] == -np.inf and yhi[0] == np.inf and ylo[1] == 0.0 and yhi[1] == 0.0
+    x, y, info = oracle_mod.pdhg(lp, tol=1e-8, max_iter=100000)
+    assert info["status"] == 5, info
+    assert y[1] == 0.0 and homogeneous_value(oracle_mod, lp, y) > 0.0
