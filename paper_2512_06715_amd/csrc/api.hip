@@ -154,6 +154,10 @@ struct pdhg_handle {
   // order) and host (caller's order, original units)
   double *rylo = nullptr, *ryhi = nullptr;
   std::vector<double> h_ylo, h_yhi;
+  // the same repair for c = 0 (the Farkas test): per row, bit 0 keeps y >= 0
+  // and bit 1 keeps y <= 0 (the intervals' ends are 0 or infinite)
+  uint8_t *fyk = nullptr;
+  std::vector<uint8_t> h_fyk;
   bool rep_valid = false;
   // c'x is bounded below on the implied box (setup's b, c): no direction of
   // its recession cone improves the objective, so the ray test is skipped
@@ -254,6 +258,7 @@ size_t layout(pdhg_handle *h, void *base) {
   h->ihi = cv.take<double>(n);
   h->rylo = cv.take<double>(m);
   h->ryhi = cv.take<double>(m);
+  h->fyk = cv.take<uint8_t>(m);
   if (mixed) {
     h->vf = cv.take<float>(nnz + 2);
     h->vtf = cv.take<float>(nnz + 2);
@@ -569,6 +574,14 @@ int setup_implied_bounds(pdhg_handle *h, const pdhg_lp *lp) {
   }
   repair_intervals(m, n, prp, pci, pv, pk, hc.data(), h->h_ilo.data(), h->h_ihi.data(), h->h_ylo,
                    h->h_yhi);
+  {
+    std::vector<double> zero(n, 0.0), flo, fhi;
+    repair_intervals(m, n, prp, pci, pv, pk, zero.data(), h->h_ilo.data(), h->h_ihi.data(), flo,
+                     fhi);
+    h->h_fyk.assign(m, 0);
+    for (int64_t i = 0; i < m; i++)
+      h->h_fyk[i] = (uint8_t)((flo[i] == 0.0 ? 1 : 0) | (fhi[i] == 0.0 ? 2 : 0));
+  }
   // every feasible x lies in the implied box, so every ray of the feasible
   // set lies in the box's recession cone; c'd >= 0 there when each term
   // c_j x_j is bounded below on [lo_j, hi_j]
@@ -612,6 +625,9 @@ int upload_implied_bounds(pdhg_handle *h) {
   }
   HC(hipMemcpyAsync(h->rylo, lo.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->hs));
   HC(hipMemcpyAsync(h->ryhi, hi.data(), sizeof(double) * m, hipMemcpyHostToDevice, h->hs));
+  std::vector<uint8_t> fk(m);
+  for (int64_t i = 0; i < m; i++) fk[i] = h->h_fyk[h->rperm ? h->h_rperm[i] : i];
+  HC(hipMemcpyAsync(h->fyk, fk.data(), m, hipMemcpyHostToDevice, h->hs));
   HC(hipStreamSynchronize(h->hs));  // the host arrays go out of scope; keep setup ordered
   h->impl_valid = true;
   h->rep_valid = true;
@@ -747,6 +763,7 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.ihi = h->impl_valid ? h->ihi : nullptr;
   e.rylo = h->rep_valid ? h->rylo : nullptr;
   e.ryhi = h->rep_valid ? h->ryhi : nullptr;
+  e.fyk = h->impl_valid ? h->fyk : nullptr;
   e.bound_allow = h->bound_allow;
   e.ybest = sizeof(T) == 4 ? b.Y[0] : nullptr;
   e.use_average = h->o.use_average;
@@ -1816,6 +1833,11 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
       i64[k].e.ilo = i64[k].e.ihi = nullptr;
       i32[k].e.ilo = i32[k].e.ihi = nullptr;
     }
+    // the Farkas intervals come from the base's box: a fixing can bound a
+    // column whose missing bound made one (a penalty slack fixed to 0), and
+    // the clamp would then zero the very duals a certificate needs, so such
+    // instances test y as it is
+    if (q.b || q.l || q.u || q.n_fix > 0) i64[k].e.fyk = i32[k].e.fyk = nullptr;
     i64[k].e.hold_k = i32[k].e.hold_k = q.hold_omega;  // weight held for these attempts
     if (q.b || q.c || q.l || q.u) {  // and its repair intervals those and its c
       i64[k].e.rylo = i64[k].e.ryhi = nullptr;

@@ -108,6 +108,7 @@ struct EvalView {
   // the dual bound's repair interval of each row (scaled, internal order);
   // null: no repair
   const double *rylo, *ryhi;
+  const uint8_t *fyk;            // Farkas repair per row: bit 0 y >= 0, bit 1 y <= 0 (nullable)
   double bound_allow;            // rounding allowance factor 2 (n + m + longest column + 4) 2^-53
   int use_average, restart;
   double pw_theta;               // 0 keeps the primal weight

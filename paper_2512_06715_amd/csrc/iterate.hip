@@ -674,6 +674,15 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_restart_rows(const Inst<T> *__re
 // projections stop changing, and a restart inside that phase makes d an
 // exact multiple of it.  Tested after the primal certificate.
 
+// y of the Farkas test: projected on >= rows, then clamped into the repair
+// interval for c = 0 (any such y is a candidate certificate)
+__device__ inline double farkas_y(double y, uint8_t kind, uint8_t fk) {
+  if (kind == 1 && y < 0.0) y = 0.0;
+  if (fk & 1) y = fmax(y, 0.0);
+  if (fk & 2) y = fmin(y, 0.0);
+  return y;
+}
+
 template <typename T>
 __device__ inline bool infeas_due(const EvalView<T> &e, const CtlState *st) {
   return e.infeas_period > 0 && !st->done && st->k > 0 && st->k % e.infeas_period == 0;
@@ -702,8 +711,8 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_rows(const Inst<T> *__res
   double s = 0.0;
   if (i < e.m) {
     ki = gin(e.kind)[i];
-    double yi = (double)gin((const T *)e.Y[st->cur])[i];
-    if (ki == 1 && yi < 0.0) yi = 0.0;
+    const double yi = farkas_y((double)gin((const T *)e.Y[st->cur])[i], ki,
+                               e.fyk ? gin(e.fyk)[i] : (uint8_t)0);
     double t = __dmul_rn(gin(e.b)[i], yi);
     q[0] = t;
     q[1] = fabs(t);
@@ -763,12 +772,12 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_cols(const Inst<T> *__res
     const AS_G double *vt = gin(e.vt);
     const AS_G T *y = gin((const T *)e.Y[st->cur]);
     const AS_G uint8_t *kind = gin(e.kind);
+    const AS_G uint8_t *fyk = e.fyk ? gin(e.fyk) : nullptr;
     const int a = cp[j], z = cp[j + 1];
     double s = 0.0, sa = 0.0;
     for (int k = a; k < z; k++) {
       const int32_t i = ri[k];
-      double yi = (double)y[i];
-      if (kind[i] == 1 && yi < 0.0) yi = 0.0;
+      const double yi = farkas_y((double)y[i], kind[i], fyk ? fyk[i] : (uint8_t)0);
       double pr = __dmul_rn(vt[k], yi);
       s += pr;
       sa += fabs(pr);
@@ -1064,6 +1073,8 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_unscale_rows(const Inst<T> *__re
   int64_t i = (int64_t)lb * PDHG_BLOCK + threadIdx.x;
   if (i >= e.m) return;
   double yv = st->which ? e.YA[i] : (double)e.Y[st->cur][i];
+  if (st->status == 5)  // the certificate itself: y as the Farkas test took it
+    yv = farkas_y(yv, e.kind[i], e.fyk ? e.fyk[i] : (uint8_t)0);
   I[inst].yout[e.rperm ? e.rperm[i] : i] = e.Dr[i] * yv;
 }
 

@@ -194,3 +194,22 @@ def test_unbounded_with_long_rows(gpu, oracle_mod, precision):
     assert info["status"] == 6, info
     assert is_ray(lp, x)
     print("attempts", info["attempts"], "oracle", io["attempts"], flush=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_farkas_repair_toy(gpu, oracle_mod, precision):
+    """An infeasible toy whose proof needs y_2 = 0 exactly (two single-entry
+    columns of row 2 lack a lower bound): the Farkas test clamps y into the
+    repair intervals for c = 0, ends with status 5 and returns that y, whose
+    value is positive, as in the oracle."""
+    from paper_2512_06715_amd.solver import Problem
+    from test_oracle_pins import farkas_repair_toy
+    lp = farkas_repair_toy()
+    print("case farkas repair toy", precision, flush=True)
+    xo, yo, io = oracle_mod.pdhg(lp, tol=1e-8, max_iter=100000)
+    assert io["status"] == 5
+    p = Problem(lp, tol=1e-8, precision=precision, max_iter=100000)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 5, info
+    assert y[1] == 0.0 and farkas_value(oracle_mod, lp, y) > 0.0, y
