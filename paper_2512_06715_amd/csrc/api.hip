@@ -763,7 +763,6 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.ihi = h->impl_valid ? h->ihi : nullptr;
   e.rylo = h->rep_valid ? h->rylo : nullptr;
   e.ryhi = h->rep_valid ? h->ryhi : nullptr;
-  e.fyk = h->impl_valid ? h->fyk : nullptr;
   e.bound_allow = h->bound_allow;
   e.ybest = sizeof(T) == 4 ? b.Y[0] : nullptr;
   e.use_average = h->o.use_average;
@@ -775,6 +774,7 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   I.st = b.st;
   I.x0 = I.y0 = nullptr;
   I.xout = I.yout = nullptr;
+  I.fyk = h->impl_valid ? h->fyk : nullptr;
 }
 
 template <typename T>
@@ -1837,7 +1837,7 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
     // column whose missing bound made one (a penalty slack fixed to 0), and
     // the clamp would then zero the very duals a certificate needs, so such
     // instances test y as it is
-    if (q.b || q.l || q.u || q.n_fix > 0) i64[k].e.fyk = i32[k].e.fyk = nullptr;
+    if (q.b || q.l || q.u || q.n_fix > 0) i64[k].fyk = i32[k].fyk = nullptr;
     i64[k].e.hold_k = i32[k].e.hold_k = q.hold_omega;  // weight held for these attempts
     if (q.b || q.c || q.l || q.u) {  // and its repair intervals those and its c
       i64[k].e.rylo = i64[k].e.ryhi = nullptr;

@@ -108,7 +108,6 @@ struct EvalView {
   // the dual bound's repair interval of each row (scaled, internal order);
   // null: no repair
   const double *rylo, *ryhi;
-  const uint8_t *fyk;            // Farkas repair per row: bit 0 y >= 0, bit 1 y <= 0 (nullable)
   double bound_allow;            // rounding allowance factor 2 (n + m + longest column + 4) 2^-53
   int use_average, restart;
   double pw_theta;               // 0 keeps the primal weight
@@ -183,6 +182,9 @@ struct Inst {
   CtlState *st;
   const double *x0, *y0;  // start point, original space (device) or null
   double *xout, *yout;    // unscaled result (device)
+  // Farkas repair per row, bit 0 y >= 0, bit 1 y <= 0 (nullable); last, so
+  // the fields the attempt kernels read keep their offsets
+  const uint8_t *fyk;
 };
 
 // Block-to-instance maps of a grouped launch: exclusive prefix sums of each

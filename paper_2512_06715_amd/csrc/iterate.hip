@@ -712,7 +712,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_rows(const Inst<T> *__res
   if (i < e.m) {
     ki = gin(e.kind)[i];
     const double yi = farkas_y((double)gin((const T *)e.Y[st->cur])[i], ki,
-                               e.fyk ? gin(e.fyk)[i] : (uint8_t)0);
+                               I[inst].fyk ? gin(I[inst].fyk)[i] : (uint8_t)0);
     double t = __dmul_rn(gin(e.b)[i], yi);
     q[0] = t;
     q[1] = fabs(t);
@@ -772,7 +772,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_infeas_cols(const Inst<T> *__res
     const AS_G double *vt = gin(e.vt);
     const AS_G T *y = gin((const T *)e.Y[st->cur]);
     const AS_G uint8_t *kind = gin(e.kind);
-    const AS_G uint8_t *fyk = e.fyk ? gin(e.fyk) : nullptr;
+    const AS_G uint8_t *fyk = I[inst].fyk ? gin(I[inst].fyk) : nullptr;
     const int a = cp[j], z = cp[j + 1];
     double s = 0.0, sa = 0.0;
     for (int k = a; k < z; k++) {
@@ -1074,7 +1074,7 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_unscale_rows(const Inst<T> *__re
   if (i >= e.m) return;
   double yv = st->which ? e.YA[i] : (double)e.Y[st->cur][i];
   if (st->status == 5)  // the certificate itself: y as the Farkas test took it
-    yv = farkas_y(yv, e.kind[i], e.fyk ? e.fyk[i] : (uint8_t)0);
+    yv = farkas_y(yv, e.kind[i], I[inst].fyk ? I[inst].fyk[i] : (uint8_t)0);
   I[inst].yout[e.rperm ? e.rperm[i] : i] = e.Dr[i] * yv;
 }
 
