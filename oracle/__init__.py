@@ -50,7 +50,12 @@ class _Opts(ctypes.Structure):
                 ("use_average", ctypes.c_int), ("omega0", ctypes.c_double),
                 ("pw_theta", ctypes.c_double), ("infeas_every", ctypes.c_int),
                 ("ilo", ctypes.c_void_p), ("ihi", ctypes.c_void_p),
-                ("dinf_eps", ctypes.c_double)]
+                ("dinf_eps", ctypes.c_double), ("trace", ctypes.c_void_p),
+                ("trace_cap", ctypes.c_int64)]
+
+# fields of one evaluation record of pdhg(..., trace=N)
+TRACE_FIELDS = ("k", "komega_cur", "komega_avg", "komega_last", "komega_prev", "restart",
+                "cand_avg", "omega", "komega_new")
 
 
 def lib():
@@ -205,17 +210,21 @@ def power_norm(m, n, row_ptr, col_idx, val, iters=50) -> float:
 
 
 INFO_FIELDS = ("status", "attempts", "accepted", "restarts", "pobj", "dobj", "rel_p",
-               "rel_d", "rel_gap", "rel_kkt", "eta", "omega", "which", "eta0", "omega0")
+               "rel_d", "rel_gap", "rel_kkt", "eta", "omega", "which", "eta0", "omega0",
+               "evaluations")
 
 
 def pdhg(lp, tol=1e-4, max_iter=100000, eval_period=64, step_mode=0, fixed_eta=0.0,
          ruiz_iters=10, pock_chambolle=True, restart=True, use_average=True,
-         omega0=0.0, pw_theta=0.5, x0=None, y0=None, infeas_every=4, dinf_eps=1e-8):
+         omega0=0.0, pw_theta=0.5, x0=None, y0=None, infeas_every=4, dinf_eps=1e-8,
+         trace=0):
     """Restarted PDHG in FP64.  Returns (x, y, info dict) in the original space.
     Every `infeas_every` evaluations (0: never) the current y is tested as a
     certificate of primal infeasibility over the implied bounds (status 5),
     then (dinf_eps > 0) the primal displacement since the last restart as a
-    ray certifying dual infeasibility (status 6; x is then the ray)."""
+    ray certifying dual infeasibility (status 6; x is then the ray).
+    trace > 0 adds info["trace"]: the first `trace` evaluations that reached
+    the restart decision, one dict of TRACE_FIELDS each."""
     a = _arrs(lp)
     ilo = ihi = None
     if infeas_every > 0:
@@ -224,6 +233,10 @@ def pdhg(lp, tol=1e-4, max_iter=100000, eval_period=64, step_mode=0, fixed_eta=0
               int(ruiz_iters), int(bool(pock_chambolle)), int(bool(restart)),
               int(bool(use_average)), float(omega0), float(pw_theta), int(infeas_every),
               _p(ilo), _p(ihi), float(dinf_eps))
+    tr = np.zeros((max(int(trace), 1), len(TRACE_FIELDS)))
+    if trace > 0:
+        o.trace = tr.ctypes.data_as(ctypes.c_void_p)
+        o.trace_cap = int(trace)
     x = np.zeros(lp.n)
     y = np.zeros(lp.m)
     info = np.zeros(len(INFO_FIELDS))
@@ -234,8 +247,10 @@ def pdhg(lp, tol=1e-4, max_iter=100000, eval_period=64, step_mode=0, fixed_eta=0
     if rc != 0:
         raise RuntimeError(f"oracle pdhg failed: {rc}")
     d = dict(zip(INFO_FIELDS, info.tolist()))
-    for k in ("status", "attempts", "accepted", "restarts", "which"):
+    for k in ("status", "attempts", "accepted", "restarts", "which", "evaluations"):
         d[k] = int(d[k])
+    if trace > 0:
+        d["trace"] = [dict(zip(TRACE_FIELDS, r)) for r in tr[:min(d["evaluations"], int(trace))]]
     return x, y, d
 
 

@@ -204,8 +204,12 @@ def simplex(lp, tol=1e-9, max_pivots=200000):
     return OPTIMAL, x, obj, yfull[:m0]
 
 
-def highs(lp):
-    """scipy.optimize.linprog(method='highs'): (status, x, objective, y)."""
+def highs(lp, method="highs"):
+    """scipy.optimize.linprog(method=...): (status, x, objective, y).
+
+    method is one of scipy's HiGHS front ends: 'highs' (HiGHS picks),
+    'highs-ds' (dual simplex) or 'highs-ipm' (interior point with crossover,
+    the faster one on LPs of millions of columns)."""
     from scipy.optimize import linprog
     import scipy.sparse as sp
     A = sp.csr_matrix((lp.val, lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n))
@@ -216,7 +220,7 @@ def highs(lp):
     if eq.any():
         kw.update(A_eq=A[eq], b_eq=lp.b[eq])
     bounds = list(zip(np.where(np.isinf(lp.l), None, lp.l), np.where(np.isinf(lp.u), None, lp.u)))
-    res = linprog(lp.c, bounds=bounds, method="highs", **kw)
+    res = linprog(lp.c, bounds=bounds, method=method, **kw)
     if res.status == 2:
         return INFEASIBLE, None, np.inf, None
     if res.status == 3:

@@ -315,12 +315,26 @@ typedef struct {
   double dinf_eps;     /* > 0: at the same evaluations, test the primal
                           displacement since the last restart as a ray
                           certifying dual infeasibility, with this tolerance */
+  double *trace;       /* nullable: one record of ORC_TRACE_LEN doubles per
+                          evaluation, at most trace_cap records (see below) */
+  int64_t trace_cap;
 } orc_opts;
+
+/* Evaluation trace (instrumentation only; it changes no arithmetic).  Record
+ * r of o->trace: [0] attempts k, [1] KKT_omega of the current iterate,
+ * [2] KKT_omega of the average (-1 without one), [3] KKT_omega of the last
+ * restart point and [4] the previous evaluation's candidate (both as the
+ * restart decision sees them; +inf when none), [5] 1 if the evaluation
+ * restarted, [6] 1 if the candidate was the average, [7] omega after the
+ * evaluation, [8] KKT_omega of the new restart point (the reference of the
+ * next decisions; -1 without a restart).  Records past trace_cap are
+ * dropped; info[15] counts all of them. */
+#define ORC_TRACE_LEN 9
 
 /* info: [0] status [1] attempts [2] accepted [3] restarts [4] pobj [5] dobj
  *       [6] rel_p [7] rel_d [8] rel_gap [9] rel_kkt [10] eta [11] omega
  *       [12] returned point (0 current, 1 average) [13] initial eta
- *       [14] initial omega */
+ *       [14] initial omega [15] evaluation records (the trace below) */
 
 typedef struct {
   int64_t m, n;
@@ -589,6 +603,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   int64_t k = 0, accepted = 0, restarts = 0, last_restart = 0;
   int status = 0, which = 0;
   int P_eval = o->eval_period > 0 ? o->eval_period : 64;
+  int64_t ntrace = 0;
 
   for (;;) {
     if (k % P_eval == 0 || k >= o->max_iter) {
@@ -639,6 +654,19 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
         break;
       }
       /* ---- restart decision on the scaled KKT_omega ---- */
+      double *rec = (o->trace && ntrace < o->trace_cap) ? o->trace + ORC_TRACE_LEN * ntrace : NULL;
+      ntrace++;
+      if (rec) {
+        rec[0] = (double)k;
+        rec[1] = ev[0];
+        rec[2] = have_avg ? eva[0] : -1.0;
+        rec[3] = kkt_last;
+        rec[4] = kkt_prev;
+        rec[5] = 0.0;
+        rec[6] = 0.0;
+        rec[7] = omega;
+        rec[8] = -1.0;
+      }
       if (o->restart && k > 0) {
         int cand_avg = have_avg && eva[0] < ev[0];
         double kc = cand_avg ? eva[0] : ev[0];
@@ -646,6 +674,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
                          (kc <= 0.8 * kkt_last && kc > kkt_prev) ||
                          ((double)(k - last_restart) >= 0.36 * (double)k);
         kkt_prev = kc;
+        if (rec) rec[6] = cand_avg;
         if (do_restart) {
           if (cand_avg) {
             memcpy(x, xa, N8);
@@ -668,6 +697,11 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
           wsum = 0.0;
           last_restart = k;
           restarts++;
+          if (rec) {
+            rec[5] = 1.0;
+            rec[7] = omega;
+            rec[8] = kkt_last;
+          }
         }
       }
     }
@@ -741,6 +775,7 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
   info[10] = eta;
   info[11] = omega;
   info[12] = which;
+  info[15] = (double)ntrace;
 
   free(v); free(Dr); free(Dc); free(cp); free(ri); free(vt);
   free(b); free(c); free(l); free(u); free(vk);

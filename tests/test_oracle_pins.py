@@ -112,6 +112,20 @@ def test_scaling_is_exact_power_of_two_equilibration(oracle_mod):
     assert np.abs(lp.val).max() / np.abs(lp.val).min() > 1e3
 
 
+def test_scaling_hand_example(oracle_mod):
+    """One Ruiz pass and one Pock-Chambolle pass on a 3x3 matrix, factors
+    worked by hand (tests/golden/scaling.json); a max in place of the
+    Pock-Chambolle sum, or rows and columns swapped, fail it."""
+    g = load_golden("scaling.json")
+    A = np.array(g["A"])
+    lp = ucgen.dense_to_lp(A, np.zeros(3, np.uint8), np.ones(3), np.ones(3), np.zeros(3),
+                           np.ones(3))
+    for e in g["expected"]:
+        vs, Dr, Dc = oracle_mod.scale(lp, e["ruiz"], e["pock_chambolle"])
+        assert vs.tolist() == e["val_csr"], e
+        assert Dr.tolist() == e["Dr"] and Dc.tolist() == e["Dc"], e
+
+
 def test_var_kind_table(oracle_mod):
     inf = np.inf
     l = np.array([-inf, 0.0, -inf, -1.0, 2.0, 0.0])
@@ -245,6 +259,101 @@ def test_one_step_hand_example(oracle_mod):
                                      fixed_eta=g["eta"], omega0=g["omega"], ruiz_iters=0,
                                      pock_chambolle=False, restart=False)
         assert x.tolist() == exp["x"] and y.tolist() == exp["y"], (k, x, y)
+
+
+def golden_lp(g):
+    L = g["lp"]
+    inf = lambda a: np.array([np.inf if v == "inf" else v for v in a], float)
+    return ucgen.dense_to_lp(np.array(L["A"]), np.array(L["row_kind"], np.uint8),
+                             np.array(L["b"]), np.array(L["c"]), inf(L["l"]), inf(L["u"]))
+
+
+def test_adaptive_step_hand_example(oracle_mod):
+    """Five adaptive attempts worked by hand (tests/golden/adaptive_step.json):
+    the step-size limit, accept/reject (attempt 3 is rejected), both terms of
+    the step update and the (k+1) count starting at 2.  A swapped exponent,
+    k in place of k+1 or a non-strict test fail it."""
+    g = load_golden("adaptive_step.json")
+    lp = golden_lp(g)
+    for k, e in g["expected"].items():
+        x, y, info = oracle_mod.pdhg(lp, tol=1e-14, max_iter=int(k), step_mode=0,
+                                     omega0=g["options"]["omega"], ruiz_iters=0,
+                                     pock_chambolle=False, restart=False, infeas_every=0)
+        assert info["attempts"] == int(k)
+        assert info["accepted"] == e["accepted"], (k, info)
+        assert info["eta0"] == 0.5
+        assert abs(info["eta"] - e["eta"]) <= 1e-14 * e["eta"], (k, info["eta"], e["eta"])
+        np.testing.assert_allclose(x, e["x"], rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(y, e["y"], rtol=1e-14, atol=1e-15)
+    # a tie: the first attempt's step equals its limit and is accepted
+    t = g["tie"]
+    lp = golden_lp(t)
+    x, y, info = oracle_mod.pdhg(lp, tol=1e-14, max_iter=1, step_mode=0, omega0=1.0,
+                                 ruiz_iters=0, pock_chambolle=False, restart=False,
+                                 infeas_every=0)
+    assert info["eta0"] == 1.0 and info["accepted"] == 1
+    assert info["eta"] == t["expected"]["eta"]
+    assert x.tolist() == t["expected"]["x"] and y.tolist() == t["expected"]["y"]
+    # the eta-weighted average of the accepted iterates, seen at an evaluation
+    a = g["average"]
+    lp = golden_lp(g)
+    _, _, info = oracle_mod.pdhg(lp, tol=1e-14, max_iter=a["eval_period"] + 1,
+                                 eval_period=a["eval_period"], step_mode=0, omega0=1.0,
+                                 ruiz_iters=0, pock_chambolle=False, infeas_every=0, trace=4)
+    rec = info["trace"][1]
+    assert rec["k"] == a["eval_period"]
+    assert abs(rec["komega_cur"] - a["komega_cur"]) <= 1e-13 * a["komega_cur"]
+    assert abs(rec["komega_avg"] - a["komega_avg"]) <= 1e-13 * a["komega_avg"]
+
+
+def test_restart_rule_hand_example(oracle_mod):
+    """Nine constant-step attempts with an evaluation after each
+    (tests/golden/restart_rule.json): the artificial criterion restarts at
+    k = 1, 2 and 5, the 0.2 criterion alone at k = 3, the 0.8 criterion alone
+    at k = 7 (to the average), and the primal weight follows the theta = 0.5
+    update (skipped at k = 1, where x did not move).  Every evaluation's
+    KKT_omega values, the reference of the last restart and the decision are
+    compared."""
+    g = load_golden("restart_rule.json")
+    lp = golden_lp(g)
+    o = g["options"]
+    x, y, info = oracle_mod.pdhg(lp, tol=1e-14, max_iter=o["attempts"], eval_period=1,
+                                 step_mode=1, fixed_eta=o["eta"], omega0=o["omega0"],
+                                 ruiz_iters=0, pock_chambolle=False, pw_theta=o["pw_theta"],
+                                 infeas_every=0, trace=32)
+    close = lambda a, b: abs(a - b) <= 1e-12 * max(1.0, abs(b))
+    tr = info["trace"]
+    assert len(tr) == len(g["evaluations"])
+    for rec, e in zip(tr, g["evaluations"]):
+        assert rec["k"] == e["k"]
+        assert close(rec["komega_cur"], e["komega_cur"]), (e["k"], rec, e)
+        assert close(rec["komega_avg"], e["komega_avg"]), (e["k"], rec, e)
+        assert close(rec["komega_last"], e["komega_last"]), (e["k"], rec, e)
+        if e["komega_prev"] == "inf":
+            assert rec["komega_prev"] == np.inf, (e["k"], rec, e)
+        else:
+            assert close(rec["komega_prev"], e["komega_prev"]), (e["k"], rec, e)
+        if e["k"] == 0:
+            assert rec["restart"] == 0
+            continue
+        assert rec["restart"] == (1.0 if e["restart"] else 0.0), (e["k"], rec, e)
+        assert rec["cand_avg"] == (1.0 if e["candidate"] == "avg" else 0.0), (e["k"], rec, e)
+        assert close(rec["omega"], e["omega_after"]), (e["k"], rec, e)
+        if e["restart"]:
+            assert close(rec["komega_new"], e["komega_new"]), (e["k"], rec, e)
+    f = g["final"]
+    assert info["restarts"] == f["restarts"]
+    assert close(info["omega"], f["omega"])
+    np.testing.assert_allclose(x, f["x"], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(y, f["y"], rtol=1e-12, atol=1e-14)
+    # restart counts after each attempt (the decision at the last evaluation
+    # is not taken: the attempt limit ends the solve first)
+    counts = [0, 0, 1, 2, 3, 3, 4, 4, 5, 5]
+    for K in range(1, o["attempts"] + 1):
+        _, _, ik = oracle_mod.pdhg(lp, tol=1e-14, max_iter=K, eval_period=1, step_mode=1,
+                                   fixed_eta=o["eta"], omega0=o["omega0"], ruiz_iters=0,
+                                   pock_chambolle=False, infeas_every=0)
+        assert ik["restarts"] == counts[K], (K, ik)
 
 
 def test_pdhg_matches_enumeration_on_toys(oracle_mod):
