@@ -24,8 +24,15 @@
  *
  * Memory: the library never allocates device memory.  The caller passes a
  * device workspace (size from pdhg_workspace_bytes) that must stay alive
- * until pdhg_destroy.  All device work is queued on the stream given to
- * pdhg_setup (0 = the null stream).
+ * until pdhg_destroy.  pdhg_setup creates one pinned host record of the
+ * control state per handle (hipHostMalloc).
+ *
+ * Streams: each handle runs its device work on a stream of its own
+ * (non-blocking, default priority) created by pdhg_setup.  Every call orders
+ * that work after what the caller queued on the stream given to pdhg_setup
+ * (0 = the null stream) by recording an event there and waiting on it, and
+ * before anything the caller queues there afterwards by the reverse.  Calls
+ * that return results in host memory synchronize before they return.
  */
 #ifndef PDHG_H
 #define PDHG_H
@@ -101,7 +108,8 @@ typedef struct {
   int64_t unroll_iters;   /* > 0: unrolled fixed-step mode with this many steps */
   int64_t checkpoint_every; /* unrolled mode: checkpoint period (default 50) */
   int use_graph;          /* 1 (default): replay iteration blocks as HIP graphs */
-  int verbose;            /* 1: one log line per evaluation on stderr */
+  int verbose;            /* 1: one log line per evaluation on stderr (a batch: one line
+                             per 64 evaluations with the instances still running) */
   double polish_tol;      /* mixed precision: FP32 phase stops at this KKT (default tol) */
   int pw_update;          /* 1 (default): primal weight updated at restarts; 0: kept */
   double pw_theta;        /* smoothing of the primal-weight update in log space (default 0.5) */
@@ -277,8 +285,10 @@ int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out);
 
 /* The implied bounds pdhg_setup derived for the dual bound (host memory,
  * caller's order, original units): lo[n], hi[n] are l, u with infinite ends
- * replaced where propagation over the rows bounds them (widened by
- * 1e-9 (1 + |bound|)).  After pdhg_update with a new b they no longer apply
+ * replaced where propagation over the rows bounds them, each widened by
+ * more than its rounding: r -+ (2 (len + 2) 2^-53 (|b_i| + sum_k |a_ik bound_k|)
+ * / |a_ij| + 4 2^-53 |r|) for a bound r derived from row i of len entries,
+ * and no bound where that is not finite.  After pdhg_update with a new b they no longer apply
  * and this returns l, u. */
 int pdhg_implied_bounds(pdhg_handle *h, double *lo, double *hi);
 

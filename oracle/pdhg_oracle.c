@@ -876,46 +876,62 @@ int orc_unrolled(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
  * at the ends of their current bounds, each row bounds each of its
  * variables.  Sweeps run over the rows in index order and use bounds found
  * earlier in the same sweep.  Only infinite bounds are replaced, and a
- * derived bound r/a is widened to r/a -+ 1e-9 (1 + |r/a|) to cover its
- * rounding.  lo, hi: in the bounds l, u; out the implied bounds.  Returns
+ * derived bound r = (b_i - sum over the others of t_k) / a_j is widened to
+ * r -+ w with w = 2 (len + 2) 2^-53 (|b_i| + sum |t_k|) / |a_j| + 4 2^-53 |r|
+ * (len = the row's entries, t_k the finite activity terms), which exceeds
+ * the rounding of r even where the terms cancel; a non-finite r or w gives
+ * no bound.  lo, hi: in the bounds l, u; out the implied bounds.  Returns
  * the number of bounds made finite. */
 int64_t orc_implied_bounds(int64_t m, int64_t n, const int32_t *rp, const int32_t *ci,
                            const double *v, const uint8_t *kind, const double *b,
                            int passes, double *lo, double *hi) {
+  const double eps = ldexp(1.0, -53);
   int64_t made = 0;
   (void)n;
   for (int pass = 0; pass < passes; pass++) {
     int64_t before = made;
     for (int64_t i = 0; i < m; i++) {
-      /* activity bounds of row i: finite parts and counts of infinite terms */
-      double minf = 0.0, maxf = 0.0;
+      /* activity bounds of row i: finite parts, their magnitudes and counts of
+       * infinite terms */
+      double minf = 0.0, maxf = 0.0, mina = 0.0, maxa = 0.0;
       int64_t mininf = 0, maxinf = 0;
+      const int64_t len = rp[i + 1] - rp[i];
       for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
         double a = v[k], L = lo[ci[k]], U = hi[ci[k]];
         double tmin = a > 0.0 ? a * L : a * U, tmax = a > 0.0 ? a * U : a * L;
-        if (isinf(tmin)) mininf++; else minf += tmin;
-        if (isinf(tmax)) maxinf++; else maxf += tmax;
+        if (isinf(tmin)) mininf++; else { minf += tmin; mina += fabs(tmin); }
+        if (isinf(tmax)) maxinf++; else { maxf += tmax; maxa += fabs(tmax); }
       }
       for (int32_t k = rp[i]; k < rp[i + 1]; k++) {
         int32_t j = ci[k];
         double a = v[k], L = lo[j], U = hi[j];
         if (a == 0.0) continue;
         double tmin = a > 0.0 ? a * L : a * U, tmax = a > 0.0 ? a * U : a * L;
-        /* a'x >= b: a_j x_j >= b - (max activity of the others) */
+        /* a'x >= b: a_j x_j >= b - (max activity of the others).  The
+         * computed r carries the rounding of the products, the row sum, the
+         * removal of the own term, the subtraction from b and the division:
+         * below 2 (len + 2) 2^-53 (|b_i| + sum |t_k|) / |a_j| + 2^-53 |r|;
+         * w exceeds it, and 4 2^-53 |r| also covers the rounding of r -+ w */
         int64_t oinf = maxinf - (isinf(tmax) ? 1 : 0);
         if (oinf == 0) {
           double r = (b[i] - (maxf - (isinf(tmax) ? 0.0 : tmax))) / a;
-          double w = 1e-9 * (1.0 + fabs(r));
-          if (a > 0.0 && isinf(lo[j])) { lo[j] = r - w; made++; }
-          if (a < 0.0 && isinf(hi[j])) { hi[j] = r + w; made++; }
+          double w = 2.0 * (double)(len + 2) * eps * (fabs(b[i]) + maxa) / fabs(a) +
+                     4.0 * eps * fabs(r);
+          if (isfinite(r) && isfinite(w)) {
+            if (a > 0.0 && isinf(lo[j])) { lo[j] = r - w; made++; }
+            if (a < 0.0 && isinf(hi[j])) { hi[j] = r + w; made++; }
+          }
         }
         if (kind[i] == 0) { /* a'x <= b: a_j x_j <= b - (min activity of the others) */
           int64_t oinf2 = mininf - (isinf(tmin) ? 1 : 0);
           if (oinf2 == 0) {
             double r = (b[i] - (minf - (isinf(tmin) ? 0.0 : tmin))) / a;
-            double w = 1e-9 * (1.0 + fabs(r));
-            if (a > 0.0 && isinf(hi[j])) { hi[j] = r + w; made++; }
-            if (a < 0.0 && isinf(lo[j])) { lo[j] = r - w; made++; }
+            double w = 2.0 * (double)(len + 2) * eps * (fabs(b[i]) + mina) / fabs(a) +
+                       4.0 * eps * fabs(r);
+            if (isfinite(r) && isfinite(w)) {
+              if (a > 0.0 && isinf(hi[j])) { hi[j] = r + w; made++; }
+              if (a < 0.0 && isinf(lo[j])) { lo[j] = r - w; made++; }
+            }
           }
         }
       }

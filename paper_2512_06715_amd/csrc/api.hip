@@ -931,6 +931,7 @@ int run_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
   const bool fp32 = sizeof(T) == 4;
   std::vector<double> best(all.size(), INFINITY), first(all.size(), INFINITY);
   std::vector<int> since(all.size(), 0);
+  long long evals = 0;
   Groups g{};
   int version = reuse_graph ? gs.version : gs.version + 1;
   RC(upload_group<T>(h, gd, all, active, g));
@@ -973,6 +974,12 @@ int run_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
       }
       still.push_back(i);
       kmin = std::min<int64_t>(kmin, s.k);
+    }
+    if (h->o.verbose && active.size() > 1 && !still.empty() && ++evals % 64 == 0) {
+      double worst = 0.0;
+      for (int i : still) worst = std::max(worst, final_state[i].rel_kkt);
+      fprintf(stderr, "pdhg batch: %d of %zu instances running, fewest attempts %lld, largest kkt %.3e\n",
+              (int)still.size(), all.size(), (long long)kmin, worst);
     }
     if (still.empty()) break;
     if (still.size() != active.size()) {

@@ -5,6 +5,17 @@ import numpy as np
 from paper_2512_06715_amd import ucgen
 
 
+def cancelling_row():
+    """x1 + x2 + 1e-6 x3 >= 1e8 with x1 <= 1e8, x2 <= 7e-9, x3 free below,
+    min x3: the row sum 1e8 + 7e-9 rounds to 1e8, so the computed r of x3's
+    implied lower bound is 0 while x = (1e8, 7e-9, -7e-3) is feasible; the
+    optimum is -7e-3."""
+    A = np.array([[1.0, 1.0, 1e-6]])
+    return ucgen.dense_to_lp(A, np.array([1], np.uint8), np.array([1e8]),
+                             np.array([0.0, 0.0, 1.0]), np.array([0.0, 0.0, -np.inf]),
+                             np.array([1e8, 7e-9, np.inf]))
+
+
 def one_by_one():
     """min x  s.t.  x >= 1,  0 <= x <= 5."""
     return ucgen.dense_to_lp(np.array([[1.0]]), np.array([1], np.uint8), np.array([1.0]),

@@ -97,3 +97,168 @@ def test_autograd_load_and_cost(gpu, oracle_mod):
     assert abs(lhs - dVo) <= 1e-9 * (1 + abs(dVo))
     assert abs(float(V.detach()) - Vo) <= 1e-10 * (1 + abs(Vo))
     p.close()
+
+
+@pytest.mark.parametrize("part", [dict(long_seg=4, tiles_per_block=2),
+                                  dict(long_seg=8, spmv_direct=1)])
+def test_adjoint_long_segments(gpu, oracle_mod, part):
+    """With a low long-row threshold the rows and columns above it take the
+    workgroup-per-segment paths of the forward attempt (mask bits recorded one
+    by one) and of the reverse sweep; the gradient still matches the oracle's
+    forward-mode derivative."""
+    lp = ucgen.random_uc(14, 5, 20, 24, 1.0, seed=9)
+    K, C = 300, 40
+    print("case adjoint long segments", part, flush=True)
+    from paper_2512_06715_amd.solver import Problem
+    eta, omega = oracle_mod.unrolled_step(lp)
+    p = Problem(lp, unroll_iters=K, checkpoint_every=C, fixed_eta=eta, fixed_omega=omega, **part)
+    assert p.partition()["long_segments"] > 0
+    x, y, info = p.solve()
+    gb, gc = p.backward(1.0)
+    p.close()
+    rng = np.random.default_rng(4)
+    for trial in range(2):
+        db = rng.standard_normal(lp.m)
+        dc = rng.standard_normal(lp.n)
+        V, dV = oracle_mod.unrolled(lp, K, eta, omega, db, dc)
+        assert abs(gb @ db + gc @ dc - dV) <= 1e-9 * (1 + abs(dV)), (trial, dV)
+    assert abs(info["primal_obj"] - V) <= 1e-10 * (1 + abs(V))
+
+
+@pytest.fixture(scope="module")
+def uc2000():
+    return ucgen.workload("uc2000_t24")
+
+
+def test_config4_step_and_dot_products(gpu, oracle_mod, uc2000):
+    """The differentiable workload (2000 buses, 24 periods, K = 1000 unrolled
+    steps, checkpoints every 50) with the GPU's own step size: eta from its
+    power iteration equals the oracle's 0.9/||A^||_2, and the reverse sweep
+    is the transpose of the oracle's forward-mode derivative in three random
+    directions.  The 601-entry reserve rows take the long-row paths."""
+    from paper_2512_06715_amd.solver import Problem
+    lp = uc2000
+    K, C = 1000, 50
+    print("case config4 dot products", flush=True)
+    p = Problem(lp, unroll_iters=K, checkpoint_every=C)
+    assert p.partition()["long_segments"] > 0
+    x, y, info = p.solve()
+    gb, gc = p.backward(1.0)
+    p.close()
+    eta_o, omega_o = oracle_mod.unrolled_step(lp)
+    print("eta gpu", info["eta"], "oracle", eta_o, "omega", info["omega"], omega_o, flush=True)
+    assert abs(info["eta"] - eta_o) <= 1e-12 * eta_o
+    assert abs(info["omega"] - omega_o) <= 1e-14 * omega_o
+    eta, omega = info["eta"], info["omega"]
+    rng = np.random.default_rng(40)
+    for trial in range(3):
+        db = rng.standard_normal(lp.m)
+        dc = rng.standard_normal(lp.n)
+        V, dV = oracle_mod.unrolled(lp, K, eta, omega, db, dc)
+        lhs = gb @ db + gc @ dc
+        print("direction", trial, "gpu", lhs, "oracle", dV, flush=True)
+        assert abs(lhs - dV) <= 1e-9 * (1 + abs(dV)), (trial, lhs, dV)
+    assert abs(info["primal_obj"] - V) <= 1e-10 * (1 + abs(V))
+
+
+def test_config4_finite_differences_and_prices(gpu, oracle_mod, uc2000):
+    """Central differences of the GPU's unrolled map (h = 1e-4 |value|) on 50
+    random nodal loads and 50 random per-(unit, period) energy costs against
+    the adjoint.  For fixed projection masks the map is affine in b and
+    quadratic in c, and a central difference of either is exact up to
+    rounding.  A coordinate along which some mask flips within +-h is found by
+    sampling V at +-h/2 as well: the map is affine (loads) or quadratic
+    (costs) on [-h, h] only if both central differences and both curvature
+    estimates agree.  The flip-free coordinates must match the adjoint; the
+    fraction with a flip is reported.  The load gradient is then set against
+    the nodal prices y_bal + 0.05 y_res of the converged LP (the envelope
+    theorem), reported with no bar: 1000 steps are far from the optimum."""
+    from paper_2512_06715_amd.autograd import UCMaps
+    from paper_2512_06715_amd.solver import Problem
+    lp = uc2000
+    K, C = 1000, 50
+    maps = UCMaps(lp)
+    print("case config4 finite differences", flush=True)
+    # the step size and primal weight of the unperturbed problem, held fixed
+    # (an update of b or c would otherwise recompute the weight ||c^||/||b^||,
+    # which the adjoint treats as a constant)
+    p = Problem(lp, unroll_iters=K, checkpoint_every=C)
+    _, _, info = p.solve()
+    p.close()
+    p = Problem(lp, unroll_iters=K, checkpoint_every=C, fixed_eta=info["eta"],
+                fixed_omega=info["omega"])
+    _, _, info = p.solve()
+    V0 = info["primal_obj"]
+    gb, gc = p.backward(1.0)
+    gload, _ = maps.grads(gb, gc)
+    load = np.asarray(lp.meta["load"], float)
+    N, T = load.shape
+    cost = np.asarray(lp.meta["gen_cost"], float)
+    rng = np.random.default_rng(40)
+    li = rng.choice(N * T, size=50, replace=False)
+    cj = rng.choice(maps.pcols.ravel(), size=50, replace=False)
+
+    def value(b, c):
+        p.update(b, c)
+        _, _, inf = p.solve()
+        return inf["primal_obj"]
+
+    rows = []
+    for q in li:
+        i, t = divmod(int(q), T)
+        h = 1e-4 * abs(load[i, t])
+        vals = []
+        for s in (1, -1, 0.5, -0.5):
+            L = load.copy()
+            L[i, t] += s * h
+            b, _ = maps.to_bc(L, cost)
+            vals.append(value(b, lp.c))
+        rows.append(("load", vals, gload[i, t], h))
+    for j in cj:
+        h = 1e-4 * abs(lp.c[j])
+        vals = []
+        for s in (1, -1, 0.5, -0.5):
+            c = lp.c.copy()
+            c[j] += s * h
+            vals.append(value(lp.b, c))
+        rows.append(("cost", vals, gc[j], h))
+    p.close()
+    # Rounding: V is computed to within a few units of 2^-53 |V| (measured on
+    # this map: residuals of V against its affine model up to 2.8 2^-53 |V|),
+    # so ev = 4 2^-53 |V| bounds the error of one value.  Detection: with a
+    # single kink at s_k in (0, h] and slope change d, the central difference
+    # over h is off by d (h - s_k) / 2h, while fd - fd(h/2) is d s_k / 2h (or
+    # all of the error when s_k >= h/2) and h/2 (k1 - k2) is d (h - 3 s_k) / 2h;
+    # the error is at most 3 times the larger of these, so with a detection
+    # threshold T = 4.5 ev / h (above their rounding, 3 ev / h) the error of an
+    # undetected kink stays below 13.5 ev / h, and the bar is
+    # 1e-6 (1 + |g|) + 15 ev / h.
+    u = 2.0 ** -53
+    flips, worst, bad = 0, 0.0, []
+    for kind, (vp, vm, vp2, vm2), g, h in rows:
+        ev = 4 * u * abs(V0)
+        T = 4.5 * ev / h
+        fd, fd2 = (vp - vm) / (2 * h), (vp2 - vm2) / h
+        k1, k2 = (vp + vm - 2 * V0) / h ** 2, (vp2 + vm2 - 2 * V0) / (h / 2) ** 2
+        if abs(fd - fd2) > T or abs(k1 - k2) * h / 2 > T:
+            flips += 1
+            continue
+        err = abs(fd - g)
+        bar = 1e-6 * (1 + abs(g)) + 15 * ev / h
+        worst = max(worst, err / bar)
+        if err > bar:
+            bad.append((kind, fd, g, h))
+    print(f"FD: {len(rows)} coordinates, {flips} with a mask flip within +-h; worst error on "
+          f"the others {worst:.3f} of the bar", flush=True)
+    assert not bad, bad
+    assert flips <= len(rows) * 3 // 4
+    # envelope check against the converged nodal prices (reported only)
+    q = Problem(lp, tol=1e-5, max_iter=3000000)
+    _, y, inf2 = q.solve()
+    q.close()
+    assert inf2["status"] == 1
+    price = y[maps.bal.T] + maps.rf * y[maps.res][None, :]
+    rel = np.linalg.norm(gload - price) / np.linalg.norm(price)
+    corr = np.corrcoef(gload.ravel(), price.ravel())[0, 1]
+    print(f"dV/dD after {K} steps vs converged nodal prices: relative difference {rel:.3e}, "
+          f"correlation {corr:.4f}; converged objective {inf2['primal_obj']:.10g}", flush=True)

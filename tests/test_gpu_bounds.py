@@ -10,12 +10,13 @@ pytestmark = pytest.mark.gpu
 
 
 def lps():
+    from edge_lps import cancelling_row
     from test_gpu_parity import dense_column_lp
     return {"uc14_t24": ucgen.workload("uc14_t24"), "dense_cols": dense_column_lp(),
-            "uc1000_t48": ucgen.workload("uc1000_t48")}
+            "uc1000_t48": ucgen.workload("uc1000_t48"), "cancelling_row": cancelling_row()}
 
 
-@pytest.mark.parametrize("name", ["uc14_t24", "dense_cols", "uc1000_t48"])
+@pytest.mark.parametrize("name", ["uc14_t24", "dense_cols", "uc1000_t48", "cancelling_row"])
 def test_implied_bounds_match_oracle(gpu, oracle_mod, name):
     from paper_2512_06715_amd.solver import Problem, implied_bounds
     lp = lps()[name]
@@ -26,6 +27,23 @@ def test_implied_bounds_match_oracle(gpu, oracle_mod, name):
     olo, ohi = oracle_mod.implied_bounds(lp)
     assert np.array_equal(lo.view(np.uint64), olo.view(np.uint64))
     assert np.array_equal(hi.view(np.uint64), ohi.view(np.uint64))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_dual_bound_with_cancelling_row(gpu, oracle_mod, precision):
+    """The implied bound of x3 admits every feasible point although its row
+    sum cancels, so the reported bound stays below the optimum -7e-3 (closed
+    form) at any accuracy."""
+    from paper_2512_06715_amd.solver import Problem, implied_bounds
+    lp = lps()["cancelling_row"]
+    print("case cancelling row", precision, flush=True)
+    for iters in (1, 64, 100000):
+        p = Problem(lp, tol=1e-6, precision=precision, max_iter=iters)
+        x, y, info = p.solve()
+        lo, hi = implied_bounds(p)
+        p.close()
+        assert lo[2] <= -7e-3
+        assert info["dual_bound"] <= -7e-3, (iters, info)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -51,14 +51,15 @@ def test_fullsize_setup_bit_exact(gpu, oracle_mod, lp):
     assert np.array_equal(g["valT"].view(np.uint64), vt.view(np.uint64))
 
 
-@pytest.mark.parametrize("K,bound", [(1, 1e-12), (48, 1e-9)])
+@pytest.mark.parametrize("K,bound", [(1, 1e-12), (48, 3e-8)])
 def test_fullsize_trajectory_fp64(gpu, oracle_mod, lp, K, bound):
-    """K FP64 attempts from the origin against the oracle's.  The step-size
-    test divides by dy'(A dx), a sum over 2M rows with heavy cancellation
-    whose value depends on the summation order (a tree here, a sequential
-    loop in the oracle); measured at this size, eta differs in the 12th digit
-    after 8 attempts and x, y by 2e-14 after 1, 4e-12 after 32, 2e-11 after
-    48 and 2e-9 after 64 attempts, with or without the locality ordering."""
+    """K FP64 attempts from the origin against the oracle's, entry by entry:
+    |x_j - xo_j| <= bound (1 + |xo_j|), the same for y.  The step-size test
+    divides by dy'(A dx), a sum over 2M rows with heavy cancellation whose
+    value depends on the summation order (a tree here, a sequential loop in
+    the oracle); measured at this size, the worst entry differs by 2.0e-14
+    after 1 attempt and 3.4e-9 after 48 (a dual entry; the primal entries
+    4.4e-10)."""
     from paper_2512_06715_amd.solver import Problem
     print("case uc6717_t96", K, "attempts", flush=True)
     p = Problem(device_lp(lp), device=True, max_iter=K, tol=1e-12)
@@ -68,9 +69,10 @@ def test_fullsize_trajectory_fp64(gpu, oracle_mod, lp, K, bound):
     xo, yo, io = oracle_mod.pdhg(lp, tol=1e-12, max_iter=K)
     assert info["attempts"] == io["attempts"] == K
     assert info["accepted"] == io["accepted"]
-    scale = 1 + np.linalg.norm(xo) + np.linalg.norm(yo)
-    err = np.linalg.norm(x - xo) + np.linalg.norm(y - yo)
-    assert err <= bound * scale, err / scale
+    for name, a, ref in (("x", x, xo), ("y", y, yo)):
+        err = np.abs(a - ref) / (1 + np.abs(ref))
+        j = int(np.argmax(err))
+        assert err[j] <= bound, (name, j, a[j], ref[j], err[j])
 
 
 def test_fullsize_mixed_solve(gpu, oracle_mod, lp):

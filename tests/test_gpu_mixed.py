@@ -25,10 +25,12 @@ def test_mixed_small_uc(gpu, oracle_mod, tol):
     assert info["status"] == 1, info
     k = oracle_mod.kkt(lp, x, y)
     assert k["rel_kkt"] <= tol * 1.001, k
-    # a relative KKT error of 1e-7 does not bound the objective's error to
-    # 1e-6 (the primal residual is relative to 1 + ||b||); measured up to
-    # 4.5e-6 at 1e-7, so the objective is held to max(10 tol, 1e-5)
-    assert abs(k["pobj"] - ref) <= max(10 * tol, 1e-5) * abs(ref)
+    # the mixed path's bar: relative objective error <= 1e-4 against the
+    # exact optimum; at 1e-10 the FP64 phase finishes the solve and the FP64
+    # path's bar, 1e-6, applies
+    bar = 1e-6 if tol < 1e-9 else 1e-4
+    print("objective error", abs(k["pobj"] - ref) / abs(ref), flush=True)
+    assert abs(k["pobj"] - ref) <= bar * abs(ref)
     assert info["dual_bound"] <= ref + 1e-12 * abs(ref)
     assert info["attempts_fp32"] <= info["attempts"]
     if tol < 1e-9:
@@ -48,5 +50,7 @@ def test_mixed_uc1000(gpu, oracle_mod):
     assert info["status"] == 1, info
     k = oracle_mod.kkt(lp, x, y)
     assert k["rel_kkt"] <= 1.001e-4, k
-    assert abs(k["pobj"] - ref) <= 1e-3 * abs(ref)
+    # the mixed path's bar against HiGHS's optimum; measured 3.7e-5 at KKT 1e-4
+    print("objective error", abs(k["pobj"] - ref) / abs(ref), flush=True)
+    assert abs(k["pobj"] - ref) <= 1e-4 * abs(ref)
     assert abs(info["primal_obj"] - k["pobj"]) <= 1e-9 * abs(ref)

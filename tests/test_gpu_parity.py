@@ -93,9 +93,18 @@ def test_one_attempt(gpu, oracle_mod, name, reorder):
 # The adaptive-step iteration amplifies rounding differences (about tenfold
 # per 40 attempts on these instances, the same under a 1e-15 perturbation of c
 # in the oracle alone), so trajectories are compared over short horizons only;
-# longer solves are compared by objective and KKT error.
-@pytest.mark.parametrize("name,iters,bound", [("uc14_t24", 64, 1e-9), ("uc14_t24", 128, 1e-7),
-                                              ("dense_cols", 64, 1e-9), ("dense_cols", 128, 1e-5)])
+# longer solves are compared by objective and KKT error.  Every entry is
+# compared: |x_j - xo_j| <= bound (1 + |xo_j|), the same for y.  Measured
+# worst entries: 1.7e-12 (uc14_t24, 64 attempts), 8.0e-12 (128), 1.2e-11
+# (dense_cols, 64), 1.7e-7 (128, after a restart).
+def assert_entrywise(a, ref, bound, what):
+    err = np.abs(a - ref) / (1 + np.abs(ref))
+    j = int(np.argmax(err))
+    assert err[j] <= bound, (what, j, a[j], ref[j], err[j])
+
+
+@pytest.mark.parametrize("name,iters,bound", [("uc14_t24", 64, 1e-10), ("uc14_t24", 128, 1e-9),
+                                              ("dense_cols", 64, 1e-9), ("dense_cols", 128, 2e-6)])
 def test_short_trajectory(gpu, oracle_mod, name, iters, bound):
     from paper_2512_06715_amd.solver import Problem
     lp = CASES[name]()
@@ -107,9 +116,8 @@ def test_short_trajectory(gpu, oracle_mod, name, iters, bound):
     assert info["attempts"] == io["attempts"]
     assert info["restarts"] == io["restarts"]
     assert info["accepted"] == io["accepted"]
-    scale = 1 + np.linalg.norm(xo) + np.linalg.norm(yo)
-    err = np.linalg.norm(x - xo) + np.linalg.norm(y - yo)
-    assert err <= bound * scale, err / scale
+    assert_entrywise(x, xo, bound, "x")
+    assert_entrywise(y, yo, bound, "y")
     k = oracle_mod.kkt(lp, x, y)
     assert abs(k["rel_kkt"] - info["rel_kkt"]) <= 1e-9 * max(1.0, k["rel_kkt"])
 

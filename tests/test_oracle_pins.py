@@ -425,8 +425,28 @@ def test_implied_bounds_hand_example(oracle_mod):
     lp = ucgen.dense_to_lp(A, np.array([0, 1], np.uint8), np.array([0.0, 1.0]), np.zeros(3),
                            np.array([-np.inf, 0.0, 0.0]), np.array([np.inf, 3.0, np.inf]))
     lo, hi = oracle_mod.implied_bounds(lp)
-    assert lo[0] == 0.0 - 1e-9 and hi[0] == 3.0 + 1e-9 * 4.0
+    # x1 >= 0 - 0 exactly (every term is zero: no margin); x1 <= 3 + w with
+    # w = 2 (2 + 2) 2^-53 (|0| + 3) / 1 + 4 2^-53 3 = 36 2^-53
+    assert lo[0] == 0.0 and hi[0] == 3.0 + 36.0 * 2.0 ** -53
     assert lo[1] == 0.0 and hi[1] == 3.0 and lo[2] == 0.0 and np.isinf(hi[2])
+
+
+def test_implied_bound_margin_covers_cancellation(oracle_mod):
+    """The margin of a derived bound covers the rounding of the row sum, not
+    just of r: the bound of x3 must admit the feasible x3 = -7e-3, and the
+    safe dual bound at y = 0 (c'x over the box) must stay below the optimum."""
+    from edge_lps import cancelling_row
+    lp = cancelling_row()
+    lo, hi = oracle_mod.implied_bounds(lp)
+    assert lo[2] <= -7e-3, lo
+    # the margin: 2 (3 + 2) 2^-53 (1e8 + 1e8 + 7e-9) / 1e-6, about 0.22
+    assert lo[2] >= -0.3, lo
+    # the optimum in closed form: x1, x2 at their upper bounds, then
+    # x3 = (1e8 - 1e8 - 7e-9) / 1e-6 = -7e-3 (a library LP solve's 1e-7 row
+    # tolerance is 0.1 in x3 here, so none is used)
+    opt = -7e-3
+    sb = oracle_mod.safe_bound(lp, np.zeros(1), lo, hi)
+    assert sb["bound"] <= opt, sb
 
 
 def test_safe_bound_is_a_lower_bound_on_toys(oracle_mod):
