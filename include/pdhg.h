@@ -240,6 +240,25 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles,
                      size_t workspace_bytes, double *const *x, double *const *y,
                      pdhg_info *infos);
 
+/* pdhg_solve_batch for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * batched solve and results, with no workspace argument.  Its workspace is a
+ * file-scope device array of the library of PDHG_STATIC_SCRATCH_BYTES
+ * (64 MiB), one per GPU, held until the process ends; the call allocates no
+ * device or pinned host memory and captures no graph (blocks of attempts
+ * are launched directly).  Returns PDHG_ERR_OOM when the batch's workspace
+ * (pdhg_batch_workspace_bytes) exceeds 64 MiB or batch exceeds
+ * PDHG_STATIC_MAX_BATCH (64), and PDHG_ERR_HIP when the array's device
+ * address cannot be found.  The handles must belong to the current device.
+ * Every call on a GPU shares its array, which keeps the last call's contents;
+ * calls from one process are serialized, and work that overlaps such a call
+ * on the same GPU through the array would race. */
+#define PDHG_STATIC_SCRATCH_BYTES (64u << 20)
+#define PDHG_STATIC_MAX_BATCH 64
+int pdhg_solve_batch_static(pdhg_handle *const *handles, int n_handles,
+                            const pdhg_instance *inst, int batch, double *const *x,
+                            double *const *y, pdhg_info *infos);
+
 /* Unrolled mode (opts.unroll_iters = K > 0, FP64): pdhg_solve runs exactly K
  * fixed-step iterations from x = proj(x0 or 0), y = proj(y0 or 0), with
  * eta = opts.fixed_eta (or 0.9/||A^||_2 by 50 power iterations), the primal

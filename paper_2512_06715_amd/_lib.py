@@ -75,6 +75,9 @@ SIGNATURES = {
     "pdhg_solve_batch": (c_int, [ctypes.POINTER(vp), c_int, ctypes.POINTER(PdhgInstance),
                                  c_int, vp, ctypes.c_size_t, ctypes.POINTER(vp),
                                  ctypes.POINTER(vp), ctypes.POINTER(PdhgInfo)]),
+    "pdhg_solve_batch_static": (c_int, [ctypes.POINTER(vp), c_int, ctypes.POINTER(PdhgInstance),
+                                        c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.POINTER(PdhgInfo)]),
     "pdhg_backward": (c_int, [vp, c_dbl, vp, vp]),
     "pdhg_update": (c_int, [vp, vp, vp]),
     "pdhg_destroy": (None, [vp]),

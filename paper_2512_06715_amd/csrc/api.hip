@@ -39,6 +39,40 @@ double now_s() {
       .count();
 }
 
+// ---------------------------------------------------------------------------
+// The no-allocation batch (pdhg_solve_batch_static) carves its workspace out
+// of this file-scope device array instead of a caller's buffer: at most
+// PDHG_STATIC_SCRATCH_BYTES (pdhg.h), held by each GPU the library runs on
+// until the process ends.  In host code the name `scratch` is only a
+// stand-in for the symbol: its device address comes from
+// hipGetSymbolAddress, once per device (static_scratch), and only that
+// address is passed on.
+#define PDHG_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[PDHG_STATIC_SCRATCH_BYTES];
+
+std::mutex g_static_mu;                          // one no-allocation batch at a time
+CtlState g_static_states[PDHG_STATIC_MAX_BATCH];  // its host mirror of the control states
+std::mutex g_symbol_mu;
+void *g_scratch_ptr[PDHG_MAX_DEVICES];           // device address of `scratch`, per device
+
+// The current device's address of `scratch` (looked up on its first use).
+int static_scratch(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= PDHG_MAX_DEVICES)
+    return fail(PDHG_ERR_HIP, "no usable current device for the no-allocation scratch");
+  std::lock_guard<std::mutex> lk(g_symbol_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PDHG_ERR_HIP, "hipGetSymbolAddress of the scratch array failed on device %d: %s",
+                  dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PDHG_OK;
+}
+
 // Bump allocator over a caller's workspace; with base == nullptr it only
 // measures.
 struct Carver {
@@ -64,7 +98,8 @@ struct GroupDev {
   Inst<float> *d32 = nullptr;
   int32_t *pre = nullptr;         // 6 * (cap + 1)
   CtlState *dstates = nullptr;    // gathered states
-  CtlState *hstates = nullptr;    // pinned host mirror
+  CtlState *hstates = nullptr;    // host mirror (pinned, except in the no-allocation batch)
+  bool graphs = true;             // false: blocks are launched directly, never captured
 };
 
 void carve_group(Carver &cv, GroupDev &gd, int cap) {
@@ -989,7 +1024,7 @@ int run_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
     }
     int64_t nb = std::min<int64_t>(P, max_iter - kmin);
     if (nb < 1) nb = 1;
-    if (nb == P && h->o.use_graph) {
+    if (nb == P && h->o.use_graph && gd.graphs) {
       RC(capture<T>(h, gs, dI, g, P, tol, max_iter, version));
       HC(hipGraphLaunch(gs.exec, h->hs));
     } else {
@@ -1738,19 +1773,21 @@ int pdhg_batch_workspace_bytes(pdhg_handle *const *handles, int n_handles,
   return PDHG_OK;
 }
 
-int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_instance *inst,
-                     int batch, void *workspace, size_t ws_bytes, double *const *x,
-                     double *const *y, pdhg_info *infos) {
-  int rc = check_batch(handles, n_handles, inst, batch);
-  if (rc) return rc;
-  if (!x || !y || !infos) return fail(PDHG_ERR_ARG, "null output arrays");
-  for (int k = 0; k < batch; k++)
-    if (!x[k] || !y[k]) return fail(PDHG_ERR_ARG, "instance %d: null output", k);
+}  // extern "C"
+
+namespace {
+
+// The batched solve on a workspace already checked to be large enough
+// (ws: 256-byte aligned).  hstates: the host mirror of the batch's control
+// states (batch entries; null: pinned memory allocated here).  graphs: false
+// launches every block directly (no graph is captured or instantiated).
+int solve_batch_on(pdhg_handle *const *handles, int n_handles, const pdhg_instance *inst,
+                   int batch, void *ws, double *const *x, double *const *y, pdhg_info *infos,
+                   CtlState *hstates, bool graphs) {
+  int rc = PDHG_OK;
   BatchPlan P;
-  size_t need = batch_layout(handles, inst, batch, nullptr, P);
-  if (!workspace || ws_bytes < need)
-    return fail(PDHG_ERR_OOM, "batch workspace of %zu bytes, need %zu", ws_bytes, need);
-  batch_layout(handles, inst, batch, (void *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255), P);
+  batch_layout(handles, inst, batch, ws, P);
+  P.gd.graphs = graphs;
   pdhg_handle *h = handles[0];  // the batch runs on this handle's stream
   for (int i = 0; i < n_handles; i++) RC(enter(handles[i]));
   for (int i = 1; i < n_handles; i++) {
@@ -1759,8 +1796,12 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
   }
   double t0 = now_s();
   PinnedStates pin;
-  HC(hipHostMalloc((void **)&pin.p, sizeof(CtlState) * batch, hipHostMallocDefault));
-  P.gd.hstates = pin.p;
+  if (hstates) {
+    P.gd.hstates = hstates;
+  } else {
+    HC(hipHostMalloc((void **)&pin.p, sizeof(CtlState) * batch, hipHostMallocDefault));
+    P.gd.hstates = pin.p;
+  }
   std::vector<Inst<double>> i64(batch);
   std::vector<Inst<float>> i32(batch);
   const bool mixed = h->o.precision == PDHG_MIXED;
@@ -1893,6 +1934,50 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_inst
               dt);
   for (int i = 0; i < n_handles; i++) RC(leave(handles[i]));
   return PDHG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles, const pdhg_instance *inst,
+                     int batch, void *workspace, size_t ws_bytes, double *const *x,
+                     double *const *y, pdhg_info *infos) {
+  int rc = check_batch(handles, n_handles, inst, batch);
+  if (rc) return rc;
+  if (!x || !y || !infos) return fail(PDHG_ERR_ARG, "null output arrays");
+  for (int k = 0; k < batch; k++)
+    if (!x[k] || !y[k]) return fail(PDHG_ERR_ARG, "instance %d: null output", k);
+  BatchPlan P;
+  size_t need = batch_layout(handles, inst, batch, nullptr, P);
+  if (!workspace || ws_bytes < need)
+    return fail(PDHG_ERR_OOM, "batch workspace of %zu bytes, need %zu", ws_bytes, need);
+  return solve_batch_on(handles, n_handles, inst, batch,
+                        (void *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255), x, y, infos,
+                        nullptr, true);
+}
+
+int pdhg_solve_batch_static(pdhg_handle *const *handles, int n_handles,
+                            const pdhg_instance *inst, int batch, double *const *x,
+                            double *const *y, pdhg_info *infos) {
+  int rc = check_batch(handles, n_handles, inst, batch);
+  if (rc) return rc;
+  if (!x || !y || !infos) return fail(PDHG_ERR_ARG, "null output arrays");
+  for (int k = 0; k < batch; k++)
+    if (!x[k] || !y[k]) return fail(PDHG_ERR_ARG, "instance %d: null output", k);
+  if (batch > PDHG_STATIC_MAX_BATCH)
+    return fail(PDHG_ERR_OOM, "no-allocation batch of %d instances, at most %d", batch,
+                PDHG_STATIC_MAX_BATCH);
+  BatchPlan P;
+  size_t need = batch_layout(handles, inst, batch, nullptr, P);
+  if (need > PDHG_STATIC_SCRATCH_BYTES)
+    return fail(PDHG_ERR_OOM, "no-allocation batch needs %zu bytes of scratch, at most %zu",
+                need, (size_t)PDHG_STATIC_SCRATCH_BYTES);
+  void *ptr = nullptr;
+  RC(static_scratch(&ptr));
+  std::lock_guard<std::mutex> lk(g_static_mu);  // one call at a time per process
+  return solve_batch_on(handles, n_handles, inst, batch, ptr, x, y, infos, g_static_states,
+                        false);
 }
 
 int pdhg_backward(pdhg_handle *h, double grad_value, double *grad_b, double *grad_c) {

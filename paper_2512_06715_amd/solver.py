@@ -191,7 +191,7 @@ def solve(lp, x0=None, y0=None, **opts):
         p.close()
 
 
-def solve_batch(problems, instances, stream=None):
+def solve_batch(problems, instances, stream=None, static=False):
     """Solve many instances in one batched run.
 
     problems: list of Problem (the bases; same precision).
@@ -202,6 +202,9 @@ def solve_batch(problems, instances, stream=None):
     the defaults) and 'hold_omega' (attempts during which the primal weight
     keeps its initial value).  Host problems take numpy arrays, device problems torch
     CUDA tensors.  Returns a list of (x, y, info dict).
+
+    static=True calls pdhg_solve_batch_static: no workspace is allocated; the
+    library's fixed device scratch array (64 MiB) holds the batch.
     """
     import torch
     lib = L.load()
@@ -240,14 +243,17 @@ def solve_batch(problems, instances, stream=None):
             x = np.zeros(base.n)
             y = np.zeros(base.m)
         outs.append((x, y))
-    nb = ctypes.c_size_t()
-    L.check(lib.pdhg_batch_workspace_bytes(H, len(problems), arr, len(instances),
-                                           ctypes.byref(nb)))
-    ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
     X = (ctypes.c_void_p * len(instances))(*[_ptr(o[0]).value for o in outs])
     Y = (ctypes.c_void_p * len(instances))(*[_ptr(o[1]).value for o in outs])
     infos = (L.PdhgInfo * len(instances))()
-    L.check(lib.pdhg_solve_batch(H, len(problems), arr, len(instances),
-                                 ctypes.c_void_p(ws.data_ptr()), int(nb.value), X, Y, infos))
-    del ws
+    if static:
+        L.check(lib.pdhg_solve_batch_static(H, len(problems), arr, len(instances), X, Y, infos))
+    else:
+        nb = ctypes.c_size_t()
+        L.check(lib.pdhg_batch_workspace_bytes(H, len(problems), arr, len(instances),
+                                               ctypes.byref(nb)))
+        ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+        L.check(lib.pdhg_solve_batch(H, len(problems), arr, len(instances),
+                                     ctypes.c_void_p(ws.data_ptr()), int(nb.value), X, Y, infos))
+        del ws
     return [(outs[k][0], outs[k][1], infos[k].as_dict()) for k in range(len(instances))]
