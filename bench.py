@@ -70,9 +70,7 @@ def load_traffic(kernel: str, workload: str, precision: str):
         return None
     with open(path) as f:
         d = json.load(f)
-    # valid_for lists later sources whose attempt kernels were checked to
-    # make the same loads and stores (the record states how)
-    if source_hash() not in [d.get("source_hash")] + list(d.get("valid_for", [])):
+    if source_hash() != d.get("source_hash"):
         return None
     return d.get("bytes_per_launch")
 

@@ -146,6 +146,11 @@ typedef struct {
                              Skipped where c'x is bounded below on the implied box (every
                              column bounded on both sides, or its cost of the sign that the
                              one finite bound limits, or zero): no ray can improve there */
+  int batch_pack;         /* 1: batched instances that share a matrix (same base, one tile
+                             per workgroup, LDS-staged tiles) run the attempt kernels a
+                             pack of 4 instances per workgroup, the tile's structure
+                             loaded once for the pack; 0 (default): one instance per
+                             workgroup.  The results do not depend on it */
 } pdhg_opts;
 
 typedef struct {

@@ -38,7 +38,7 @@ class PdhgOpts(ctypes.Structure):
                 ("spmv_direct", c_int), ("long_seg", c_int), ("reorder", c_int),
                 ("compact_index", c_int), ("infeas_every", c_int),
                 ("polish_pw_update", c_int), ("fp32_stall_evals", c_int),
-                ("dinf_tol", c_dbl)]
+                ("dinf_tol", c_dbl), ("batch_pack", c_int)]
 
 
 class PdhgInfo(ctypes.Structure):

@@ -350,6 +350,7 @@ int check_opts(const pdhg_opts *o) {
   if (o->fp32_stall_evals < 0) return fail(PDHG_ERR_ARG, "fp32_stall_evals must be >= 0");
   if (!(o->dinf_tol >= 0.0) || !isfinite(o->dinf_tol))
     return fail(PDHG_ERR_ARG, "dinf_tol must be finite and >= 0");
+  if (o->batch_pack != 0 && o->batch_pack != 1) return fail(PDHG_ERR_ARG, "batch_pack must be 0 or 1");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -907,7 +908,21 @@ int upload_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
     g.interleave = a.rp == b.rp && a.cp == b.cp && a.v == b.v && a.vt == b.vt &&
                    a.grid_rows == b.grid_rows && a.grid_cols == b.grid_cols &&
                    a.tpb_rows == b.tpb_rows && a.tpb_cols == b.tpb_cols &&
-                   a.n_long_rows == b.n_long_rows && a.n_long_cols == b.n_long_cols;
+                   a.n_long_rows == b.n_long_rows && a.n_long_cols == b.n_long_cols &&
+                   a.long_seg == b.long_seg && a.direct == b.direct;
+  }
+  // shared-matrix instances walked a pack at a time (same tiles, partials and
+  // bits as one at a time)
+  const IterView<T> &w0 = sel[0].w;
+  g.pack = (g.interleave && g.compact && h->o.batch_pack && w0.tpb_rows == 1 &&
+            w0.tpb_cols == 1 && !w0.direct && !w0.mask_x && !w0.mask_y)
+               ? PDHG_PACK
+               : 0;
+  if (g.pack) {
+    const int npk = (na + PDHG_PACK - 1) / PDHG_PACK;
+    const int64_t tr = (w0.m + PDHG_TILE - 1) / PDHG_TILE, tc = (w0.n + PDHG_TILE - 1) / PDHG_TILE;
+    g.n_primal_pack = (int)(w0.n_long_cols * (int64_t)na + tc * npk);
+    g.n_dual_pack = (int)(w0.n_long_rows * (int64_t)na + tr * npk);
   }
   return PDHG_OK;
 }
@@ -1284,6 +1299,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->polish_pw_update = 1;
   o->fp32_stall_evals = 300;
   o->dinf_tol = 1e-8;
+  o->batch_pack = 0;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }

@@ -264,6 +264,27 @@ __device__ __forceinline__ bool primal_finish(int64_t j, T t, T tau, T xj, T cj,
   return xt > lj && xt < uj;
 }
 
+// Long column lb of an instance (a workgroup of its own): its row-dot over
+// the stored transpose in FP64, then the primal update by lane 0.
+template <typename T>
+__device__ __forceinline__ void primal_long(const AS_C IterView<T> &w, const AS_C CtlState *st,
+                                            int lb, uint64_t *mask) {
+  const int cur = st->cur;
+  const T tau = (T)(st->eta / st->omega);
+  const AS_G T *x = gin((const T *)w.X[cur]), *y = gin((const T *)w.Y[cur]);
+  const AS_G T *c = gin(w.c), *l = gin(w.l), *u = gin(w.u);
+  AS_G T *xn = gout(w.X[cur ^ 1]);
+  int64_t j = gin(w.long_cols)[lb];
+  const AS_C int32_t *cpc = cin(w.cp);
+  double t = long_rowdot<T>(gin(w.ri), gin(w.vt), y, cpc[j], cpc[j + 1]);
+  if (threadIdx.x == 0) {
+    double dd = 0.0;
+    bool in = primal_finish<T>(j, (T)t, tau, x[j], c[j], l[j], u[j], xn, nullptr, (T)0, 0.0, 0, dd);
+    gout(w.part_dx2)[lb] = dd;
+    if (mask && in) record_bit(mask, j);
+  }
+}
+
 template <typename T, bool C>
 __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ __align__(16) T lds[TILE_CAP + PDHG_TILE];
@@ -286,16 +307,7 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
   uint64_t *mask = w.mask_x ? w.mask_x + (st->k - w.mask_k0) * ((n + 63) >> 6) : nullptr;
   double d2[1] = {0.0};
   if (lb < w.n_long_cols) {
-    int64_t j = gin(w.long_cols)[lb];
-    const AS_C int32_t *cpc = cin(w.cp);
-    double t = long_rowdot<T>(ri, vt, y, cpc[j], cpc[j + 1]);
-    if (threadIdx.x == 0) {
-      double dd = 0.0;
-      bool in = primal_finish<T>(j, (T)t, tau, x[j], c[j], l[j], u[j], xn, nullptr, (T)0, 0.0, 0,
-                                 dd);
-      gout(w.part_dx2)[lb] = dd;
-      if (mask && in) record_bit(mask, j);
-    }
+    primal_long<T>(w, st, lb, mask);
     return;
   }
   const int tpb = w.tpb_cols, long_seg = w.long_seg, direct = w.direct;
@@ -350,6 +362,29 @@ __device__ __forceinline__ bool dual_finish(int64_t i, T s, T sigma, T yi, T axi
   return in;
 }
 
+// Long row lb of an instance: its row-dot over A in FP64, then the dual
+// update by lane 0.
+template <typename T>
+__device__ __forceinline__ void dual_long(const AS_C IterView<T> &w, const AS_C CtlState *st,
+                                          int lb, uint64_t *mask) {
+  const int cur = st->cur;
+  const T sigma = (T)(st->eta * st->omega);
+  const AS_G T *xn = gin((const T *)w.X[cur ^ 1]);
+  const AS_G T *y = gin((const T *)w.Y[cur]), *ax = gin((const T *)w.AX[cur]), *bb = gin(w.b);
+  AS_G T *yn = gout(w.Y[cur ^ 1]), *axn = gout(w.AX[cur ^ 1]);
+  int64_t i = gin(w.long_rows)[lb];
+  const AS_C int32_t *rpc = cin(w.rp);
+  double t = long_rowdot<T>(gin(w.ci), gin(w.v), xn, rpc[i], rpc[i + 1]);
+  if (threadIdx.x == 0) {
+    double acc[2] = {0.0, 0.0};
+    bool in = dual_finish<T>(i, (T)t, sigma, y[i], ax[i], bb[i], gin(w.kind)[i], yn, axn, nullptr,
+                             (T)0, 0.0, 0, acc[0], acc[1]);
+    gout(w.part_dy)[lb] = acc[0];
+    gout(w.part_dy)[w.grid_rows + lb] = acc[1];
+    if (mask && in) record_bit(mask, i);
+  }
+}
+
 template <typename T, bool C>
 __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ __align__(16) T lds[TILE_CAP + PDHG_TILE];
@@ -374,16 +409,7 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
   const int64_t G = w.grid_rows;
   double acc[2] = {0.0, 0.0};
   if (lb < w.n_long_rows) {
-    int64_t i = gin(w.long_rows)[lb];
-    const AS_C int32_t *rpc = cin(w.rp);
-    double t = long_rowdot<T>(ci, v, xn, rpc[i], rpc[i + 1]);
-    if (threadIdx.x == 0) {
-      bool in = dual_finish<T>(i, (T)t, sigma, y[i], ax[i], bb[i], kind[i], yn, axn, nullptr,
-                               (T)0, 0.0, 0, acc[0], acc[1]);
-      gout(w.part_dy)[lb] = acc[0];
-      gout(w.part_dy)[G + lb] = acc[1];
-      if (mask && in) record_bit(mask, i);
-    }
+    dual_long<T>(w, st, lb, mask);
     return;
   }
   const int tpb = w.tpb_rows, long_seg = w.long_seg, direct = w.direct;
@@ -424,6 +450,257 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Multi-instance tiles: instances that share one matrix (branch-and-bound
+// variants of one LP, g.pack > 0) are walked NB at a time.  A workgroup
+// applies one tile of the shared matrix to a pack of NB instances: the
+// tile's 16-bit indices and values are staged in LDS once, then each lane
+// walks its own row in CSR order, four entries at a time, gathering the pack's
+// NB vectors together (4 NB independent loads in flight per lane).  Each
+// product is rounded on its own and the row sum starts at zero and adds them
+// in CSR order, as in the single-instance kernels, so every instance gets
+// the same bits either way.  Long rows and columns keep a workgroup per
+// instance (the first n_long * ninst blocks); the tiles follow tile-major,
+// the packs of one tile next to each other on one XCD.
+
+// Stage the raw structure of a tile (indices relative to its smallest one,
+// values) in LDS, two entries per load as in stage_pairs; entry e of the
+// tile sits at slot e - a0, a0 = base & ~1.
+template <typename T>
+__device__ __forceinline__ void stage_structure(const AS_G uint16_t *ix16, const AS_G T *v,
+                                                int base, int top, uint16_t *sidx, T *sval) {
+  typedef typename Pair<T>::type T2;
+  const int a0 = base & ~1;
+  const int npair = (top - a0 + 1) >> 1;
+  const AS_G uint32_t *iw = (const AS_G uint32_t *)(ix16 + a0);
+  const AS_G T2 *vw = (const AS_G T2 *)(v + a0);
+  constexpr int TP = TILE_U / 2;
+  for (int p0 = 0; p0 < npair; p0 += TP * PDHG_TILE) {
+    uint32_t w[TP];
+    T2 vv[TP];
+#pragma unroll
+    for (int q = 0; q < TP; q++) {
+      int p = p0 + q * PDHG_TILE + (int)threadIdx.x;
+      int pc = p < npair ? p : npair - 1;
+      w[q] = ld_stream(iw + pc);
+      vv[q] = ld_stream(vw + pc);
+    }
+#pragma unroll
+    for (int q = 0; q < TP; q++) {
+      int p = p0 + q * PDHG_TILE + (int)threadIdx.x;
+      int pc = p < npair ? p : npair - 1;
+      *(uint32_t *)(sidx + 2 * pc) = w[q];
+      *(T2 *)(sval + 2 * pc) = vv[q];
+    }
+  }
+}
+
+// Row sums s[q] = sum_k v[k] x_q[idx[k]] of this lane's row (entries [rs, re)
+// of the tile staged from a0) for the pack's instances q < nq, in CSR order.
+// Without staging (a tile past the LDS buffer) the entries come from global
+// memory.
+template <typename T, int NB>
+__device__ __forceinline__ void pack_rowdot(const uint16_t *sidx, const T *sval, bool staged,
+                                            const AS_G uint16_t *ix16, const AS_G T *v, int tb,
+                                            int a0, int rs, int re, const AS_G T *const (&x)[NB],
+                                            int nq, T (&s)[NB]) {
+#pragma unroll
+  for (int q = 0; q < NB; q++) s[q] = 0;
+  for (int k0 = rs; k0 < re; k0 += TILE_U) {
+    int id[TILE_U];
+    T vv[TILE_U];
+#pragma unroll
+    for (int u = 0; u < TILE_U; u++) {
+      int k = k0 + u < re ? k0 + u : re - 1;
+      id[u] = tb + (int)(staged ? sidx[k - a0] : ix16[k]);
+      vv[u] = staged ? sval[k - a0] : v[k];
+    }
+    T gx[TILE_U][NB];
+#pragma unroll
+    for (int u = 0; u < TILE_U; u++)
+#pragma unroll
+      for (int q = 0; q < NB; q++) gx[u][q] = q < nq ? x[q][id[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < TILE_U; u++)
+      if (k0 + u < re) {
+#pragma unroll
+        for (int q = 0; q < NB; q++) s[q] += mul_rn(vv[u], gx[u][q]);
+      }
+  }
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(PDHG_TILE) void k_primal_pack(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ __align__(16) uint16_t sidx[TILE_CAP + 4];
+  __shared__ __align__(16) T sval[TILE_CAP + 4];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const AS_C IterView<T> &w0 = cin(I)[0].w;  // the shared matrix and partition
+  const int nlong = w0.n_long_cols;
+  if (b < nlong * g.ninst) {
+    const int inst = b % g.ninst;
+    primal_long<T>(cin(I)[inst].w, cin(cin(I)[inst].st), b / g.ninst, nullptr);
+    return;
+  }
+  const int npk = (g.ninst + NB - 1) / NB;
+  const int tb_ = b - nlong * g.ninst;
+  const int64_t t = tb_ / npk;
+  const int q0 = (tb_ % npk) * NB;
+  const int nq = g.ninst - q0 < NB ? g.ninst - q0 : NB;
+  const int64_t n = w0.n;
+  const int64_t r0 = t * PDHG_TILE;
+  const int64_t rend = r0 + PDHG_TILE < n ? r0 + PDHG_TILE : n;
+  const int64_t j = r0 + threadIdx.x;
+  const bool valid = j < n;
+  const AS_C int32_t *cpc = cin(w0.cp);
+  const int base = cpc[r0], top = cpc[rend];
+  const int tbase = cin(w0.tb_cols)[t];
+  // the pack's step sizes, iterates and the column's own values
+  T tau[NB], xj[NB], cj[NB], lj[NB], uj[NB], xsj[NB];
+  const AS_G T *y[NB];
+#pragma unroll
+  for (int q = 0; q < NB; q++) {
+    xj[q] = cj[q] = lj[q] = uj[q] = xsj[q] = 0;
+    tau[q] = 0;
+    y[q] = nullptr;
+    if (q < nq) {
+      const AS_C IterView<T> &w = cin(I)[q0 + q].w;
+      const AS_C CtlState *st = cin(cin(I)[q0 + q].st);
+      const int cur = st->cur;
+      tau[q] = (T)(st->eta / st->omega);
+      y[q] = gin((const T *)w.Y[cur]);
+      if (valid) {
+        xj[q] = gin((const T *)w.X[cur])[j];
+        cj[q] = ld_stream(gin(w.c) + j);
+        lj[q] = ld_stream(gin(w.l) + j);
+        uj[q] = ld_stream(gin(w.u) + j);
+        if (st->pending > 0.0 && !st->fresh) xsj[q] = gin((const T *)w.XS)[j];
+      }
+    }
+  }
+  const bool staged = top - base <= TILE_CAP;
+  if (staged && top > base) stage_structure<T>(gin(w0.rix16), gin(w0.vt), base, top, sidx, sval);
+  int rs = 0, re = 0;
+  if (valid) {
+    const TileIx<true> ix{nullptr, nullptr, gin(w0.cofs), gin(w0.rix16), tbase};
+    ix.bounds(j, base, rs, re);
+  }
+  __syncthreads();
+  const bool mine = valid && (re - rs <= w0.long_seg);
+  T sum[NB];
+  pack_rowdot<T, NB>(sidx, sval, staged, gin(w0.rix16), gin(w0.vt), tbase, base & ~1, rs,
+                     mine ? re : rs, y, nq, sum);
+  double d2[NB];
+#pragma unroll
+  for (int q = 0; q < NB; q++) {
+    d2[q] = 0.0;
+    if (q < nq && valid) {
+      const AS_C IterView<T> &w = cin(I)[q0 + q].w;
+      const AS_C CtlState *st = cin(cin(I)[q0 + q].st);
+      const int cur = st->cur;
+      AS_G T *xn = gout(w.X[cur ^ 1]);
+      AS_G T *xs = gout(w.XS);
+      if (mine)
+        primal_finish<T>(j, sum[q], tau[q], xj[q], cj[q], lj[q], uj[q], xn, xs, xsj[q],
+                         st->pending, st->fresh, d2[q]);
+      else
+        fold_sum<T>(xs, j, xsj[q], xj[q], st->pending, st->fresh);  // long column
+    }
+  }
+  double out[NB];
+  block_reduce<NB, PDHG_TILE>(d2, 0u, out);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NB; q++)
+      if (q < nq) gout(cin(I)[q0 + q].w.part_dx2)[nlong + t] = out[q];
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(PDHG_TILE) void k_dual_pack(const Inst<T> *__restrict__ I, Groups g) {
+  __shared__ __align__(16) uint16_t sidx[TILE_CAP + 4];
+  __shared__ __align__(16) T sval[TILE_CAP + 4];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const AS_C IterView<T> &w0 = cin(I)[0].w;
+  const int nlong = w0.n_long_rows;
+  if (b < nlong * g.ninst) {
+    const int inst = b % g.ninst;
+    dual_long<T>(cin(I)[inst].w, cin(cin(I)[inst].st), b / g.ninst, nullptr);
+    return;
+  }
+  const int npk = (g.ninst + NB - 1) / NB;
+  const int tb_ = b - nlong * g.ninst;
+  const int64_t t = tb_ / npk;
+  const int q0 = (tb_ % npk) * NB;
+  const int nq = g.ninst - q0 < NB ? g.ninst - q0 : NB;
+  const int64_t m = w0.m;
+  const int64_t r0 = t * PDHG_TILE;
+  const int64_t rend = r0 + PDHG_TILE < m ? r0 + PDHG_TILE : m;
+  const int64_t i = r0 + threadIdx.x;
+  const bool valid = i < m;
+  const AS_C int32_t *rpc = cin(w0.rp);
+  const int base = rpc[r0], top = rpc[rend];
+  const int tbase = cin(w0.tb_rows)[t];
+  T yi[NB], axi[NB], bi[NB], ysi[NB];
+  uint8_t ki = 0;
+  const AS_G T *xn[NB];
+#pragma unroll
+  for (int q = 0; q < NB; q++) {
+    yi[q] = axi[q] = bi[q] = ysi[q] = 0;
+    xn[q] = nullptr;
+    if (q < nq) {
+      const AS_C IterView<T> &w = cin(I)[q0 + q].w;
+      const AS_C CtlState *st = cin(cin(I)[q0 + q].st);
+      const int cur = st->cur;
+      xn[q] = gin((const T *)w.X[cur ^ 1]);
+      if (valid) {
+        yi[q] = gin((const T *)w.Y[cur])[i];
+        axi[q] = gin((const T *)w.AX[cur])[i];
+        bi[q] = ld_stream(gin(w.b) + i);
+        if (st->pending > 0.0 && !st->fresh) ysi[q] = gin((const T *)w.YS)[i];
+      }
+    }
+  }
+  if (valid) ki = gin(w0.kind)[i];
+  const bool staged = top - base <= TILE_CAP;
+  if (staged && top > base) stage_structure<T>(gin(w0.cix16), gin(w0.v), base, top, sidx, sval);
+  int rs = 0, re = 0;
+  if (valid) {
+    const TileIx<true> ix{nullptr, nullptr, gin(w0.rofs), gin(w0.cix16), tbase};
+    ix.bounds(i, base, rs, re);
+  }
+  __syncthreads();
+  const bool mine = valid && (re - rs <= w0.long_seg);
+  T sum[NB];
+  pack_rowdot<T, NB>(sidx, sval, staged, gin(w0.cix16), gin(w0.v), tbase, base & ~1, rs,
+                     mine ? re : rs, xn, nq, sum);
+  double acc[2 * NB];
+#pragma unroll
+  for (int q = 0; q < NB; q++) {
+    acc[2 * q] = acc[2 * q + 1] = 0.0;
+    if (q < nq && valid) {
+      const AS_C IterView<T> &w = cin(I)[q0 + q].w;
+      const AS_C CtlState *st = cin(cin(I)[q0 + q].st);
+      const int cur = st->cur;
+      const T sigma = (T)(st->eta * st->omega);
+      AS_G T *yn = gout(w.Y[cur ^ 1]), *axn = gout(w.AX[cur ^ 1]), *ys = gout(w.YS);
+      if (mine)
+        dual_finish<T>(i, sum[q], sigma, yi[q], axi[q], bi[q], ki, yn, axn, ys, ysi[q],
+                       st->pending, st->fresh, acc[2 * q], acc[2 * q + 1]);
+      else
+        fold_sum<T>(ys, i, ysi[q], yi[q], st->pending, st->fresh);  // long row
+    }
+  }
+  double out[2 * NB];
+  block_reduce<2 * NB, PDHG_TILE>(acc, 0u, out);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NB; q++)
+      if (q < nq) {
+        const AS_C IterView<T> &w = cin(I)[q0 + q].w;
+        gout(w.part_dy)[nlong + t] = out[2 * q];
+        gout(w.part_dy)[w.grid_rows + nlong + t] = out[2 * q + 1];
+      }
+}
+
 }  // namespace
 
 // With events, the kernel is launched through hipExtLaunchKernelGGL, whose
@@ -452,6 +729,14 @@ void launch_dual_as(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t
 template <typename T>
 void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
                    hipEvent_t t1) {
+  if (g.pack) {
+    if (t0)
+      hipExtLaunchKernelGGL(k_primal_pack<T, PDHG_PACK>, dim3(grid_of(g.n_primal_pack)),
+                            dim3(PDHG_TILE), 0, s, t0, t1, 0, I, g);
+    else
+      k_primal_pack<T, PDHG_PACK><<<grid_of(g.n_primal_pack), PDHG_TILE, 0, s>>>(I, g);
+    return;
+  }
   if (g.compact)
     launch_primal_as<T, true>(I, g, s, t0, t1);
   else
@@ -460,6 +745,14 @@ void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t 
 
 template <typename T>
 void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  if (g.pack) {
+    if (t0)
+      hipExtLaunchKernelGGL(k_dual_pack<T, PDHG_PACK>, dim3(grid_of(g.n_dual_pack)),
+                            dim3(PDHG_TILE), 0, s, t0, t1, 0, I, g);
+    else
+      k_dual_pack<T, PDHG_PACK><<<grid_of(g.n_dual_pack), PDHG_TILE, 0, s>>>(I, g);
+    return;
+  }
   if (g.compact)
     launch_dual_as<T, true>(I, g, s, t0, t1);
   else

@@ -12,6 +12,8 @@
 #endif
 // workgroups per instance of the step-control kernel
 #define PDHG_CTL_SPLIT 16
+// instances per workgroup of the attempt kernels when instances share a matrix
+#define PDHG_PACK 4
 // default length above which a row / column is handled by a workgroup
 #define PDHG_LONG_SEG 64
 // tile groups per launch above which a workgroup takes several tiles
@@ -203,6 +205,11 @@ struct Groups {
   int interleave;
   // 1: every instance has the 16-bit structure; the attempt kernels read it
   int compact;
+  // > 0: instances sharing one matrix (interleave, 16-bit structure, one
+  // tile per workgroup, LDS-staged tiles, no mask recording) are walked
+  // PDHG_PACK at a time by the pack kernels, whose grids are these
+  int pack;
+  int n_primal_pack, n_dual_pack;
 };
 
 // ---------------------------------------------------------------------------

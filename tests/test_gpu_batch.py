@@ -89,3 +89,57 @@ def test_shared_matrix_batch_matches_standalone(gpu, oracle_mod, precision, coun
             assert np.array_equal(xs, x) and np.array_equal(ys, y), k
         else:
             np.testing.assert_allclose(x, xs, rtol=0, atol=1e-9 * (1 + np.abs(xs).max()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("long_seg", [0, 4])
+def test_pack_kernels_bit_identical(gpu, oracle_mod, precision, long_seg):
+    """Shared-matrix instances walked four per workgroup (the pack kernels,
+    the tile's structure loaded once) give the bits of one instance per
+    workgroup: same products, same CSR-order sums, same partials.  Six
+    instances make a full and a partial pack; a long-row threshold of 4
+    sends thousands of rows and columns to the per-instance long path."""
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    base = ucgen.random_uc(14, 5, 20, 12, 1.0, seed=23)
+    nodes = node_variants(base, 5, 9)
+    print("case pack kernels", precision, long_seg, flush=True)
+    insts = [dict(base=0)] + [dict(base=0, fix_idx=v.meta["fix_idx"], fix_val=v.meta["fix_val"])
+                              for v in nodes]
+    out = {}
+    for pack in (1, 0):
+        p = Problem(base, tol=1e-4, max_iter=400000, precision=precision, long_seg=long_seg,
+                    batch_pack=pack)
+        out[pack] = solve_batch([p], insts)
+        p.close()
+    for k in range(len(insts)):
+        (x1, y1, i1), (x0, y0, i0) = out[1][k], out[0][k]
+        assert i1["status"] == i0["status"] == 1, (k, i1, i0)
+        assert i1["attempts"] == i0["attempts"] and i1["restarts"] == i0["restarts"], k
+        assert np.array_equal(x1, x0) and np.array_equal(y1, y0), k
+        lp = ([base] + nodes)[k]
+        assert oracle_mod.kkt(lp, x1, y1)["rel_kkt"] <= 1.001e-4
+
+
+def test_uc4224_variants_batch(gpu, oracle_mod):
+    """Branch-and-bound variants of the 4224-bus, 48-period LP (a random 0-20%
+    of the commitments fixed), in mixed precision to relative KKT 1e-4 in one
+    batch: every instance reaches the tolerance by the oracle's checker and
+    matches its standalone solve."""
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    lp = ucgen.workload("uc4224_t48")
+    variants = [ucgen.fix_commitments(lp, seed=100 + k) for k in range(5)]
+    print("case uc4224 variants", flush=True)
+    opts = dict(tol=1e-4, max_iter=2000000, precision="mixed")
+    p = Problem(lp, **opts)
+    insts = [dict(base=0, fix_idx=v.meta["fix_idx"], fix_val=v.meta["fix_val"]) for v in variants]
+    res = solve_batch([p], insts)
+    for k, (x, y, info) in enumerate(res):
+        assert info["status"] == 1, (k, info)
+        kk = oracle_mod.kkt(variants[k], x, y)
+        assert kk["rel_kkt"] <= 1.001e-4, (k, kk)
+        (xs, ys, info_s), = solve_batch([p], [insts[k]])
+        print(k, "attempts", info["attempts"], "alone", info_s["attempts"], flush=True)
+        assert info_s["attempts"] == info["attempts"], k
+        np.testing.assert_allclose(x, xs, rtol=0, atol=1e-9 * (1 + np.abs(xs).max()))
+        np.testing.assert_allclose(y, ys, rtol=0, atol=1e-9 * (1 + np.abs(ys).max()))
+    p.close()
