@@ -85,10 +85,31 @@ def cpu_baseline(lp, sample_lo: int, sample_hi: int):
     oracle.pdhg(lp, tol=1e-4, max_iter=sample_hi)
     t2 = time.perf_counter()
     per_attempt = ((t2 - t1) - (t1 - t0)) / (sample_hi - sample_lo)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=1.0 / per_attempt, unit="attempts/s", cores=1, kind="oracle",
+                cpu_model=model, host_threads=os.cpu_count(),
                 sample=f"FP64 oracle PDHG, {sample_hi - sample_lo} attempts "
                        f"(runs capped at {sample_lo} and {sample_hi} attempts, difference), "
                        f"same LP, single thread; {t2 - t0:.1f}s of CPU work")
+
+
+def reference_objective(workload: str):
+    """The workload's exact optimum from tests/golden/lp_refs.json, if stored."""
+    path = os.path.join(ROOT, "tests", "golden", "lp_refs.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        refs = json.load(f)
+    r = refs.get(workload)
+    return r["objective"] if r and r.get("status") == "optimal" else None
 
 
 def fp64_compare(lp, args):
@@ -103,78 +124,81 @@ def fp64_compare(lp, args):
     dt = time.perf_counter() - t0
     p.close()
     return dict(fp64_time_to_tol_s=round(dt, 3), fp64_attempts=info["attempts"],
+                fp64_primal_obj=info["primal_obj"],
                 fp64_attempts_per_s=round(info["attempts"] / dt, 1),
                 fp64_rel_kkt=info["rel_kkt"], fp64_status=info["status_name"])
 
 
-def batch_run(args):
-    """Batched LPs/s on the small instances of the batched workload (500-2000
-    buses, 24 periods, mixed precision, KKT 1e-4 each) against the same
-    instances solved one at a time with pdhg_solve (setup excluded from both)."""
-    import torch
-    from paper_2512_06715_amd import ucgen
-    from paper_2512_06715_amd.solver import Problem, solve_batch
-    lps = [ucgen.small_batch_instance(j) for j in range(args.batch_small)]
-    probs = [Problem(lp, tol=args.tol, precision="mixed", max_iter=args.max_iter) for lp in lps]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = solve_batch(probs, [dict(base=k) for k in range(len(lps))])
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    ok = sum(1 for r in res if r[2]["status"] == 1)
-    print(f"[bench] batch of {len(lps)}: {tb:.2f}s, {ok} solved; now one at a time",
-          file=sys.stderr, flush=True)
-    ts = 0.0
-    for k, p in enumerate(probs):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        p.solve()
-        torch.cuda.synchronize()
-        ts += time.perf_counter() - t0
-        p.close()
-        if k % 8 == 7:
-            print(f"[bench] {k + 1} solved one at a time, {ts:.2f}s", file=sys.stderr, flush=True)
-    n = len(lps)
-    return dict(instances=n, solved=ok, lps_per_s=round(n / tb, 4),
-                sequential_lps_per_s=round(n / ts, 4), speedup=round(ts / tb, 3),
-                batch_s=round(tb, 3), sequential_s=round(ts, 3),
-                workload="small instances 0..%d of the batched workload "
-                         "(N ~ U{500..2000}, T=24, distinct matrices), mixed, KKT 1e-4" % (n - 1))
-
-
-def batch_big_run(args):
-    """Batched LPs/s on branch-and-bound variants of the 4224-bus, 48-period
-    LP (0-20% of the commitments fixed; one shared matrix) against the same
-    variants solved one at a time (a batch of one)."""
+def config3_run(args):
+    """The batched workload as stated: branch-and-bound variants of the
+    4224-bus, 48-period LP (a random 0-20% of the commitments fixed, one
+    shared matrix) and small distinct LPs (500-2000 buses, 24 periods), all in
+    one batched solve, mixed precision, KKT 1e-4 each, autotuned SpMV
+    partitions.  Sequential is the same library solving the instances one at a
+    time (a batch of one for a variant, pdhg_solve for a small LP), measured
+    on the first `seq_sample` of each kind and scaled to all of them."""
+    import numpy as np
     import torch
     from paper_2512_06715_amd import ucgen
     from paper_2512_06715_amd.solver import Problem, solve_batch
     lp = ucgen.workload("uc4224_t48")
-    base = Problem(lp, tol=args.tol, precision="mixed", max_iter=args.max_iter)
-    insts = []
+    opts = dict(tol=args.tol, precision="mixed", max_iter=args.max_iter, autotune=1)
+    # verbose: the library prints a progress line every 64 evaluations of the batch
+    base = Problem(lp, verbose=1, **opts)
+    smalls = [ucgen.small_batch_instance(j) for j in range(args.batch_small)]
+    sp = [Problem(s_, **opts) for s_ in smalls]
+    variants = []
     for k in range(args.batch_big):
         v = ucgen.fix_commitments(lp, seed=100 + k)
-        insts.append(dict(base=0, fix_idx=v.meta["fix_idx"], fix_val=v.meta["fix_val"]))
+        variants.append(dict(base=0, fix_idx=v.meta["fix_idx"], fix_val=v.meta["fix_val"]))
+    insts = variants + [dict(base=1 + j) for j in range(len(smalls))]
+    print(f"[bench] batch of {len(insts)} ({len(variants)} variants of uc4224_t48, "
+          f"{len(smalls)} small LPs) ...", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = solve_batch([base], insts)
+    res = solve_batch([base] + sp, insts)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    ok = sum(1 for r in res if r[2]["status"] == 1)
-    ts = 0.0
-    for d in insts:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        solve_batch([base], [d])
-        torch.cuda.synchronize()
-        ts += time.perf_counter() - t0
     base.close()
-    n = len(insts)
-    return dict(instances=n, solved=ok, lps_per_s=round(n / tb, 4),
-                sequential_lps_per_s=round(n / ts, 4), speedup=round(ts / tb, 3),
-                batch_s=round(tb, 3), sequential_s=round(ts, 3),
-                workload="%d branch-and-bound variants of uc4224_t48 (4224 buses, 700 units, "
-                         "5800 lines, 48 periods), mixed, KKT 1e-4" % n)
+    att = [r[2]["attempts"] for r in res]
+    ok = sum(1 for r in res if r[2]["status"] == 1)
+    print(f"[bench] batch: {tb:.1f}s, {ok} of {len(insts)} solved; sequential sample ...",
+          file=sys.stderr, flush=True)
+    seq = Problem(lp, **opts)   # the same base without progress lines
+    t_big, t_small = [], []
+    for d in variants[:args.seq_sample]:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        solve_batch([seq], [d])
+        torch.cuda.synchronize()
+        t_big.append(time.perf_counter() - t1)
+    for p in sp[:args.seq_sample]:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p.solve()
+        torch.cuda.synchronize()
+        t_small.append(time.perf_counter() - t1)
+    seq.close()
+    for p in sp:
+        p.close()
+    est = len(variants) * float(np.mean(t_big or [0.0])) + len(smalls) * float(np.mean(t_small or [0.0]))
+    nv = len(variants)
+    return dict(
+        workload="%d branch-and-bound variants of uc4224_t48 (4224 buses, 700 units, 5800 "
+                 "lines, 48 periods; 0-20%% of the commitments fixed) and %d distinct LPs of "
+                 "500-2000 buses (24 periods), one batched solve, mixed, KKT %g, autotuned "
+                 "partitions" % (nv, len(smalls), args.tol),
+        instances=len(insts), solved=ok, batch_s=round(tb, 3), lps_per_s=round(len(insts) / tb, 4),
+        sequential_s_estimate=round(est, 3),
+        sequential_lps_per_s=round(len(insts) / est, 4) if est > 0 else None,
+        speedup=round(est / tb, 3) if est > 0 else None,
+        sequential_sample="%d variants (%.2f s mean) and %d small LPs (%.2f s mean) solved one at "
+                          "a time, scaled to %d and %d" % (len(t_big), float(np.mean(t_big or [0])),
+                                                           len(t_small), float(np.mean(t_small or [0])),
+                                                           nv, len(smalls)),
+        attempts_variants_mean=round(float(np.mean(att[:nv])), 1) if nv else None,
+        attempts_small_mean=round(float(np.mean(att[nv:])), 1) if smalls else None,
+        attempts_max=int(max(att)), us_per_instance_attempt=round(1e6 * tb / sum(att), 3))
 
 
 def nodes_run(args):
@@ -279,11 +303,13 @@ def main():
     ap.add_argument("--workload", default="uc6717_t96")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--no-compare-fp64", action="store_true")
+    ap.add_argument("--batch-big", type=int, default=96,
+                    help="branch-and-bound variants of the 4224-bus, 48-period LP in the "
+                         "batched workload (one shared matrix)")
     ap.add_argument("--batch-small", type=int, default=32,
-                    help="small instances of the batched workload (0 skips the batch run)")
-    ap.add_argument("--batch-big", type=int, default=0,
-                    help="branch-and-bound variants of the 4224-bus, 48-period LP to batch "
-                         "(one shared matrix; 0 skips this run)")
+                    help="small distinct LPs in the batched workload (both 0 skip it)")
+    ap.add_argument("--seq-sample", type=int, default=4,
+                    help="instances of each kind solved one at a time for the sequential rate")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--nodes", type=int, default=0,
                     help="K > 0: branch-and-bound children of the K most fractional "
@@ -291,6 +317,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
     ap.add_argument("--kernel-attempts", type=int, default=200)
+    ap.add_argument("--cold-attempts", type=int, default=50,
+                    help="attempts timed with the caches flushed before each (0 skips)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="64,192")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -358,22 +386,34 @@ def main():
     elapsed = time.perf_counter() - t0
     attempts = sum(i["attempts"] for i in infos)
 
-    # live per-kernel timing on the library stream
+    # live per-kernel timing on the library stream (warm: the solve's own
+    # operating point), then with L2 and the Infinity Cache flushed
     kt = prob.time_kernels(args.kernel_attempts)
     compact = bool(prob.partition()["compact"])
     vb = 8 if args.precision == "fp64" else 4
     dom = "dual" if kt["dual"] >= kt["primal"] else "primal"
     nbytes = kernel_bytes(dom, lp.m, lp.n, lp.nnz, vb, compact)
     achieved = nbytes / (kt[dom] * 1e-3) / 1e9
+    attempt_bytes = sum(kernel_bytes(k, lp.m, lp.n, lp.nnz, vb, compact) for k in ("primal", "dual"))
     kname = f"k_{dom}"
-    roofline_kernel = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=load_traffic(kname, args.workload, args.precision),
                     kernel=kname, ms_per_launch=round(kt[dom], 5),
                     algorithmic_bytes_per_launch=nbytes,
                     index_form="16-bit tile-relative" if compact else "32-bit CSR",
-                    kernel_ms=dict((k, round(v, 5)) for k, v in kt.items()))
-    roofline = roofline_kernel
+                    kernel_ms=dict((k, round(v, 5)) for k, v in kt.items()),
+                    attempt=dict(algorithmic_bytes=attempt_bytes, ms=round(kt["attempt"], 5),
+                                 frac=round(attempt_bytes / (kt["attempt"] * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS, 4),
+                                 note="both attempt kernels' bytes over the whole attempt "
+                                      "(step control and launch gaps included)"))
+    if args.cold_attempts > 0:
+        kc = prob.time_kernels_cold(args.cold_attempts)
+        roofline["cold"] = dict(
+            kernel_ms=dict((k, round(v, 5)) for k, v in kc.items()),
+            frac=round(nbytes / (kc[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            note="1 GiB read between attempts evicts L2 and the 256 MB Infinity Cache")
     prob.close()
     del DevLP
 
@@ -381,15 +421,11 @@ def main():
     if not args.no_compare_fp64 and args.precision == "mixed":
         print("[bench] plain FP64 solve of the same LP ...", file=sys.stderr, flush=True)
         extra.update(fp64_compare(lp, args))
-    if args.batch_small > 0:
-        print("[bench] batched solve ...", file=sys.stderr, flush=True)
-        extra["batch"] = batch_run(args)
+    if args.batch_big > 0 or args.batch_small > 0:
+        extra["batch"] = config3_run(args)
     if args.nodes > 0:
         print("[bench] branch-and-bound nodes ...", file=sys.stderr, flush=True)
         extra["nodes"] = nodes_run(args)
-    if args.batch_big > 0:
-        print("[bench] batched branch-and-bound variants ...", file=sys.stderr, flush=True)
-        extra["batch_big"] = batch_big_run(args)
     if not args.no_adjoint:
         print("[bench] unrolled solve + adjoint ...", file=sys.stderr, flush=True)
         extra.update(adjoint_run())
@@ -403,6 +439,13 @@ def main():
     if "fp64_time_to_tol_s" in extra:
         extra["mixed_speedup_vs_fp64"] = round(extra["fp64_time_to_tol_s"] / (elapsed / args.steps), 3)
     last = infos[-1]
+    ref = reference_objective(args.workload)
+    extra["objective_error"] = dict(
+        reference=ref, source="tests/golden/lp_refs.json (HiGHS through the oracle package)",
+        relative=(abs(last["primal_obj"] - ref) / abs(ref)) if ref is not None else None,
+        fp64_relative=(abs(extra["fp64_primal_obj"] - ref) / abs(ref))
+        if ref is not None and "fp64_primal_obj" in extra else None,
+        dual_bound_gap=(last["primal_obj"] - last["dual_bound"]) / abs(last["primal_obj"]))
     out = dict(
         metric=METRIC,
         value=round(attempts / elapsed, 1),

@@ -340,6 +340,14 @@ int pdhg_get_partition(pdhg_handle *h, int *out);
  * included).  Precision as set up. */
 int pdhg_time_kernels(pdhg_handle *h, int attempts, double *ms_out);
 
+/* pdhg_time_kernels with cold caches: before each attempt the library reads
+ * flush_bytes of the caller's device buffer `flush` (contents ignored; make it
+ * larger than twice the 256 MB Infinity Cache), which evicts the previous
+ * attempt's lines from L2 and the Infinity Cache, so the kernels fetch the
+ * matrix and vectors from HBM.  Same outputs as pdhg_time_kernels. */
+int pdhg_time_kernels_cold(pdhg_handle *h, int attempts, const void *flush, size_t flush_bytes,
+                           double *ms_out);
+
 #ifdef __cplusplus
 }
 #endif

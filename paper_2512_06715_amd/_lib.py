@@ -85,6 +85,7 @@ SIGNATURES = {
     "pdhg_export_setup": (c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
     "pdhg_spmv": (c_int, [vp, c_int, vp, vp]),
     "pdhg_time_kernels": (c_int, [vp, c_int, ctypes.POINTER(c_dbl)]),
+    "pdhg_time_kernels_cold": (c_int, [vp, c_int, vp, ctypes.c_size_t, vp]),
     "pdhg_get_partition": (c_int, [vp, ctypes.POINTER(c_int)]),
     "pdhg_locality_order": (c_int, [c_i64, c_i64, vp, vp, vp, vp]),
     "pdhg_implied_bounds": (c_int, [vp, vp, vp]),

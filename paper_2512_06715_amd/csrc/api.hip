@@ -2138,7 +2138,8 @@ int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out) {
 
 namespace {
 template <typename T>
-int time_kernels(pdhg_handle *h, int attempts, double *ms) {
+int time_kernels(pdhg_handle *h, int attempts, double *ms, const double *flush = nullptr,
+                 int64_t flush_n = 0) {
   InstData d = base_data(h);
   std::vector<Inst<T>> one{make_inst<T>(h, d, h->it)};
   std::vector<int> act{0};
@@ -2150,6 +2151,9 @@ int time_kernels(pdhg_handle *h, int attempts, double *ms) {
   for (auto &e : ev) HC(hipEventCreate(&e));
   double acc[4] = {0, 0, 0, 0};
   for (int a = 0; a < attempts; a++) {
+    // cold caches: reading flush_n doubles evicts the previous attempt's
+    // lines from L2 and the Infinity Cache (clean lines, no write-back)
+    if (flush) launch_sumsq(flush, flush_n, h->scratch, h->nscratch, h->hs);
     launch_primal<T>(dI, g, h->hs, ev[0], ev[1]);
     launch_dual<T>(dI, g, h->hs, ev[2], ev[3]);
     launch_control<T>(dI, g, h->hs, ev[4], ev[5]);
@@ -2215,6 +2219,19 @@ extern "C" int pdhg_time_kernels(pdhg_handle *h, int attempts, double *ms_out) {
   RC(enter(h));
   int rc = h->o.precision == PDHG_MIXED ? time_kernels<float>(h, attempts, ms_out)
                                         : time_kernels<double>(h, attempts, ms_out);
+  if (rc) return rc;
+  return leave(h);
+}
+
+extern "C" int pdhg_time_kernels_cold(pdhg_handle *h, int attempts, const void *flush,
+                                      size_t flush_bytes, double *ms_out) {
+  if (!h || !ms_out || attempts < 1 || !flush || flush_bytes < 8)
+    return fail(PDHG_ERR_ARG, "bad argument");
+  RC(enter(h));
+  const double *f = (const double *)flush;
+  const int64_t fn = (int64_t)(flush_bytes / 8);
+  int rc = h->o.precision == PDHG_MIXED ? time_kernels<float>(h, attempts, ms_out, f, fn)
+                                        : time_kernels<double>(h, attempts, ms_out, f, fn);
   if (rc) return rc;
   return leave(h);
 }

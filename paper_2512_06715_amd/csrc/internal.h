@@ -12,6 +12,9 @@
 #endif
 // workgroups per instance of the step-control kernel
 #define PDHG_CTL_SPLIT 16
+// partials of each kind (attempt workgroups) up to which one control
+// workgroup reduces an instance alone
+#define PDHG_CTL_SOLO 4096
 // instances per workgroup of the attempt kernels when instances share a matrix
 #define PDHG_PACK 4
 // default length above which a row / column is handled by a workgroup

@@ -34,8 +34,14 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_control(const Inst<T> *__restric
   const AS_C Inst<T> &in = cin(I)[inst];
   CtlState *gst = in.st;
   const int64_t nc = in.w.grid_cols, nr = in.w.grid_rows;
-  const int64_t c0 = nc * part / PDHG_CTL_SPLIT, c1 = nc * (part + 1) / PDHG_CTL_SPLIT;
-  const int64_t r0 = nr * part / PDHG_CTL_SPLIT, r1 = nr * (part + 1) / PDHG_CTL_SPLIT;
+  // an instance with few partials (up to PDHG_CTL_SOLO of each kind) is
+  // reduced and decided by its first workgroup alone: no slice sums, fences
+  // or ticket; the others return
+  const bool solo = nc <= PDHG_CTL_SOLO && nr <= PDHG_CTL_SOLO;
+  if (solo && part != 0) return;
+  const int nsplit = solo ? 1 : PDHG_CTL_SPLIT;
+  const int64_t c0 = nc * part / nsplit, c1 = nc * (part + 1) / nsplit;
+  const int64_t r0 = nr * part / nsplit, r1 = nr * (part + 1) / nsplit;
   const AS_G double *px = gin((const double *)in.w.part_dx2), *py = gin((const double *)in.w.part_dy);
   double v[3] = {0.0, 0.0, 0.0};
   {
@@ -59,28 +65,35 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_control(const Inst<T> *__restric
     }
   }
   block_reduce<3, PDHG_BLOCK>(v, 0u, r);
-  double *stage = in.w.ctl_stage;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < 3; q++) stage[3 * part + q] = r[q];
-    __threadfence();  // the slice sums are visible before the ticket counts them
-    last = atomicAdd(&gst->ticket, 1) == PDHG_CTL_SPLIT - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  // last workgroup: every lane fetches one slice sum or one state word after
-  // its acquire fence (one round trip), then lane 0 combines them in order
   __shared__ double sl[3 * PDHG_CTL_SPLIT];
   __shared__ unsigned long long sw[sizeof(CtlState) / 8];
-  __threadfence();
-  if (threadIdx.x < 3 * PDHG_CTL_SPLIT) sl[threadIdx.x] = gin((const double *)stage)[threadIdx.x];
-  else if (threadIdx.x - 3 * PDHG_CTL_SPLIT < sizeof(CtlState) / 8)
-    sw[threadIdx.x - 3 * PDHG_CTL_SPLIT] =
-        gin((const unsigned long long *)gst)[threadIdx.x - 3 * PDHG_CTL_SPLIT];
-  __syncthreads();
+  if (solo) {
+    if (threadIdx.x < sizeof(CtlState) / 8)
+      sw[threadIdx.x] = gin((const unsigned long long *)gst)[threadIdx.x];
+    if (threadIdx.x < 3) sl[threadIdx.x] = r[threadIdx.x];
+    __syncthreads();
+  } else {
+    double *stage = in.w.ctl_stage;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int q = 0; q < 3; q++) stage[3 * part + q] = r[q];
+      __threadfence();  // the slice sums are visible before the ticket counts them
+      last = atomicAdd(&gst->ticket, 1) == PDHG_CTL_SPLIT - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    // last workgroup: every lane fetches one slice sum or one state word after
+    // its acquire fence (one round trip), then lane 0 combines them in order
+    __threadfence();
+    if (threadIdx.x < 3 * PDHG_CTL_SPLIT) sl[threadIdx.x] = gin((const double *)stage)[threadIdx.x];
+    else if (threadIdx.x - 3 * PDHG_CTL_SPLIT < sizeof(CtlState) / 8)
+      sw[threadIdx.x - 3 * PDHG_CTL_SPLIT] =
+          gin((const unsigned long long *)gst)[threadIdx.x - 3 * PDHG_CTL_SPLIT];
+    __syncthreads();
+  }
   if (threadIdx.x != 0) return;
   double dx2 = 0.0, dy2 = 0.0, inter = 0.0;
-  for (int p = 0; p < PDHG_CTL_SPLIT; p++) {
+  for (int p = 0; p < nsplit; p++) {
     dx2 += sl[3 * p];
     dy2 += sl[3 * p + 1];
     inter += sl[3 * p + 2];

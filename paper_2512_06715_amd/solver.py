@@ -151,6 +151,18 @@ class Problem:
         L.check(lib.pdhg_time_kernels(self.handle, int(attempts), ms))
         return dict(primal=ms[0], dual=ms[1], control=ms[2], attempt=ms[3])
 
+    def time_kernels_cold(self, attempts: int = 50, flush_bytes: int = 1 << 30) -> dict:
+        """time_kernels with the L2 and Infinity Cache flushed before each attempt
+        (a read of a flush_bytes device buffer)."""
+        import torch
+        lib = L.load()
+        ms = (ctypes.c_double * 4)()
+        buf = torch.zeros(flush_bytes // 8, dtype=torch.float64, device="cuda")
+        L.check(lib.pdhg_time_kernels_cold(self.handle, int(attempts),
+                                           ctypes.c_void_p(buf.data_ptr()), int(flush_bytes), ms))
+        del buf
+        return dict(primal=ms[0], dual=ms[1], control=ms[2], attempt=ms[3])
+
     def close(self):
         if getattr(self, "handle", None):
             L.load().pdhg_destroy(self.handle)
