@@ -272,6 +272,27 @@ def nodes_run(args):
     return out
 
 
+def polish_run(args, p, x, y, info):
+    """Feasibility polishing of the last timed solve's point (pdhg_polish to
+    relative residuals 100 times below the solve's tolerance): its time and
+    the residuals before and after."""
+    import torch
+    ptol = args.tol / 100
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, pi = p.polish(x, y, tol=ptol, omega=info["omega"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(workload="%s, the timed solve's point (KKT %g), polished to relative residuals "
+                         "%g" % (args.workload, args.tol, ptol),
+                seconds=round(dt, 3), attempts=pi["attempts"],
+                before=dict(rel_primal=info["rel_primal"], rel_dual=info["rel_dual"],
+                            rel_gap=info["rel_gap"], primal_obj=info["primal_obj"]),
+                after=dict(rel_primal=pi["rel_primal"], rel_dual=pi["rel_dual"],
+                           rel_gap=pi["rel_gap"], primal_obj=pi["primal_obj"],
+                           dual_bound=pi["dual_bound"]))
+
+
 def adjoint_run():
     """Unrolled solve (1000 steps, checkpoints every 50) and its adjoint on the
     2000-bus, 24-period differentiable case."""
@@ -311,6 +332,7 @@ def main():
     ap.add_argument("--seq-sample", type=int, default=4,
                     help="instances of each kind solved one at a time for the sequential rate")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-polish", action="store_true")
     ap.add_argument("--nodes", type=int, default=0,
                     help="K > 0: branch-and-bound children of the K most fractional "
                          "commitments of the 4224-bus LP's root, warm against cold")
@@ -378,7 +400,7 @@ def main():
     t0 = time.perf_counter()
     infos = []
     for s in range(args.steps):
-        _, _, info = prob.solve()
+        xs, ys, info = prob.solve()
         infos.append(info)
         print(f"[bench] step {s}: {info['attempts']} attempts, {info['solve_s']:.2f}s, "
               f"{info['status_name']} kkt={info['rel_kkt']:.2e}", file=sys.stderr, flush=True)
@@ -414,10 +436,13 @@ def main():
             kernel_ms=dict((k, round(v, 5)) for k, v in kc.items()),
             frac=round(nbytes / (kc[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             note="1 GiB read between attempts evicts L2 and the 256 MB Infinity Cache")
+    extra = {}
+    if not args.no_polish:
+        print("[bench] feasibility polish ...", file=sys.stderr, flush=True)
+        extra["polish"] = polish_run(args, prob, xs, ys, infos[-1])
     prob.close()
     del DevLP
 
-    extra = {}
     if not args.no_compare_fp64 and args.precision == "mixed":
         print("[bench] plain FP64 solve of the same LP ...", file=sys.stderr, flush=True)
         extra.update(fp64_compare(lp, args))

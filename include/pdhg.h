@@ -245,6 +245,27 @@ int pdhg_solve_batch(pdhg_handle *const *handles, int n_handles,
                      size_t workspace_bytes, double *const *x, double *const *y,
                      pdhg_info *infos);
 
+/* Feasibility polishing of a point (x, y), e.g. a solve's result, toward a
+ * vertex-ready start for crossover (the PDHG-then-crossover pipeline of the
+ * paper's "PDHG Execution & Crossover Refinement" section): two further PDHG
+ * solves on the handle's matrix, in FP64 whatever opts.precision, adaptive,
+ * restarted, with no infeasibility tests.
+ *   1. Primal feasibility: the LP with c = 0, from (x, 0), until the relative
+ *      primal residual is at most tol; its x is kept.
+ *   2. Dual feasibility: the LP with b = 0 and every finite bound set to 0
+ *      (the same cone of admissible reduced costs), from (0, y), until the
+ *      relative dual residual is at most tol; its y is kept.
+ * x_out, y_out receive the combined point (caller's order, original space,
+ * memory kind of the LP; they may not alias x, y).  info reports the combined
+ * point on the original problem (relative residuals, gap, objectives, dual
+ * bound; status PDHG_OPTIMAL when its relative KKT error is at most
+ * opts.tol, else PDHG_ITER_LIMIT), attempts and restarts of both steps
+ * together.  max_iter: attempts per step (<= 0: opts.max_iter); omega > 0:
+ * initial primal weight of both steps (scaled space, as pdhg_info reports
+ * it; 0: 1).  PDHG_ERR_STATE in the unrolled mode. */
+int pdhg_polish(pdhg_handle *h, const double *x, const double *y, double tol, int64_t max_iter,
+                double omega, double *x_out, double *y_out, pdhg_info *info);
+
 /* pdhg_solve_batch for callers that cannot allocate (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * batched solve and results, with no workspace argument.  Its workspace is a

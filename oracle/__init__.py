@@ -51,7 +51,7 @@ class _Opts(ctypes.Structure):
                 ("pw_theta", ctypes.c_double), ("infeas_every", ctypes.c_int),
                 ("ilo", ctypes.c_void_p), ("ihi", ctypes.c_void_p),
                 ("dinf_eps", ctypes.c_double), ("trace", ctypes.c_void_p),
-                ("trace_cap", ctypes.c_int64)]
+                ("trace_cap", ctypes.c_int64), ("term", ctypes.c_int)]
 
 # fields of one evaluation record of pdhg(..., trace=N)
 TRACE_FIELDS = ("k", "komega_cur", "komega_avg", "komega_last", "komega_prev", "restart",
@@ -217,14 +217,15 @@ INFO_FIELDS = ("status", "attempts", "accepted", "restarts", "pobj", "dobj", "re
 def pdhg(lp, tol=1e-4, max_iter=100000, eval_period=64, step_mode=0, fixed_eta=0.0,
          ruiz_iters=10, pock_chambolle=True, restart=True, use_average=True,
          omega0=0.0, pw_theta=0.5, x0=None, y0=None, infeas_every=4, dinf_eps=1e-8,
-         trace=0):
+         trace=0, term=0):
     """Restarted PDHG in FP64.  Returns (x, y, info dict) in the original space.
     Every `infeas_every` evaluations (0: never) the current y is tested as a
     certificate of primal infeasibility over the implied bounds (status 5),
     then (dinf_eps > 0) the primal displacement since the last restart as a
     ray certifying dual infeasibility (status 6; x is then the ray).
     trace > 0 adds info["trace"]: the first `trace` evaluations that reached
-    the restart decision, one dict of TRACE_FIELDS each."""
+    the restart decision, one dict of TRACE_FIELDS each.  term: the measure
+    held to tol (0 relative KKT error, 1 primal residual, 2 dual residual)."""
     a = _arrs(lp)
     ilo = ihi = None
     if infeas_every > 0:
@@ -233,6 +234,7 @@ def pdhg(lp, tol=1e-4, max_iter=100000, eval_period=64, step_mode=0, fixed_eta=0
               int(ruiz_iters), int(bool(pock_chambolle)), int(bool(restart)),
               int(bool(use_average)), float(omega0), float(pw_theta), int(infeas_every),
               _p(ilo), _p(ihi), float(dinf_eps))
+    o.term = int(term)
     tr = np.zeros((max(int(trace), 1), len(TRACE_FIELDS)))
     if trace > 0:
         o.trace = tr.ctypes.data_as(ctypes.c_void_p)

@@ -318,6 +318,9 @@ typedef struct {
   double *trace;       /* nullable: one record of ORC_TRACE_LEN doubles per
                           evaluation, at most trace_cap records (see below) */
   int64_t trace_cap;
+  int term;            /* the quantity held to tol: 0 the relative KKT error,
+                          1 the relative primal residual, 2 the relative dual
+                          residual (feasibility polishing) */
 } orc_opts;
 
 /* Evaluation trace (instrumentation only; it changes no arithmetic).  Record
@@ -626,12 +629,14 @@ int orc_pdhg(int64_t m, int64_t n, const int32_t *rp0, const int32_t *ci0,
         status = ST_NUMERICAL;
         break;
       }
-      if (ev[1] <= o->tol) {
+      /* the tested measure: [1] relative KKT, [4] primal, [5] dual residual */
+      const int tq = o->term == 1 ? 4 : (o->term == 2 ? 5 : 1);
+      if (ev[tq] <= o->tol) {
         status = ST_OPTIMAL;
         which = 0;
         break;
       }
-      if (have_avg && eva[1] <= o->tol) {
+      if (have_avg && eva[tq] <= o->tol) {
         status = ST_OPTIMAL;
         which = 1;
         break;

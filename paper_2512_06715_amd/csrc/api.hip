@@ -217,6 +217,12 @@ struct pdhg_handle {
   double ur_eta = 0, ur_omega = 0;
   bool ur_valid = false;
 
+  // feasibility polishing (pdhg_polish): the polished primal and dual points
+  // (caller's order, original space), discarded outputs, a zero vector and
+  // the bounds with their finite entries zeroed (scaled space)
+  double *pol_x = nullptr, *pol_y = nullptr, *pol_xd = nullptr, *pol_yd = nullptr,
+         *pol_zero = nullptr, *pol_lz = nullptr, *pol_uz = nullptr;
+
   // the handle's own instance (pdhg_solve) and its cached block graphs
   IterBufs it{};
   GroupDev grp{};
@@ -310,6 +316,13 @@ size_t layout(pdhg_handle *h, void *base) {
   int gc = (int)std::min<int64_t>(n + h->nblk_cols, 0x7fffffff);
   carve_iter(cv, h->it, m, n, gr, gc, mixed);
   carve_group(cv, h->grp, 1);
+  h->pol_x = cv.take<double>(n);
+  h->pol_y = cv.take<double>(m);
+  h->pol_xd = cv.take<double>(n);
+  h->pol_yd = cv.take<double>(m);
+  h->pol_zero = cv.take<double>(std::max(m, n));
+  h->pol_lz = cv.take<double>(n);
+  h->pol_uz = cv.take<double>(n);
   if (h->o.unroll_iters > 0) {
     int64_t K = h->o.unroll_iters;
     int64_t C = h->o.checkpoint_every > 0 ? std::min<int64_t>(h->o.checkpoint_every, K) : K;
@@ -802,6 +815,7 @@ void fill_common(Inst<T> &I, const pdhg_handle *h, const InstData &d, const Iter
   e.bound_allow = h->bound_allow;
   e.ybest = sizeof(T) == 4 ? b.Y[0] : nullptr;
   e.use_average = h->o.use_average;
+  e.term = 0;
   e.restart = h->o.restart;
   e.pw_theta = h->o.pw_update ? h->o.pw_theta : 0.0;
   e.hold_k = 0;
@@ -1668,6 +1682,137 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, do
 }
 
 }  // extern "C"
+
+namespace {
+
+// One FP64 solve of a variant of the handle's problem on its own buffers:
+// data d (scaled), norms of b0 / c0 (original space) for the relative
+// measures, start (x0, y0) and results (xo, yo) in the caller's order and
+// original space, termination on e.term.  The polish steps are adaptive
+// whatever opts.step_mode, test no infeasibility and keep no dual bound.
+int polish_solve(pdhg_handle *h, const InstData &d, const double *b0, const double *c0,
+                 const double *x0, const double *y0, int term, double tol, int64_t max_iter,
+                 double omega0, double t0, double *xo, double *yo, CtlState &fin, int &status) {
+  Inst<double> I = make_inst<double>(h, d, h->it);
+  I.w.adaptive = 1;
+  I.e.term = term;
+  I.e.ilo = I.e.ihi = nullptr;
+  I.e.rylo = I.e.ryhi = nullptr;
+  I.fyk = nullptr;
+  I.e.infeas_period = 0;
+  I.e.dinf_tol = 0.0;
+  I.x0 = x0;
+  I.y0 = y0;
+  I.xout = xo;
+  I.yout = yo;
+  launch_init_ctl(h->v, h->nnz, d.b, d.c, b0, c0, h->m, h->n, h->scratch, h->nscratch, I.st, 0,
+                  0.0, omega0, h->hs);
+  HK();
+  std::vector<Inst<double>> one{I};
+  std::vector<int> act{0}, st(1, 0);
+  std::vector<CtlState> f(1);
+  Groups g{};
+  RC(upload_group<double>(h, h->grp, one, act, g));
+  launch_init_point<double>(h->grp.d64, g, h->hs);
+  HK();
+  RC(run_group<double>(h, h->grp, one, act, tol, max_iter, t0, 0, h->graph[0], false, st, f));
+  launch_unscale<double>(h->grp.d64, g, h->hs);
+  HK();
+  fin = f[0];
+  status = st[0];
+  return PDHG_OK;
+}
+
+}  // namespace
+
+extern "C" int pdhg_polish(pdhg_handle *h, const double *x, const double *y, double tol,
+                           int64_t max_iter, double omega, double *x_out, double *y_out,
+                           pdhg_info *info) {
+  if (!h || !x || !y || !x_out || !y_out || !info) return fail(PDHG_ERR_ARG, "null argument");
+  if (!(tol > 0.0)) return fail(PDHG_ERR_ARG, "tol must be > 0");
+  if (!(omega >= 0.0) || !std::isfinite(omega)) return fail(PDHG_ERR_ARG, "omega must be >= 0");
+  if (h->ur_K > 0) return fail(PDHG_ERR_STATE, "no feasibility polishing in the unrolled mode");
+  RC(enter(h));
+  const double t0 = now_s();
+  const int64_t m = h->m, n = h->n;
+  if (max_iter <= 0) max_iter = h->o.max_iter;
+  // the point, staged in device memory (caller's order, original space)
+  const double *dx = x, *dy = y;
+  if (!h->on_device) {
+    HC(hipMemcpyAsync(h->pol_xd, x, sizeof(double) * n, hipMemcpyHostToDevice, h->hs));
+    HC(hipMemcpyAsync(h->pol_yd, y, sizeof(double) * m, hipMemcpyHostToDevice, h->hs));
+    dx = h->pol_xd;
+    dy = h->pol_yd;
+  }
+  launch_fill(h->pol_zero, 0.0, std::max(m, n), h->hs);
+  launch_zero_finite(h->l, h->pol_lz, n, h->hs);
+  launch_zero_finite(h->u, h->pol_uz, n, h->hs);
+  HK();
+  const double om = omega > 0.0 ? omega : 0.0;
+  // 1. primal feasibility: c = 0, from (x, 0), until the relative primal
+  //    residual is at most tol; its x is kept (in pol_x)
+  InstData dp = base_data(h);
+  dp.c = h->pol_zero;
+  CtlState f1{}, f2{}, f3{};
+  int s1 = 0, s2 = 0, s3 = 0;
+  RC(polish_solve(h, dp, h->b0, h->pol_zero, dx, nullptr, 1, tol, max_iter, om, t0, h->pol_x,
+                  h->pol_y, f1, s1));
+  // 2. dual feasibility: b = 0 and the finite bounds 0 (the same dual cone of
+  //    reduced costs), from (0, y), until the relative dual residual is at
+  //    most tol; its y is kept (in pol_y)
+  InstData dd = base_data(h);
+  dd.b = h->pol_zero;
+  dd.l = h->pol_lz;
+  dd.u = h->pol_uz;
+  RC(polish_solve(h, dd, h->pol_zero, h->c0, nullptr, dy, 2, tol, max_iter, om, t0, h->pol_xd,
+                  h->pol_y, f2, s2));
+  // 3. the combined point on the original problem: one evaluation (no
+  //    attempt), then its dual bound and unscaled result
+  double *xo = h->on_device ? x_out : h->it.ATYA;
+  double *yo = h->on_device ? y_out : h->it.AXA;
+  {
+    InstData d = base_data(h);
+    Inst<double> I = make_inst<double>(h, d, h->it);
+    I.x0 = h->pol_x;
+    I.y0 = h->pol_y;
+    I.xout = xo;
+    I.yout = yo;
+    launch_init_ctl(h->v, h->nnz, d.b, d.c, h->b0, h->c0, m, n, h->scratch, h->nscratch, I.st, 0,
+                    0.0, om, h->hs);
+    HK();
+    std::vector<Inst<double>> i64{I};
+    std::vector<Inst<float>> i32;
+    std::vector<int> act{0}, st(1, 0), final_fp32{0};
+    std::vector<CtlState> fin(1);
+    Groups g{};
+    RC(upload_group<double>(h, h->grp, i64, act, g));
+    launch_init_point<double>(h->grp.d64, g, h->hs);
+    HK();
+    RC(run_group<double>(h, h->grp, i64, act, h->o.tol, 0, t0, 0, h->graph[0], false, st, fin));
+    RC(bound_group(h, h->grp, i64, i32, final_fp32, fin));
+    RC(unscale_group(h, h->grp, i64, i32, final_fp32));
+    f3 = fin[0];
+    s3 = st[0];
+  }
+  if (!h->on_device) {
+    HC(hipMemcpyAsync(x_out, xo, sizeof(double) * n, hipMemcpyDeviceToHost, h->hs));
+    HC(hipMemcpyAsync(y_out, yo, sizeof(double) * m, hipMemcpyDeviceToHost, h->hs));
+  }
+  HC(hipStreamSynchronize(h->hs));
+  (void)s3;
+  fill_info(info, f3, f3.rel_kkt <= h->o.tol ? PDHG_OPTIMAL : PDHG_ITER_LIMIT, 0, h->setup_s,
+            now_s() - t0);
+  info->attempts = f1.k + f2.k;
+  info->accepted = f1.accepted + f2.accepted;
+  info->restarts = f1.restarts + f2.restarts;
+  info->eta = f1.eta;
+  info->omega = f1.omega;
+  // either step stopped short of tol (attempt limit or no progress): the
+  // point's residuals say how far it got
+  (void)s1;
+  (void)s2;
+  return leave(h);
+}
 
 // ---------------------------------------------------------------------------
 // batched solve

@@ -122,6 +122,10 @@ struct EvalView {
   int long_seg;
   // caller's index of each internal row / column (null: same order)
   const int32_t *rperm, *cperm;
+  // the quantity the termination test holds to the tolerance: 0 the relative
+  // KKT error, 1 the relative primal residual, 2 the relative dual residual
+  // (feasibility polishing)
+  int term;
 };
 
 #define EV_ROWQ 10
@@ -149,6 +153,8 @@ void launch_scale_vectors(const double *b0, const double *c0, const double *l0,
                           int64_t m, int64_t n, double *b, double *c, double *l,
                           double *u, hipStream_t s);
 void launch_fill(double *p, double v, int64_t n, hipStream_t s);
+// dst[j] = 0 where src[j] is finite, src[j] (an infinite bound) elsewhere
+void launch_zero_finite(const double *src, double *dst, int64_t n, hipStream_t s);
 void launch_fix_bounds(double *l, double *u, const int32_t *idx, const double *val, int64_t nfix,
                        const int32_t *inv, int64_t n,
                        hipStream_t s);

@@ -561,13 +561,17 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_eval_control(const Inst<T> *__re
   }
   const PointKKT *rep = &pc;
   int which = 0;
+  // the tested quantity: the relative KKT error, or for feasibility
+  // polishing one relative residual alone
+  const double tc = e.term == 1 ? pc.rel_p : (e.term == 2 ? pc.rel_d : pc.rel_kkt);
+  const double ta = e.term == 1 ? pa.rel_p : (e.term == 2 ? pa.rel_d : pa.rel_kkt);
   if (!isfinite(pc.rel_kkt)) {
     st->done = 1;
     st->status = 4;
-  } else if (pc.rel_kkt <= tol) {
+  } else if (tc <= tol) {
     st->done = 1;
     st->status = 1;
-  } else if (avg && pa.rel_kkt <= tol) {
+  } else if (avg && ta <= tol) {
     st->done = 1;
     st->status = 1;
     which = 1;

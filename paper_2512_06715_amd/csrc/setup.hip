@@ -89,6 +89,12 @@ __global__ void k_fill_f64(double *p, double v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+// A bound vector with its finite entries set to zero (infinite ones kept).
+__global__ void k_zero_finite(const double *src, double *dst, int64_t n) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) dst[j] = isfinite(src[j]) ? 0.0 : src[j];
+}
+
 __global__ void k_cast_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = (float)s[i];  // round to nearest even
@@ -418,6 +424,10 @@ void launch_compact(const int32_t *ptr, const int32_t *idx, int64_t rows, uint16
 
 void launch_fill(double *p, double v, int64_t n, hipStream_t s) {
   k_fill_f64<<<grid_for(n), PDHG_BLOCK, 0, s>>>(p, v, n);
+}
+
+void launch_zero_finite(const double *src, double *dst, int64_t n, hipStream_t s) {
+  k_zero_finite<<<grid_for(n), PDHG_BLOCK, 0, s>>>(src, dst, n);
 }
 
 void launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s) {

@@ -101,6 +101,22 @@ class Problem:
                                ctypes.byref(info)))
         return x, y, info.as_dict()
 
+    def polish(self, x, y, tol: float = 1e-8, max_iter: int = 0, omega: float = 0.0):
+        """Feasibility polishing of (x, y): returns (x', y', info dict) with the
+        combined point's measures on the original problem (pdhg_polish)."""
+        lib = L.load()
+        if self.device:
+            import torch
+            xo = torch.empty(self.n, dtype=torch.float64, device="cuda")
+            yo = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        else:
+            x, y = _host(x, np.float64), _host(y, np.float64)
+            xo, yo = np.zeros(self.n), np.zeros(self.m)
+        info = L.PdhgInfo()
+        L.check(lib.pdhg_polish(self.handle, _ptr(x), _ptr(y), float(tol), int(max_iter),
+                                float(omega), _ptr(xo), _ptr(yo), ctypes.byref(info)))
+        return xo, yo, info.as_dict()
+
     def export_setup(self) -> dict:
         lib = L.load()
         out = dict(var_kind=np.zeros(self.n, np.uint8), colptr=np.zeros(self.n + 1, np.int32),
