@@ -293,6 +293,32 @@ def polish_run(args, p, x, y, info):
                            dual_bound=pi["dual_bound"]))
 
 
+def tol_sweep(args, dev_lp):
+    """Attempts and time to relative KKT 1e-3 ... 1e-6 on the benched LP in both
+    precisions (cold starts; each solve capped at args.sweep_max_iter
+    attempts; the library prints one line per evaluation to stderr)."""
+    import torch
+    from paper_2512_06715_amd.solver import Problem
+    out = []
+    for prec in ("mixed", "fp64"):
+        for tol in (1e-3, 1e-4, 1e-5, 1e-6):
+            p = Problem(dev_lp, device=True, tol=tol, max_iter=args.sweep_max_iter, precision=prec,
+                        verbose=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = p.solve()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            p.close()
+            rec = dict(precision=prec, tol=tol, status=info["status_name"], seconds=round(dt, 3),
+                       attempts=info["attempts"], attempts_fp32=info["attempts_fp32"],
+                       rel_kkt=info["rel_kkt"], primal_obj=info["primal_obj"],
+                       dual_bound=info["dual_bound"])
+            print(f"[bench] sweep {json.dumps(rec)}", file=sys.stderr, flush=True)
+            out.append(rec)
+    return out
+
+
 def adjoint_run():
     """Unrolled solve (1000 steps, checkpoints every 50) and its adjoint on the
     2000-bus, 24-period differentiable case."""
@@ -333,6 +359,9 @@ def main():
                     help="instances of each kind solved one at a time for the sequential rate")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-polish", action="store_true")
+    ap.add_argument("--tol-sweep", action="store_true",
+                    help="also solve the benched LP to relative KKT 1e-3 ... 1e-6 in both precisions")
+    ap.add_argument("--sweep-max-iter", type=int, default=1_500_000)
     ap.add_argument("--nodes", type=int, default=0,
                     help="K > 0: branch-and-bound children of the K most fractional "
                          "commitments of the 4224-bus LP's root, warm against cold")
@@ -437,6 +466,8 @@ def main():
             frac=round(nbytes / (kc[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             note="1 GiB read between attempts evicts L2 and the 256 MB Infinity Cache")
     extra = {}
+    if args.tol_sweep:
+        extra["tol_sweep"] = tol_sweep(args, DevLP)
     if not args.no_polish:
         print("[bench] feasibility polish ...", file=sys.stderr, flush=True)
         extra["polish"] = polish_run(args, prob, xs, ys, infos[-1])
