@@ -323,6 +323,14 @@ int pdhg_export_setup(pdhg_handle *h, uint8_t *var_kind, int32_t *colptr,
                       int32_t *rowidx, double *valT, double *val_s, double *Dr,
                       double *Dc);
 
+/* Copy the FP32 data the mixed-precision attempt kernels read (host memory,
+ * caller's order; any pointer may be null): the scaled values of A in CSR
+ * order val_s[nnz], of the transpose valT[nnz] (rows ascending inside each
+ * column), and the scaled b[m], c[n], l[n], u[n], each the round-to-nearest
+ * FP32 cast of the FP64 scaled value.  PDHG_ERR_STATE for an FP64 handle. */
+int pdhg_export_fp32(pdhg_handle *h, float *val_s, float *valT, float *b, float *c, float *l,
+                     float *u);
+
 /* out = A_scaled x (transpose = 0, x[n], out[m]) or A_scaled' x
  * (transpose = 1, x[m], out[n]) with the solver's FP64 SpMV kernels; host
  * memory. */

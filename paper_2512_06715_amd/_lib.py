@@ -75,6 +75,7 @@ SIGNATURES = {
     "pdhg_solve_batch": (c_int, [ctypes.POINTER(vp), c_int, ctypes.POINTER(PdhgInstance),
                                  c_int, vp, ctypes.c_size_t, ctypes.POINTER(vp),
                                  ctypes.POINTER(vp), ctypes.POINTER(PdhgInfo)]),
+    "pdhg_export_fp32": (c_int, [vp, vp, vp, vp, vp, vp, vp]),
     "pdhg_polish": (c_int, [vp, vp, vp, c_dbl, c_i64, c_dbl, vp, vp, ctypes.POINTER(PdhgInfo)]),
     "pdhg_solve_batch_static": (c_int, [ctypes.POINTER(vp), c_int, ctypes.POINTER(PdhgInstance),
                                         c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),

@@ -2249,6 +2249,64 @@ int pdhg_export_setup(pdhg_handle *h, uint8_t *var_kind, int32_t *colptr, int32_
   return leave(h);
 }
 
+int pdhg_export_fp32(pdhg_handle *h, float *val_s, float *valT, float *b, float *c, float *l,
+                     float *u) {
+  if (!h) return fail(PDHG_ERR_ARG, "null handle");
+  if (h->o.precision != PDHG_MIXED) return fail(PDHG_ERR_STATE, "no FP32 copies in FP64 mode");
+  RC(enter(h));
+  const int64_t m = h->m, n = h->n, nnz = h->nnz;
+  std::vector<float> vf(std::max<int64_t>(nnz, 1)), vtf(std::max<int64_t>(nnz, 1)), bf(m), cf(n),
+      lf(n), uf(n);
+  std::vector<int32_t> prp(m + 1), pci(std::max<int64_t>(nnz, 1)), pcp(n + 1),
+      pri(std::max<int64_t>(nnz, 1));
+  auto d2h = [&](void *dst, const void *src, size_t bytes) -> int {
+    HC(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->hs));
+    return PDHG_OK;
+  };
+  if (nnz) {
+    RC(d2h(vf.data(), h->vf, sizeof(float) * nnz));
+    RC(d2h(vtf.data(), h->vtf, sizeof(float) * nnz));
+    RC(d2h(pci.data(), h->ci, sizeof(int32_t) * nnz));
+    RC(d2h(pri.data(), h->ri, sizeof(int32_t) * nnz));
+  }
+  RC(d2h(prp.data(), h->rp, sizeof(int32_t) * (m + 1)));
+  RC(d2h(pcp.data(), h->cp, sizeof(int32_t) * (n + 1)));
+  RC(d2h(bf.data(), h->bf, sizeof(float) * m));
+  RC(d2h(cf.data(), h->cf, sizeof(float) * n));
+  RC(d2h(lf.data(), h->lf, sizeof(float) * n));
+  RC(d2h(uf.data(), h->uf, sizeof(float) * n));
+  HC(hipStreamSynchronize(h->hs));
+  if (!h->rperm) {
+    if (val_s) std::copy(vf.begin(), vf.begin() + nnz, val_s);
+    if (valT) std::copy(vtf.begin(), vtf.begin() + nnz, valT);
+    if (b) std::copy(bf.begin(), bf.end(), b);
+    if (c) std::copy(cf.begin(), cf.end(), c);
+    if (l) std::copy(lf.begin(), lf.end(), l);
+    if (u) std::copy(uf.begin(), uf.end(), u);
+    return leave(h);
+  }
+  // relabelled back into the caller's order through double (exact both ways)
+  auto back = [&](int64_t rows, const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                  const std::vector<float> &val, const std::vector<int32_t> &ro,
+                  const std::vector<int32_t> &co, float *out) {
+    std::vector<double> wide(val.begin(), val.end());
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;
+    unpermute_csr(rows, ptr.data(), idx.data(), wide.data(), ro, co, rp, ci, v);
+    for (int64_t k = 0; k < nnz; k++) out[k] = (float)v[k];
+  };
+  if (val_s) back(m, prp, pci, vf, h->h_rperm, h->h_cperm, val_s);
+  if (valT) back(n, pcp, pri, vtf, h->h_cperm, h->h_rperm, valT);
+  for (int64_t i = 0; i < m; i++)
+    if (b) b[h->h_rperm[i]] = bf[i];
+  for (int64_t j = 0; j < n; j++) {
+    if (c) c[h->h_cperm[j]] = cf[j];
+    if (l) l[h->h_cperm[j]] = lf[j];
+    if (u) u[h->h_cperm[j]] = uf[j];
+  }
+  return leave(h);
+}
+
 int pdhg_spmv(pdhg_handle *h, int transpose, const double *x, double *out) {
   if (!h || !x || !out) return fail(PDHG_ERR_ARG, "null argument");
   RC(enter(h));

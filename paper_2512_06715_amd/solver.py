@@ -126,6 +126,16 @@ class Problem:
                                       ("var_kind", "colptr", "rowidx", "valT", "val_s", "Dr", "Dc")]))
         return out
 
+    def export_fp32(self) -> dict:
+        """The FP32 copies of the mixed-precision path (caller's order)."""
+        lib = L.load()
+        out = dict(val_s=np.zeros(self.nnz, np.float32), valT=np.zeros(self.nnz, np.float32),
+                   b=np.zeros(self.m, np.float32), c=np.zeros(self.n, np.float32),
+                   l=np.zeros(self.n, np.float32), u=np.zeros(self.n, np.float32))
+        L.check(lib.pdhg_export_fp32(self.handle, *[_ptr(out[k]) for k in
+                                     ("val_s", "valT", "b", "c", "l", "u")]))
+        return out
+
     def spmv(self, x, transpose: bool = False) -> np.ndarray:
         lib = L.load()
         x = _host(x, np.float64)

@@ -75,6 +75,29 @@ def test_setup_bit_exact(gpu, oracle_mod, name, reorder):
 
 
 @pytest.mark.parametrize("reorder", [1, 0])
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_casts_bit_exact(gpu, oracle_mod, name, reorder):
+    """The FP32 data of the mixed path are the round-to-nearest casts of the
+    oracle's scaled FP64 values (numpy's float32 conversion), bit for bit, in
+    the caller's order, for A, its transpose and b, c, l, u."""
+    from paper_2512_06715_amd.solver import Problem
+    lp = CASES[name]()
+    print("case fp32 casts", name, reorder, flush=True)
+    p = Problem(lp, precision="mixed", reorder=reorder)
+    g = p.export_fp32()
+    p.close()
+    vs, Dr, Dc = oracle_mod.scale(lp, 10, True)
+    cp, ri, vt = oracle_mod.transpose(lp.m, lp.n, lp.row_ptr, lp.col_idx, vs)
+    f32 = lambda a: np.asarray(a, np.float64).astype(np.float32).view(np.uint32)
+    assert np.array_equal(g["val_s"].view(np.uint32), f32(vs))
+    assert np.array_equal(g["valT"].view(np.uint32), f32(vt))
+    assert np.array_equal(g["b"].view(np.uint32), f32(Dr * lp.b))
+    assert np.array_equal(g["c"].view(np.uint32), f32(Dc * lp.c))
+    assert np.array_equal(g["l"].view(np.uint32), f32(lp.l / Dc))
+    assert np.array_equal(g["u"].view(np.uint32), f32(lp.u / Dc))
+
+
+@pytest.mark.parametrize("reorder", [1, 0])
 @pytest.mark.parametrize("name", ["uc14_t24", "dense_cols"])
 def test_one_attempt(gpu, oracle_mod, name, reorder):
     from paper_2512_06715_amd.solver import Problem
