@@ -81,6 +81,10 @@ enum { PDHG_FP64 = 0, PDHG_MIXED = 1 };
  * CSR: row_ptr[m+1] int32 with row_ptr[0] = 0 and row_ptr[m] = nnz,
  * col_idx[nnz] int32 strictly ascending inside each row, val[nnz] finite.
  * row_kind[m] uint8; b[m], c[n] finite; l[n] may hold -INFINITY, u[n] +INFINITY.
+ * obj_offset: a finite constant of the objective, c'x + obj_offset.  It is added
+ * to the reported primal_obj, dual_obj and dual_bound only: the relative gap and
+ * every termination test use the objectives of min c'x without it, so a solve
+ * takes the same steps whatever the offset (nonfinite: PDHG_ERR_NONFINITE).
  * on_device = 0: host pointers; 1: device pointers (validated on the GPU). */
 typedef struct {
   int64_t m, n, nnz;
@@ -89,6 +93,7 @@ typedef struct {
   const double *val;
   const uint8_t *row_kind;
   const double *b, *c, *l, *u;
+  double obj_offset;
   int on_device;
 } pdhg_lp;
 
@@ -151,6 +156,12 @@ typedef struct {
                              pack of 4 instances per workgroup, the tile's structure
                              loaded once for the pack; 0 (default): one instance per
                              workgroup.  The results do not depend on it */
+  int batch_share_bounds; /* 1 (default): a batched instance whose box differs from its
+                             base's only by fixings to one of the base's own bounds has
+                             the attempt kernels read the base's l, u and a two-bit code
+                             per column (1/4 byte instead of one bound pair per column);
+                             0: every instance with fixings reads bound arrays of its
+                             own.  The results do not depend on it */
 } pdhg_opts;
 
 typedef struct {
@@ -376,6 +387,51 @@ int pdhg_time_kernels(pdhg_handle *h, int attempts, double *ms_out);
  * matrix and vectors from HBM.  Same outputs as pdhg_time_kernels. */
 int pdhg_time_kernels_cold(pdhg_handle *h, int attempts, const void *flush, size_t flush_bytes,
                            double *ms_out);
+
+/* Merge-path CSR SpMV, y = A x, the load-balanced partition of the sparse
+ * products that the PDHG iteration applies twice per step (the A x and A'y
+ * of the "PDHG Background" section): the m row ends and nnz nonzeros form one
+ * merged sequence, and every workgroup and every lane take an equal share of
+ * it whatever the row lengths.  A row's products are rounded on their own and
+ * summed in a fixed order (within a lane in CSR order, then the lanes' and
+ * workgroups' partial sums in order), so repeated calls give the same bits;
+ * the order differs from the attempt kernels' sum in CSR order.
+ *
+ * All pointers are device memory; stream may be null (the null stream).
+ * row_ptr[m+1] int32, col_idx[nnz] int32 in [0, n), val[nnz], x[n], y[m]
+ * (written, not read).  The workspace (256-byte aligned, caller-owned) holds
+ * the plan and the workgroups' carries; its size comes from
+ * pdhg_spmv_merge_workspace_bytes.  m + nnz must stay below 2^31
+ * (PDHG_ERR_ARG); m = 0 is a no-op. */
+int pdhg_spmv_merge_workspace_bytes(int64_t m, int64_t nnz, size_t *bytes);
+
+/* The plan: the start of every workgroup's share, found by a binary search on
+ * the merge path, written into the workspace, once per sparsity structure.
+ * It first checks the structure on the device (row_ptr[0] = 0, nondecreasing,
+ * row_ptr[m] = nnz, 0 <= col_idx < n: else PDHG_ERR_CSR) and synchronizes
+ * the stream to read the result.  Later SpMV calls on the workspace must pass
+ * the same row_ptr and col_idx. */
+int pdhg_spmv_merge_plan(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                         const int32_t *col_idx, void *workspace, size_t ws_bytes, void *stream);
+
+/* y = A x in FP64 / FP32 on a planned workspace; asynchronous on stream.
+ * PDHG_ERR_OOM for a workspace below the needed size. */
+int pdhg_spmv_merge_f64(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                        const double *val, const double *x, double *y, void *workspace,
+                        size_t ws_bytes, void *stream);
+int pdhg_spmv_merge_f32(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                        const float *val, const float *x, float *y, void *workspace,
+                        size_t ws_bytes, void *stream);
+
+/* Average ms of the merge-path SpMV on the handle's own scaled matrices in
+ * its iteration precision (FP32 for PDHG_MIXED): ms_out[0] for A'y (n rows of
+ * the stored transpose), ms_out[1] for A x (m rows), each the SpMV and its
+ * carry fix-up, timed with HIP events on the handle's stream over `attempts`
+ * repetitions after planning both.  The workspace holds both plans:
+ * pdhg_spmv_merge_workspace_bytes(n, nnz) + (m, nnz) bytes.  It overwrites
+ * the handle's iterate buffers (the next solve starts afresh). */
+int pdhg_time_spmv_merge(pdhg_handle *h, int attempts, void *workspace, size_t ws_bytes,
+                         double *ms_out);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,8 @@ vp = ctypes.c_void_p
 class PdhgLP(ctypes.Structure):
     _fields_ = [("m", c_i64), ("n", c_i64), ("nnz", c_i64),
                 ("row_ptr", vp), ("col_idx", vp), ("val", vp), ("row_kind", vp),
-                ("b", vp), ("c", vp), ("l", vp), ("u", vp), ("on_device", c_int)]
+                ("b", vp), ("c", vp), ("l", vp), ("u", vp), ("obj_offset", c_dbl),
+                ("on_device", c_int)]
 
 
 class PdhgOpts(ctypes.Structure):
@@ -38,7 +39,8 @@ class PdhgOpts(ctypes.Structure):
                 ("spmv_direct", c_int), ("long_seg", c_int), ("reorder", c_int),
                 ("compact_index", c_int), ("infeas_every", c_int),
                 ("polish_pw_update", c_int), ("fp32_stall_evals", c_int),
-                ("dinf_tol", c_dbl), ("batch_pack", c_int)]
+                ("dinf_tol", c_dbl), ("batch_pack", c_int),
+                ("batch_share_bounds", c_int)]
 
 
 class PdhgInfo(ctypes.Structure):
@@ -88,6 +90,11 @@ SIGNATURES = {
     "pdhg_spmv": (c_int, [vp, c_int, vp, vp]),
     "pdhg_time_kernels": (c_int, [vp, c_int, ctypes.POINTER(c_dbl)]),
     "pdhg_time_kernels_cold": (c_int, [vp, c_int, vp, ctypes.c_size_t, vp]),
+    "pdhg_spmv_merge_workspace_bytes": (c_int, [c_i64, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "pdhg_spmv_merge_plan": (c_int, [c_i64, c_i64, c_i64, vp, vp, vp, ctypes.c_size_t, vp]),
+    "pdhg_spmv_merge_f64": (c_int, [c_i64, c_i64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+    "pdhg_spmv_merge_f32": (c_int, [c_i64, c_i64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+    "pdhg_time_spmv_merge": (c_int, [vp, c_int, vp, ctypes.c_size_t, vp]),
     "pdhg_get_partition": (c_int, [vp, ctypes.POINTER(c_int)]),
     "pdhg_locality_order": (c_int, [c_i64, c_i64, vp, vp, vp, vp]),
     "pdhg_implied_bounds": (c_int, [vp, vp, vp]),

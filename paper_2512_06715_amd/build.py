@@ -12,7 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpdhg.so")
-SOURCES = ["setup.hip", "attempt.hip", "iterate.hip", "reorder.hip", "implied.hip", "api.hip"]
+SOURCES = ["setup.hip", "attempt.hip", "iterate.hip", "reorder.hip", "implied.hip", "spmv_merge.hip",
+           "api.hip"]
 ARCH = os.environ.get("PDHG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -158,6 +158,7 @@ struct pdhg_handle {
   int64_t m = 0, n = 0, nnz = 0;
   pdhg_opts o{};
   int on_device = 0;
+  double obj_offset = 0.0;  // added to the reported objectives only
   hipStream_t hs = nullptr;
   hipStream_t user = nullptr;
   hipEvent_t ev = nullptr;
@@ -364,6 +365,8 @@ int check_opts(const pdhg_opts *o) {
   if (!(o->dinf_tol >= 0.0) || !isfinite(o->dinf_tol))
     return fail(PDHG_ERR_ARG, "dinf_tol must be finite and >= 0");
   if (o->batch_pack != 0 && o->batch_pack != 1) return fail(PDHG_ERR_ARG, "batch_pack must be 0 or 1");
+  if (o->batch_share_bounds != 0 && o->batch_share_bounds != 1)
+    return fail(PDHG_ERR_ARG, "batch_share_bounds must be 0 or 1");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -379,6 +382,7 @@ int check_lp_shape(const pdhg_lp *lp) {
   if (!lp->row_ptr || !lp->row_kind || !lp->b || !lp->c || !lp->l || !lp->u ||
       (lp->nnz > 0 && (!lp->col_idx || !lp->val)))
     return fail(PDHG_ERR_ARG, "null array in lp");
+  if (!isfinite(lp->obj_offset)) return fail(PDHG_ERR_NONFINITE, "obj_offset is not finite");
   return PDHG_OK;
 }
 
@@ -1066,7 +1070,7 @@ int run_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
 }
 
 void fill_info(pdhg_info *info, const CtlState &s, int status, int64_t attempts_fp32,
-               double setup_s, double solve_s) {
+               double setup_s, double solve_s, double obj_offset) {
   memset(info, 0, sizeof *info);
   info->status = status;
   info->which = s.which;
@@ -1074,8 +1078,8 @@ void fill_info(pdhg_info *info, const CtlState &s, int status, int64_t attempts_
   info->attempts_fp32 = attempts_fp32;
   info->accepted = s.accepted;
   info->restarts = s.restarts;
-  info->primal_obj = s.pobj;
-  info->dual_obj = s.dobj;
+  info->primal_obj = s.pobj + obj_offset;
+  info->dual_obj = s.dobj + obj_offset;
   info->rel_primal = s.rel_p;
   info->rel_dual = s.rel_d;
   info->rel_gap = s.rel_gap;
@@ -1084,7 +1088,7 @@ void fill_info(pdhg_info *info, const CtlState &s, int status, int64_t attempts_
   info->omega = s.omega;
   info->setup_s = setup_s;
   info->solve_s = solve_s;
-  info->dual_bound = s.dual_bound;
+  info->dual_bound = s.dual_bound + obj_offset;  // -INFINITY stays -INFINITY
 }
 
 // Solve a group of prepared instances (start points and result pointers set)
@@ -1314,6 +1318,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->fp32_stall_evals = 300;
   o->dinf_tol = 1e-8;
   o->batch_pack = 0;
+  o->batch_share_bounds = 1;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -1358,6 +1363,7 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
   h->nnz = lp->nnz;
   h->o = *opts;
   h->on_device = lp->on_device;
+  h->obj_offset = lp->obj_offset;
   h->user = (hipStream_t)stream;
   layout(h, (void *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255));
   auto setup_body = [&]() -> int {
@@ -1542,7 +1548,7 @@ int solve_unrolled(pdhg_handle *h, const double *dx0, const double *dy0, double 
   h->ur_eta = st.eta;
   h->ur_omega = st.omega;
   h->ur_valid = true;
-  fill_info(info, st, PDHG_ITER_LIMIT, 0, h->setup_s, now_s() - t0);
+  fill_info(info, st, PDHG_ITER_LIMIT, 0, h->setup_s, now_s() - t0, h->obj_offset);
   return PDHG_OK;
 }
 
@@ -1677,7 +1683,7 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, do
   }
   HC(hipStreamSynchronize(h->hs));
   fill_info(info, fin[0], status[0], h->o.precision == PDHG_MIXED ? att32[0] : 0, h->setup_s,
-            now_s() - t0);
+            now_s() - t0, h->obj_offset);
   return leave(h);
 }
 
@@ -1801,7 +1807,7 @@ extern "C" int pdhg_polish(pdhg_handle *h, const double *x, const double *y, dou
   HC(hipStreamSynchronize(h->hs));
   (void)s3;
   fill_info(info, f3, f3.rel_kkt <= h->o.tol ? PDHG_OPTIMAL : PDHG_ITER_LIMIT, 0, h->setup_s,
-            now_s() - t0);
+            now_s() - t0, h->obj_offset);
   info->attempts = f1.k + f2.k;
   info->accepted = f1.accepted + f2.accepted;
   info->restarts = f1.restarts + f2.restarts;
@@ -1827,6 +1833,8 @@ struct BatchPlan {
   std::vector<uint8_t *> vk;
   std::vector<int32_t *> fix_idx;
   std::vector<double *> fix_val;
+  std::vector<uint32_t *> fixw;  // fixing codes over the base's bounds (attempt kernels)
+  std::vector<int *> fixbad;     // set when the codes cannot express the instance's box
   std::vector<double *> xo, yo;  // staging for host results
   std::vector<double *> x0, y0;  // staging for host warm starts
   GroupDev gd;
@@ -1843,6 +1851,8 @@ size_t batch_layout(pdhg_handle *const *hs, const pdhg_instance *inst, int batch
   P.vk.assign(batch, nullptr);
   P.fix_idx.assign(batch, nullptr);
   P.fix_val.assign(batch, nullptr);
+  P.fixw.assign(batch, nullptr);
+  P.fixbad.assign(batch, nullptr);
   P.xo = P.yo = P.x0 = P.y0 = nd;
   for (int k = 0; k < batch; k++) {
     const pdhg_handle *h = hs[inst[k].base];
@@ -1869,6 +1879,10 @@ size_t batch_layout(pdhg_handle *const *hs, const pdhg_instance *inst, int batch
       if (mixed) {
         P.lf[k] = cv.take<float>(n);
         P.uf[k] = cv.take<float>(n);
+      }
+      if (h->o.batch_share_bounds) {
+        P.fixw[k] = cv.take<uint32_t>((n + 15) / 16);
+        P.fixbad[k] = cv.take<int>(1);
       }
     }
     if (inst[k].n_fix > 0) {
@@ -2000,6 +2014,10 @@ int solve_batch_on(pdhg_handle *const *handles, int n_handles, const pdhg_instan
                           h->hs);
       }
       launch_var_kind(P.l0[k], P.u0[k], n, P.vk[k], h->hs);
+      if (P.fixw[k]) {
+        HC(hipMemsetAsync(P.fixbad[k], 0, sizeof(int), h->hs));
+        launch_fix_codes(P.l0[k], P.u0[k], hb->l0, hb->u0, n, P.fixw[k], P.fixbad[k], h->hs);
+      }
       l0 = P.l0[k];
       u0 = P.u0[k];
     }
@@ -2035,9 +2053,22 @@ int solve_batch_on(pdhg_handle *const *handles, int n_handles, const pdhg_instan
     launch_init_ctl(hb->v, hb->nnz, d.b, d.c, q.b ? P.b0[k] : hb->b0, q.c ? P.c0[k] : hb->c0, m, n,
                     hb->scratch, hb->nscratch, ib.st, hb->o.step_mode, eta0, omega0, h->hs);
     HK();
+    int fix_bad = 1;
+    if (P.fixw[k])
+      HC(hipMemcpyAsync(&fix_bad, P.fixbad[k], sizeof(int), hipMemcpyDeviceToHost, h->hs));
     HC(hipStreamSynchronize(h->hs));  // the base's scratch is reused by the next instance
     i64[k] = make_inst<double>(hb, d, ib);
     i32[k] = make_inst<float>(hb, d, ib);
+    if (!fix_bad) {  // the attempt kernels read the base's bounds and the codes
+      i64[k].w.l = hb->l;
+      i64[k].w.u = hb->u;
+      i64[k].w.fixw = P.fixw[k];
+      if (mixed) {
+        i32[k].w.l = hb->lf;
+        i32[k].w.u = hb->uf;
+        i32[k].w.fixw = P.fixw[k];
+      }
+    }
     if (q.b || q.l || q.u) {  // the base's implied bounds assume its b, l, u
       i64[k].e.ilo = i64[k].e.ihi = nullptr;
       i32[k].e.ilo = i32[k].e.ihi = nullptr;
@@ -2092,7 +2123,7 @@ int solve_batch_on(pdhg_handle *const *handles, int n_handles, const pdhg_instan
   double dt = now_s() - t0;
   for (int k = 0; k < batch; k++)
     fill_info(&infos[k], fin[k], status[k], mixed ? att32[k] : 0, handles[inst[k].base]->setup_s,
-              dt);
+              dt, handles[inst[k].base]->obj_offset);
   for (int i = 0; i < n_handles; i++) RC(leave(handles[i]));
   return PDHG_OK;
 }
@@ -2435,6 +2466,145 @@ extern "C" int pdhg_time_kernels_cold(pdhg_handle *h, int attempts, const void *
   const int64_t fn = (int64_t)(flush_bytes / 8);
   int rc = h->o.precision == PDHG_MIXED ? time_kernels<float>(h, attempts, ms_out, f, fn)
                                         : time_kernels<double>(h, attempts, ms_out, f, fn);
+  if (rc) return rc;
+  return leave(h);
+}
+
+// ---------------------------------------------------------------------------
+// merge-path SpMV
+
+namespace {
+
+#define HCN(call)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(PDHG_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+  } while (0)
+
+int merge_sizes_ok(int64_t m, int64_t nnz) {
+  if (m < 0 || nnz < 0 || m + nnz >= 0x7fffffffLL)
+    return fail(PDHG_ERR_ARG, "m and nnz must be >= 0 with m + nnz < 2^31");
+  return PDHG_OK;
+}
+
+template <typename T>
+int spmv_merge_call(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                    const T *val, const T *x, T *y, void *ws, size_t ws_bytes, void *stream) {
+  RC(merge_sizes_ok(m, nnz));
+  if (m == 0) return PDHG_OK;
+  if (!row_ptr || !y || !ws || (nnz > 0 && (!col_idx || !val || !x)))
+    return fail(PDHG_ERR_ARG, "null argument");
+  if (((uintptr_t)ws & 255) != 0) return fail(PDHG_ERR_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < merge_workspace_bytes(m, nnz))
+    return fail(PDHG_ERR_OOM, "workspace of %zu bytes, need %zu", ws_bytes,
+                merge_workspace_bytes(m, nnz));
+  launch_spmv_merge<T>(row_ptr, col_idx, val, x, y, m, nnz, ws, (hipStream_t)stream);
+  HCN(hipGetLastError());
+  return PDHG_OK;
+}
+
+}  // namespace
+
+extern "C" int pdhg_spmv_merge_workspace_bytes(int64_t m, int64_t nnz, size_t *bytes) {
+  RC(merge_sizes_ok(m, nnz));
+  if (!bytes) return fail(PDHG_ERR_ARG, "null argument");
+  *bytes = merge_workspace_bytes(m, nnz);
+  return PDHG_OK;
+}
+
+extern "C" int pdhg_spmv_merge_plan(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                    const int32_t *col_idx, void *ws, size_t ws_bytes,
+                                    void *stream) {
+  RC(merge_sizes_ok(m, nnz));
+  if (n < 0) return fail(PDHG_ERR_ARG, "n must be >= 0");
+  if (m == 0) return PDHG_OK;
+  if (!row_ptr || !ws || (nnz > 0 && !col_idx)) return fail(PDHG_ERR_ARG, "null argument");
+  if (((uintptr_t)ws & 255) != 0) return fail(PDHG_ERR_ARG, "workspace must be 256-byte aligned");
+  const size_t need = merge_workspace_bytes(m, nnz);
+  if (ws_bytes < need) return fail(PDHG_ERR_OOM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  // the structure check writes its flag into the carry-value area, which
+  // the SpMV overwrites before reading
+  const size_t nwg = (size_t)merge_workgroups(m, nnz);
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  int *bad = (int *)((char *)ws + up(4 * (nwg + 1)) + up(4 * nwg));
+  HCN(hipMemsetAsync(bad, 0, sizeof(int), s));
+  launch_merge_check(row_ptr, col_idx, m, n, nnz, bad, s);
+  HCN(hipGetLastError());
+  int hbad = 1;
+  HCN(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HCN(hipStreamSynchronize(s));
+  if (hbad) return fail(PDHG_ERR_CSR, "row_ptr or col_idx is not a canonical CSR structure");
+  launch_merge_plan(row_ptr, m, nnz, ws, s);
+  HCN(hipGetLastError());
+  return PDHG_OK;
+}
+
+extern "C" int pdhg_spmv_merge_f64(int64_t m, int64_t nnz, const int32_t *row_ptr,
+                                   const int32_t *col_idx, const double *val, const double *x,
+                                   double *y, void *ws, size_t ws_bytes, void *stream) {
+  return spmv_merge_call<double>(m, nnz, row_ptr, col_idx, val, x, y, ws, ws_bytes, stream);
+}
+
+extern "C" int pdhg_spmv_merge_f32(int64_t m, int64_t nnz, const int32_t *row_ptr,
+                                   const int32_t *col_idx, const float *val, const float *x,
+                                   float *y, void *ws, size_t ws_bytes, void *stream) {
+  return spmv_merge_call<float>(m, nnz, row_ptr, col_idx, val, x, y, ws, ws_bytes, stream);
+}
+
+namespace {
+
+template <typename T>
+int time_merge(pdhg_handle *h, int attempts, char *ws, double *ms) {
+  const bool f32 = sizeof(T) == 4;
+  const T *v = f32 ? (const T *)h->vf : (const T *)h->v;
+  const T *vt = f32 ? (const T *)h->vtf : (const T *)h->vt;
+  const IterBufs &b = h->it;
+  // A' y into the average's buffer (n), A x into the next A x buffer (m)
+  const T *xin = f32 ? (const T *)b.Xf[0] : (const T *)b.X[0];
+  const T *yin = f32 ? (const T *)b.Yf[0] : (const T *)b.Y[0];
+  T *aty = f32 ? (T *)b.XSf : (T *)b.XS;
+  T *ax = f32 ? (T *)b.AXf[1] : (T *)b.AX[1];
+  char *wsT = ws, *wsA = ws + merge_workspace_bytes(h->n, h->nnz);
+  launch_merge_plan(h->cp, h->n, h->nnz, wsT, h->hs);
+  launch_merge_plan(h->rp, h->m, h->nnz, wsA, h->hs);
+  HK();
+  hipEvent_t ev[4];
+  for (auto &e : ev) HC(hipEventCreate(&e));
+  double acc[2] = {0, 0};
+  for (int a = 0; a < attempts; a++) {
+    HC(hipEventRecord(ev[0], h->hs));
+    launch_spmv_merge<T>(h->cp, h->ri, vt, yin, aty, h->n, h->nnz, wsT, h->hs);
+    HC(hipEventRecord(ev[1], h->hs));
+    HC(hipEventRecord(ev[2], h->hs));
+    launch_spmv_merge<T>(h->rp, h->ci, v, xin, ax, h->m, h->nnz, wsA, h->hs);
+    HC(hipEventRecord(ev[3], h->hs));
+    HK();
+    HC(hipEventSynchronize(ev[3]));
+    float t;
+    HC(hipEventElapsedTime(&t, ev[0], ev[1]));
+    acc[0] += t;
+    HC(hipEventElapsedTime(&t, ev[2], ev[3]));
+    acc[1] += t;
+  }
+  for (auto &e : ev) HC(hipEventDestroy(e));
+  ms[0] = acc[0] / attempts;
+  ms[1] = acc[1] / attempts;
+  return PDHG_OK;
+}
+
+}  // namespace
+
+extern "C" int pdhg_time_spmv_merge(pdhg_handle *h, int attempts, void *ws, size_t ws_bytes,
+                                    double *ms_out) {
+  if (!h || !ms_out || !ws || attempts < 1) return fail(PDHG_ERR_ARG, "bad argument");
+  if (((uintptr_t)ws & 255) != 0) return fail(PDHG_ERR_ARG, "workspace must be 256-byte aligned");
+  const size_t need = merge_workspace_bytes(h->n, h->nnz) + merge_workspace_bytes(h->m, h->nnz);
+  if (ws_bytes < need) return fail(PDHG_ERR_OOM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  RC(enter(h));
+  int rc = h->o.precision == PDHG_MIXED ? time_merge<float>(h, attempts, (char *)ws, ms_out)
+                                        : time_merge<double>(h, attempts, (char *)ws, ms_out);
   if (rc) return rc;
   return leave(h);
 }

@@ -88,6 +88,10 @@ struct IterView {
   // equality row or pre-projection y > 0) into words [(k - mask_k0) * words]
   uint64_t *mask_x, *mask_y;
   int64_t mask_k0;
+  // non-null: l and u are the base's arrays, shared by the batch, and this
+  // instance's fixings are two-bit codes, sixteen columns per word (1: both
+  // bounds l_j, 2: both u_j); null: l and u are the instance's own
+  const uint32_t *fixw;
 };
 
 // FP64 evaluation view (always FP64 matrix); iterates of type T.
@@ -155,6 +159,18 @@ void launch_scale_vectors(const double *b0, const double *c0, const double *l0,
 void launch_fill(double *p, double v, int64_t n, hipStream_t s);
 // dst[j] = 0 where src[j] is finite, src[j] (an infinite bound) elsewhere
 void launch_zero_finite(const double *src, double *dst, int64_t n, hipStream_t s);
+// merge-path SpMV (spmv_merge.hip)
+int merge_workgroups(int64_t m, int64_t nnz);
+size_t merge_workspace_bytes(int64_t m, int64_t nnz);
+void launch_merge_check(const int32_t *rp, const int32_t *ci, int64_t m, int64_t n, int64_t nnz,
+                        int *bad, hipStream_t s);
+void launch_merge_plan(const int32_t *rp, int64_t m, int64_t nnz, void *ws, hipStream_t s);
+template <typename T>
+void launch_spmv_merge(const int32_t *rp, const int32_t *ci, const T *v, const T *x, T *y,
+                       int64_t m, int64_t nnz, void *ws, hipStream_t s);
+
+void launch_fix_codes(const double *lk, const double *uk, const double *lb, const double *ub,
+                      int64_t n, uint32_t *codes, int *bad, hipStream_t s);
 void launch_fix_bounds(double *l, double *u, const int32_t *idx, const double *val, int64_t nfix,
                        const int32_t *inv, int64_t n,
                        hipStream_t s);

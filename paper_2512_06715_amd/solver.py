@@ -44,7 +44,8 @@ class Problem:
     """An LP set up on the GPU.
 
     `lp` has attributes m, n, row_ptr, col_idx, val, row_kind, b, c, l, u
-    (numpy arrays: host input, or torch CUDA tensors with device=True).
+    (numpy arrays: host input, or torch CUDA tensors with device=True) and
+    optionally obj_offset, a constant added to the reported objectives.
     """
 
     def __init__(self, lp, device: bool = False, stream=None, **opts):
@@ -66,7 +67,7 @@ class Problem:
         self.nnz = nnz
         self._lp = L.PdhgLP(self.m, self.n, nnz, *[_ptr(arrs[k]) for k in
                             ("row_ptr", "col_idx", "val", "row_kind", "b", "c", "l", "u")],
-                            1 if device else 0)
+                            float(getattr(lp, "obj_offset", 0.0)), 1 if device else 0)
         self.opts = default_opts(**opts)
         nbytes = ctypes.c_size_t()
         L.check(lib.pdhg_workspace_bytes(ctypes.byref(self._lp), ctypes.byref(self.opts),
@@ -189,6 +190,23 @@ class Problem:
         del buf
         return dict(primal=ms[0], dual=ms[1], control=ms[2], attempt=ms[3])
 
+    def time_spmv_merge(self, attempts: int = 200) -> dict:
+        """Average ms of the merge-path SpMV on this problem's scaled matrices in
+        its iteration precision: A'y (`transpose`) and A x (`forward`)."""
+        import torch
+        lib = L.load()
+        nb = ctypes.c_size_t()
+        L.check(lib.pdhg_spmv_merge_workspace_bytes(self.n, self.nnz, ctypes.byref(nb)))
+        na = ctypes.c_size_t()
+        L.check(lib.pdhg_spmv_merge_workspace_bytes(self.m, self.nnz, ctypes.byref(na)))
+        ws = torch.empty(nb.value + na.value + 256, dtype=torch.uint8, device="cuda")
+        base = (ws.data_ptr() + 255) & ~255
+        ms = (ctypes.c_double * 2)()
+        L.check(lib.pdhg_time_spmv_merge(self.handle, int(attempts), ctypes.c_void_p(base),
+                                         nb.value + na.value, ms))
+        del ws
+        return dict(transpose=ms[0], forward=ms[1])
+
     def close(self):
         if getattr(self, "handle", None):
             L.load().pdhg_destroy(self.handle)
@@ -227,6 +245,44 @@ def solve(lp, x0=None, y0=None, **opts):
         return p.solve(x0, y0)
     finally:
         p.close()
+
+
+class MergeSpmv:
+    """Merge-path SpMV y = A x on device CSR tensors (int32 row_ptr and
+    col_idx, float64 or float32 values): the plan is made once here, then
+    each call launches on the current torch stream."""
+
+    def __init__(self, row_ptr, col_idx, val, n: int):
+        import torch
+        lib = L.load()
+        self.m = int(row_ptr.numel()) - 1
+        self.n = int(n)
+        self.nnz = int(col_idx.numel())
+        if val.dtype not in (torch.float64, torch.float32) or int(val.numel()) != self.nnz:
+            raise ValueError("val must be float64 or float32 with one entry per nonzero")
+        self.dtype = val.dtype
+        self.rp, self.ci, self.val = row_ptr, col_idx, val
+        nb = ctypes.c_size_t()
+        L.check(lib.pdhg_spmv_merge_workspace_bytes(self.m, self.nnz, ctypes.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        self.ws = (self._ws.data_ptr() + 255) & ~255
+        stream = torch.cuda.current_stream().cuda_stream
+        L.check(lib.pdhg_spmv_merge_plan(self.m, self.n, self.nnz, _ptr(row_ptr), _ptr(col_idx),
+                                         ctypes.c_void_p(self.ws), self.ws_bytes,
+                                         ctypes.c_void_p(stream)))
+
+    def __call__(self, x, out=None):
+        import torch
+        lib = L.load()
+        if x.dtype != self.dtype or int(x.numel()) != self.n:
+            raise ValueError("x must match the matrix's dtype and column count")
+        y = torch.empty(self.m, dtype=self.dtype, device="cuda") if out is None else out
+        fn = lib.pdhg_spmv_merge_f64 if self.dtype == torch.float64 else lib.pdhg_spmv_merge_f32
+        stream = torch.cuda.current_stream().cuda_stream
+        L.check(fn(self.m, self.nnz, _ptr(self.rp), _ptr(self.ci), _ptr(self.val), _ptr(x),
+                   _ptr(y), ctypes.c_void_p(self.ws), self.ws_bytes, ctypes.c_void_p(stream)))
+        return y
 
 
 def solve_batch(problems, instances, stream=None, static=False):

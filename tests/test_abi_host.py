@@ -39,18 +39,19 @@ def test_default_opts():
     assert o.fp32_stall_evals == 300 and o.dinf_tol == 1e-8
 
 
-def _lp_struct(lp):
+def _lp_struct(lp, obj_offset=0.0):
     arrs = [np.ascontiguousarray(lp.row_ptr, np.int32), np.ascontiguousarray(lp.col_idx, np.int32),
             np.ascontiguousarray(lp.val, np.float64), np.ascontiguousarray(lp.row_kind, np.uint8),
             np.ascontiguousarray(lp.b, np.float64), np.ascontiguousarray(lp.c, np.float64),
             np.ascontiguousarray(lp.l, np.float64), np.ascontiguousarray(lp.u, np.float64)]
-    s = L.PdhgLP(lp.m, lp.n, len(lp.col_idx), *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs], 0)
+    s = L.PdhgLP(lp.m, lp.n, len(lp.col_idx), *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs],
+                 obj_offset, 0)
     return s, arrs
 
 
-def _setup_rc(lp, opts=None):
+def _setup_rc(lp, opts=None, obj_offset=0.0):
     lib = L.load()
-    s, keep = _lp_struct(lp)
+    s, keep = _lp_struct(lp, obj_offset)
     o = L.PdhgOpts()
     lib.pdhg_default_opts(ctypes.byref(o))
     if opts:
@@ -125,6 +126,10 @@ def test_setup_rejects_bad_options_and_small_workspace():
 def test_shape_errors():
     lp = ucgen.workload("uc14_t24").copy()
     assert _setup_rc(lp)[0] == -5     # valid LP, no workspace
+    assert _setup_rc(lp, obj_offset=-1e9)[0] == -5
+    for bad in (float("nan"), float("inf")):
+        rc, msg = _setup_rc(lp, obj_offset=bad)
+        assert rc == -4 and "obj_offset" in msg
     lp.m = 0
     assert _setup_rc(lp)[0] == -1
 

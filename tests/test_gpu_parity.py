@@ -304,3 +304,28 @@ def test_lds_and_per_row_partitions_bit_identical(gpu, precision):
     assert i0["attempts"] == i1["attempts"] and i0["accepted"] == i1["accepted"]
     assert np.array_equal(x0.view(np.uint64), x1.view(np.uint64))
     assert np.array_equal(y0.view(np.uint64), y1.view(np.uint64))
+
+
+def test_objective_offset_is_reported_only(gpu):
+    """A constant in the objective shifts the reported objectives and the dual
+    bound by exactly that constant and changes nothing else: the same steps,
+    the same bits of x and y, in a solve and in a batch."""
+    from paper_2512_06715_amd.solver import Problem, solve_batch
+    lp = ucgen.workload("uc14_t24")
+    shifted = lp.copy()
+    shifted.obj_offset = -1234.5
+    print("case objective offset", flush=True)
+    out = []
+    for q in (lp, shifted):
+        p = Problem(q, tol=1e-4, max_iter=400000)
+        out.append(p.solve())
+        (bx, by, bi), = solve_batch([p], [dict(base=0)])
+        out.append((bx, by, bi))
+        p.close()
+    for (x0, y0, i0), (x1, y1, i1) in ((out[0], out[2]), (out[1], out[3])):
+        assert i0["status"] == i1["status"] == 1
+        assert i0["attempts"] == i1["attempts"]
+        assert np.array_equal(x0, x1) and np.array_equal(y0, y1)
+        for key in ("primal_obj", "dual_obj", "dual_bound"):
+            assert i1[key] == i0[key] + shifted.obj_offset, key
+        assert i1["rel_kkt"] == i0["rel_kkt"] and i1["rel_gap"] == i0["rel_gap"]
