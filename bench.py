@@ -54,6 +54,32 @@ def kernel_bytes(kind: str, m: int, n: int, nnz: int, vb: int, compact: bool = T
     raise ValueError(kind)
 
 
+def unit_bytes(kind: str, m: int, n: int, nnz: int, vb: int) -> int:
+    """The method's algorithmic bytes per unit of work as the scope table
+    states them (32-bit indices, each element moved once), vb = 8 or 4:
+    primal: the fused primal step, A' CSR ((4 + vb) nnz + 4(n+1)), gather y
+            (vb m), stream x, c, l, u (4 vb n), write x' and one more column
+            vector (2 vb n);
+    dual:   the fused dual step, A CSR ((4 + vb) nnz + 4(m+1)), gather x
+            (vb n), stream y, b, Ax (3 vb m), write y', Ax' (2 vb m);
+    attempt: both with the Ax cache and the averages, (8 + 2 vb) nnz
+            + (4 + 9 vb) n + (4 + 8 vb) m."""
+    if kind == "primal":
+        return (4 + vb) * nnz + 4 * (n + 1) + vb * m + 6 * vb * n
+    if kind == "dual":
+        return (4 + vb) * nnz + 4 * (m + 1) + vb * n + 5 * vb * m
+    if kind == "attempt":
+        return (8 + 2 * vb) * nnz + (4 + 9 * vb) * n + (4 + 8 * vb) * m
+    raise ValueError(kind)
+
+
+def merge_spmv_bytes(rows: int, gathered: int, nnz: int, vb: int) -> int:
+    """Algorithmic bytes of one unfused SpMV over a 32-bit CSR matrix of
+    `rows` rows: pointers 4(rows+1), indices 4 nnz, values vb nnz, the
+    gathered vector vb gathered, the result vb rows."""
+    return 4 * (rows + 1) + 4 * nnz + vb * nnz + vb * gathered + vb * rows
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     for f in ("attempt.hip", "device.h", "internal.h"):
@@ -368,6 +394,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
     ap.add_argument("--kernel-attempts", type=int, default=200)
+    ap.add_argument("--merge-attempts", type=int, default=100,
+                    help="repetitions of the merge-path SpMV timing (0: skip)")
     ap.add_argument("--cold-attempts", type=int, default=50,
                     help="attempts timed with the caches flushed before each (0 skips)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -443,27 +471,54 @@ def main():
     compact = bool(prob.partition()["compact"])
     vb = 8 if args.precision == "fp64" else 4
     dom = "dual" if kt["dual"] >= kt["primal"] else "primal"
+    ubytes = unit_bytes(dom, lp.m, lp.n, lp.nnz, vb)
     nbytes = kernel_bytes(dom, lp.m, lp.n, lp.nnz, vb, compact)
-    achieved = nbytes / (kt[dom] * 1e-3) / 1e9
+    achieved = ubytes / (kt[dom] * 1e-3) / 1e9
+    attempt_unit = unit_bytes("attempt", lp.m, lp.n, lp.nnz, vb)
     attempt_bytes = sum(kernel_bytes(k, lp.m, lp.n, lp.nnz, vb, compact) for k in ("primal", "dual"))
     kname = f"k_{dom}"
+
+    def frac(b, ms):
+        return round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=load_traffic(kname, args.workload, args.precision),
                     kernel=kname, ms_per_launch=round(kt[dom], 5),
-                    algorithmic_bytes_per_launch=nbytes,
-                    index_form="16-bit tile-relative" if compact else "32-bit CSR",
+                    algorithmic_bytes_per_launch=ubytes,
+                    bytes_unit="fused step with 32-bit indices (bench.unit_bytes)",
+                    moved=dict(bytes_per_launch=nbytes, frac=frac(nbytes, kt[dom]),
+                               index_form="16-bit tile-relative" if compact else "32-bit CSR",
+                               note="the bytes this kernel has to move in its own storage "
+                                    "form (bench.kernel_bytes)"),
+                    other_kernel=dict(
+                        kernel="k_dual" if dom == "primal" else "k_primal",
+                        frac=frac(unit_bytes("dual" if dom == "primal" else "primal",
+                                             lp.m, lp.n, lp.nnz, vb),
+                                  kt["dual" if dom == "primal" else "primal"])),
                     kernel_ms=dict((k, round(v, 5)) for k, v in kt.items()),
-                    attempt=dict(algorithmic_bytes=attempt_bytes, ms=round(kt["attempt"], 5),
-                                 frac=round(attempt_bytes / (kt["attempt"] * 1e-3) / 1e9
-                                            / HBM_PEAK_GBS, 4),
-                                 note="both attempt kernels' bytes over the whole attempt "
-                                      "(step control and launch gaps included)"))
+                    attempt=dict(algorithmic_bytes=attempt_unit, ms=round(kt["attempt"], 5),
+                                 frac=frac(attempt_unit, kt["attempt"]),
+                                 moved_bytes=attempt_bytes,
+                                 moved_frac=frac(attempt_bytes, kt["attempt"]),
+                                 note="a whole attempt with the Ax cache and averages over "
+                                      "its duration (step control and launch gaps included)"))
+    if args.merge_attempts > 0:
+        # the merge-path SpMV on the same scaled (and reordered) matrices, in
+        # the iteration precision: a load-balanced, unfused alternative
+        km = prob.time_spmv_merge(args.merge_attempts)
+        mb = dict(transpose=merge_spmv_bytes(lp.n, lp.m, lp.nnz, vb),
+                  forward=merge_spmv_bytes(lp.m, lp.n, lp.nnz, vb))
+        roofline["spmv_merge"] = dict(
+            (k, dict(ms=round(km[k], 5), algorithmic_bytes=mb[k],
+                     frac=round(mb[k] / (km[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
+            for k in ("transpose", "forward"))
+        roofline["spmv_merge"]["note"] = ("y = A x alone (no fused update), 32-bit CSR, plan "
+                                          "made once; transpose = the primal kernel's A'y")
     if args.cold_attempts > 0:
         kc = prob.time_kernels_cold(args.cold_attempts)
         roofline["cold"] = dict(
             kernel_ms=dict((k, round(v, 5)) for k, v in kc.items()),
-            frac=round(nbytes / (kc[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            frac=frac(ubytes, kc[dom]), moved_frac=frac(nbytes, kc[dom]),
             note="1 GiB read between attempts evicts L2 and the 256 MB Infinity Cache")
     extra = {}
     if args.tol_sweep:

@@ -162,6 +162,12 @@ typedef struct {
                              per column (1/4 byte instead of one bound pair per column);
                              0: every instance with fixings reads bound arrays of its
                              own.  The results do not depend on it */
+  int stream_nt;          /* load policy of the attempt kernels' streams (matrix, read-once
+                             vectors): 1 non-temporal, 0 ordinary loads, -1 (default)
+                             per precision: non-temporal when the larger attempt kernel
+                             moves at least 192 MiB (three quarters of the 256 MiB
+                             Infinity Cache), ordinary below.  The results do not depend
+                             on it */
 } pdhg_opts;
 
 typedef struct {
@@ -364,10 +370,12 @@ int pdhg_implied_bounds(pdhg_handle *h, double *lo, double *hi);
 int pdhg_locality_order(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
                         int32_t *row_order, int32_t *col_order);
 
-/* The SpMV partition in use, out[5]: out[0] tiles per workgroup, out[1] 1 for
+/* The SpMV partition in use, out[7]: out[0] tiles per workgroup, out[1] 1 for
  * per-row loops (0: LDS-staged tiles), out[2] long-segment threshold, out[3]
  * number of long rows plus long columns, out[4] 1 when the attempt kernels
- * read the 16-bit structure (opts.compact_index). */
+ * read the 16-bit structure (opts.compact_index), out[5] and out[6] 1 when
+ * the FP64 and the FP32 attempt kernels use non-temporal stream loads
+ * (opts.stream_nt). */
 int pdhg_get_partition(pdhg_handle *h, int *out);
 
 /* Run `attempts` more attempts from the handle's current iterate (the state
@@ -377,7 +385,8 @@ int pdhg_get_partition(pdhg_handle *h, int *out);
  * projection, long columns included), ms_out[1] dual step (Ax row-dot +
  * projection, long rows included), ms_out[2] step control, ms_out[3] whole
  * attempt (first kernel's start to last kernel's end, launch gaps
- * included).  Precision as set up. */
+ * included).  Precision as set up.  On a handle that has not solved yet the
+ * attempts start from the zero point after 16 untimed ones. */
 int pdhg_time_kernels(pdhg_handle *h, int attempts, double *ms_out);
 
 /* pdhg_time_kernels with cold caches: before each attempt the library reads

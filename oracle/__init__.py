@@ -11,6 +11,7 @@ Contents
   Chambolle-Pock updates plus the adaptive steps and restarts of the PDLP
   method it cites), an independent KKT checker and the unrolled PDHG with
   its forward-mode derivative.
+- `csr_matvec`: the sparse product y = A x by its definition (numpy).
 - `exact.py`: the LP optimum by definition on tiny problems (vertex
   enumeration), a dense bounded simplex, and HiGHS through scipy as a
   library LP solve.
@@ -171,6 +172,22 @@ def transpose(m, n, row_ptr, col_idx, val):
     vt = np.zeros(len(ci), np.float64)
     lib().orc_transpose(m, n, _p(rp), _p(ci), _p(v), _p(cp), _p(ri), _p(vt))
     return cp, ri, vt
+
+
+def csr_matvec(row_ptr, col_idx, val, x):
+    """y = A x by definition: y_i = sum over row i's nonzeros of a_ik x_k, the
+    products and the sum in FP64, in CSR order (the sparse product that both
+    steps of the "PDHG Background" iteration apply).  Also returns
+    s_i = sum_k |a_ik x_k|, which with the row length bounds the rounding of
+    any summation order of the same products."""
+    rp = np.asarray(row_ptr, np.int64)
+    ci = np.asarray(col_idx, np.int64)
+    prod = np.asarray(val, np.float64) * np.asarray(x, np.float64)[ci]
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    m = len(rp) - 1
+    y = np.bincount(rows, weights=prod, minlength=m)
+    s = np.bincount(rows, weights=np.abs(prod), minlength=m)
+    return y, s
 
 
 def pow2_sqrt(M: float) -> float:

@@ -159,6 +159,10 @@ struct pdhg_handle {
   pdhg_opts o{};
   int on_device = 0;
   double obj_offset = 0.0;  // added to the reported objectives only
+  int stream_nt[2] = {1, 1};  // attempt kernels' load policy per precision (FP64, FP32)
+  // the iterate buffers and control state hold a solve's state (pdhg_solve
+  // initialises them; setup leaves the iterate part of the state unset)
+  bool state_ready = false;
   hipStream_t hs = nullptr;
   hipStream_t user = nullptr;
   hipEvent_t ev = nullptr;
@@ -367,6 +371,8 @@ int check_opts(const pdhg_opts *o) {
   if (o->batch_pack != 0 && o->batch_pack != 1) return fail(PDHG_ERR_ARG, "batch_pack must be 0 or 1");
   if (o->batch_share_bounds != 0 && o->batch_share_bounds != 1)
     return fail(PDHG_ERR_ARG, "batch_share_bounds must be 0 or 1");
+  if (o->stream_nt < -1 || o->stream_nt > 1)
+    return fail(PDHG_ERR_ARG, "stream_nt must be -1, 0 or 1");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -703,6 +709,27 @@ int build_compact(pdhg_handle *h) {
   return PDHG_OK;
 }
 
+// Load policy of the attempt kernels' streams per iteration precision
+// (stream_nt[0] FP64, [1] FP32): non-temporal when the larger of the two
+// attempt kernels moves at least three quarters of the 256 MiB Infinity
+// Cache, so that L2 keeps the gathered windows; ordinary loads below, whose
+// lines the Infinity Cache can hold for the next launch.  The bytes are the
+// kernels' own storage form (structure, values, the gathered vector, the
+// streamed, written and folded vectors).
+void set_stream_policy(pdhg_handle *h) {
+  const double m = (double)h->m, n = (double)h->n, nnz = (double)h->nnz;
+  auto structure = [&](double r) {
+    return h->compact ? 2 * r + 8 * ceil(r / PDHG_TILE) + 2 * nnz : 4 * (r + 1) + 4 * nnz;
+  };
+  for (int f = 0; f < 2; f++) {
+    const double vb = f ? 4.0 : 8.0;
+    const double primal = structure(n) + vb * nnz + vb * m + 7 * vb * n;
+    const double dual = structure(m) + vb * nnz + vb * n + 7 * vb * m + m;
+    const bool big = std::max(primal, dual) >= 0.75 * 256.0 * 1024 * 1024;
+    h->stream_nt[f] = h->o.stream_nt < 0 ? (big ? 1 : 0) : h->o.stream_nt;
+  }
+}
+
 // Rows and columns longer than the partition's threshold get a workgroup each.
 int build_long_lists(pdhg_handle *h) {
   std::vector<int32_t> lr, lc;
@@ -920,6 +947,7 @@ int upload_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
   g.n_lcols = pre[5 * c1 + na];
   g.compact = 1;
   for (int k = 0; k < na; k++) g.compact = g.compact && sel[k].w.cix16 != nullptr;
+  g.nt = h->stream_nt[sizeof(T) == 4];
   g.interleave = na > 1;
   for (int k = 1; k < na && g.interleave; k++) {
     const IterView<T> &a = sel[0].w, &b = sel[k].w;
@@ -1319,6 +1347,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->dinf_tol = 1e-8;
   o->batch_pack = 0;
   o->batch_share_bounds = 1;
+  o->stream_nt = -1;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -1413,6 +1442,7 @@ int pdhg_setup(const pdhg_lp *lp, const pdhg_opts *opts, void *workspace, size_t
     HK();
     if (h->o.reorder) RC(reorder_problem(h));
     RC(build_compact(h));
+    set_stream_policy(h);
     RC(upload_implied_bounds(h));
     // long rows and columns (handled by a workgroup each in the iteration)
     h->hrp.resize(m + 1);
@@ -1661,6 +1691,7 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, do
       HC(hipMemcpyAsync(y, yo, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->hs));
     }
     HC(hipStreamSynchronize(h->hs));
+    h->state_ready = true;
     info->solve_s = now_s() - t0;
     return leave(h);
   }
@@ -1682,6 +1713,7 @@ int pdhg_solve(pdhg_handle *h, const double *x0, const double *y0, double *x, do
     HC(hipMemcpyAsync(y, yo, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->hs));
   }
   HC(hipStreamSynchronize(h->hs));
+  h->state_ready = true;
   fill_info(info, fin[0], status[0], h->o.precision == PDHG_MIXED ? att32[0] : 0, h->setup_s,
             now_s() - t0, h->obj_offset);
   return leave(h);
@@ -2380,6 +2412,14 @@ int time_kernels(pdhg_handle *h, int attempts, double *ms, const double *flush =
   Groups g{};
   RC(upload_group<T>(h, h->grp, one, act, g));
   const Inst<T> *dI = dev_insts<T>(h->grp);
+  if (!h->state_ready) {
+    // no solve has set the iterates and the control state (the buffer
+    // index, steps, weights): start from the zero point, a few attempts in
+    launch_init_point<T>(dI, g, h->hs);
+    for (int i = 0; i < 16; i++) launch_attempt<T>(dI, g, h->hs);
+    HK();
+    h->state_ready = true;
+  }
   // the start/stop events of each kernel carry its dispatch's own timestamps
   hipEvent_t ev[6];
   for (auto &e : ev) HC(hipEventCreate(&e));
@@ -2445,6 +2485,8 @@ extern "C" int pdhg_get_partition(pdhg_handle *h, int *out) {
   out[2] = h->long_seg;
   out[3] = h->n_long_rows + h->n_long_cols;
   out[4] = h->compact ? 1 : 0;
+  out[5] = h->stream_nt[0];
+  out[6] = h->stream_nt[1];
   return PDHG_OK;
 }
 

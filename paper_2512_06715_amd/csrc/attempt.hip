@@ -27,11 +27,17 @@ namespace {
 #define TILE_CAP (8 * PDHG_TILE)  // nonzeros of a tile staged in LDS
 #define TILE_U 4       // nonzeros per lane loaded before their gathers
 
-// Streams read exactly once per launch bypass the cache hierarchy's reuse
-// policy so that L2 keeps the gathered vector windows.
-template <typename T>
+// Streams read exactly once per launch: with NT they bypass the cache
+// hierarchy's reuse policy so that L2 keeps the gathered vector windows
+// (when a launch's bytes exceed the Infinity Cache); without it they are
+// ordinary loads, whose lines the Infinity Cache can still hold for the
+// next launch (when they fit).
+template <bool NT, typename T>
 __device__ __forceinline__ T ld_stream(const AS_G T *p) {
-  return __builtin_nontemporal_load(p);
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
 }
 
 // Iterate stores of the attempt kernels.
@@ -49,7 +55,7 @@ __device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, 
 // tile-relative form (row ends `ofs` counted from the tile's first nonzero,
 // indices `ix16` counted from the tile's smallest index `tb`).  Row i of the
 // tile is lane threadIdx.x.
-template <bool C>
+template <bool C, bool NT>
 struct TileIx {
   const AS_G int32_t *ptr, *idx;
   const AS_G uint16_t *ofs, *ix16;
@@ -57,9 +63,9 @@ struct TileIx {
   // index of nonzero k: streamed (read once per launch) or cached
   __device__ __forceinline__ int col_stream(int k) const {
     if constexpr (C)
-      return tb + (int)ld_stream(ix16 + k);
+      return tb + (int)ld_stream<NT>(ix16 + k);
     else
-      return ld_stream(idx + k);
+      return ld_stream<NT>(idx + k);
   }
   __device__ __forceinline__ int col(int k) const {
     if constexpr (C)
@@ -109,8 +115,8 @@ struct Pair<double> {
 // their slots; lanes past the last pair repeat it and write the same values.
 // The lane's row bounds (rs, re) are loaded after the first loads of the
 // stream.
-template <typename T>
-__device__ __forceinline__ void stage_pairs(const TileIx<true> &ix, const AS_G T *v,
+template <typename T, bool NT>
+__device__ __forceinline__ void stage_pairs(const TileIx<true, NT> &ix, const AS_G T *v,
                                             const AS_G T *x, int base, int top, T *lds, int64_t i,
                                             bool valid, int &rs, int &re) {
   typedef typename Pair<T>::type T2;
@@ -126,8 +132,8 @@ __device__ __forceinline__ void stage_pairs(const TileIx<true> &ix, const AS_G T
     for (int q = 0; q < TP; q++) {
       int p = p0 + q * PDHG_TILE + (int)threadIdx.x;
       int pc = p < npair ? p : npair - 1;
-      w[q] = ld_stream(iw + pc);
-      vv[q] = ld_stream(vw + pc);
+      w[q] = ld_stream<NT>(iw + pc);
+      vv[q] = ld_stream<NT>(vw + pc);
     }
     if (p0 == 0 && valid) ix.bounds(i, base, rs, re);
 #pragma unroll
@@ -145,8 +151,8 @@ __device__ __forceinline__ void stage_pairs(const TileIx<true> &ix, const AS_G T
   }
 }
 
-template <typename T, bool C>
-__device__ __forceinline__ T tile_rowdot(const TileIx<C> &ix, const AS_G T *v, const AS_G T *x,
+template <typename T, bool C, bool NT>
+__device__ __forceinline__ T tile_rowdot(const TileIx<C, NT> &ix, const AS_G T *v, const AS_G T *x,
                                          int64_t i, bool valid, int base, int top, int long_seg,
                                          T *lds, int direct, bool &mine) {
   const int cnt = top - base;
@@ -156,7 +162,7 @@ __device__ __forceinline__ T tile_rowdot(const TileIx<C> &ix, const AS_G T *v, c
     const int off = base & 1;  // slot of the tile's first entry
     if constexpr (C) {
       if (cnt > 0)
-        stage_pairs<T>(ix, v, x, base, top, lds, i, valid, rs, re);
+        stage_pairs<T, NT>(ix, v, x, base, top, lds, i, valid, rs, re);
       else if (valid)
         ix.bounds(i, base, rs, re);
     }
@@ -174,7 +180,7 @@ __device__ __forceinline__ T tile_rowdot(const TileIx<C> &ix, const AS_G T *v, c
         int k = k0 + q * PDHG_TILE + (int)threadIdx.x;
         int kc = base + (k < cnt ? k : cnt - 1);
         id[q] = ix.col_stream(kc);
-        vv[q] = ld_stream(v + kc);
+        vv[q] = ld_stream<NT>(v + kc);
       }
       if (k0 == 0 && valid) ix.bounds(i, base, rs, re);
 #pragma unroll
@@ -298,7 +304,7 @@ __device__ __forceinline__ void primal_long(const AS_C IterView<T> &w, const AS_
   }
 }
 
-template <typename T, bool C>
+template <typename T, bool C, bool NT>
 __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ __align__(16) T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -338,15 +344,15 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
     T xj = 0, cj = 0, lj = 0, uj = 0, xsj = 0;
     if (j < n) {
       xj = x[j];
-      cj = ld_stream(c + j);
-      lj = ld_stream(l + j);
-      uj = ld_stream(u + j);
+      cj = ld_stream<NT>(c + j);
+      lj = ld_stream<NT>(l + j);
+      uj = ld_stream<NT>(u + j);
       if (fixw) fixed_box<T>(fixw, j, lj, uj);
       if (fold_read) xsj = xs[j];
     }
-    const TileIx<C> ix{cp, ri, gin(w.cofs), gin(w.rix16), C ? cin(w.tb_cols)[t] : 0};
+    const TileIx<C, NT> ix{cp, ri, gin(w.cofs), gin(w.rix16), C ? cin(w.tb_cols)[t] : 0};
     bool mine;
-    T s = tile_rowdot<T, C>(ix, vt, y, j, j < n, base, top, long_seg, lds, direct, mine);
+    T s = tile_rowdot<T, C, NT>(ix, vt, y, j, j < n, base, top, long_seg, lds, direct, mine);
     bool in = false;
     if (mine)
       in = primal_finish<T>(j, s, tau, xj, cj, lj, uj, xn, xs, xsj, pend, fresh, d2[0]);
@@ -400,7 +406,7 @@ __device__ __forceinline__ void dual_long(const AS_C IterView<T> &w, const AS_C 
   }
 }
 
-template <typename T, bool C>
+template <typename T, bool C, bool NT>
 __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ __align__(16) T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -442,13 +448,13 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
     if (i < m) {
       yi = y[i];
       axi = ax[i];
-      bi = ld_stream(bb + i);
+      bi = ld_stream<NT>(bb + i);
       ki = kind[i];
       if (fold_read) ysi = ys[i];
     }
-    const TileIx<C> ix{rp, ci, gin(w.rofs), gin(w.cix16), C ? cin(w.tb_rows)[t] : 0};
+    const TileIx<C, NT> ix{rp, ci, gin(w.rofs), gin(w.cix16), C ? cin(w.tb_rows)[t] : 0};
     bool mine;
-    T s = tile_rowdot<T, C>(ix, v, xn, i, i < m, base, top, long_seg, lds, direct, mine);
+    T s = tile_rowdot<T, C, NT>(ix, v, xn, i, i < m, base, top, long_seg, lds, direct, mine);
     bool in = false;
     if (mine)
       in = dual_finish<T>(i, s, sigma, yi, axi, bi, ki, yn, axn, ys, ysi, pend, fresh, acc[0],
@@ -497,8 +503,8 @@ __device__ __forceinline__ void stage_structure(const AS_G uint16_t *ix16, const
     for (int q = 0; q < TP; q++) {
       int p = p0 + q * PDHG_TILE + (int)threadIdx.x;
       int pc = p < npair ? p : npair - 1;
-      w[q] = ld_stream(iw + pc);
-      vv[q] = ld_stream(vw + pc);
+      w[q] = ld_stream<true>(iw + pc);
+      vv[q] = ld_stream<true>(vw + pc);
     }
 #pragma unroll
     for (int q = 0; q < TP; q++) {
@@ -585,9 +591,9 @@ __global__ __launch_bounds__(PDHG_TILE) void k_primal_pack(const Inst<T> *__rest
       y[q] = gin((const T *)w.Y[cur]);
       if (valid) {
         xj[q] = gin((const T *)w.X[cur])[j];
-        cj[q] = ld_stream(gin(w.c) + j);
-        lj[q] = ld_stream(gin(w.l) + j);
-        uj[q] = ld_stream(gin(w.u) + j);
+        cj[q] = ld_stream<true>(gin(w.c) + j);
+        lj[q] = ld_stream<true>(gin(w.l) + j);
+        uj[q] = ld_stream<true>(gin(w.u) + j);
         if (w.fixw) fixed_box<T>(gin(w.fixw), j, lj[q], uj[q]);
         if (st->pending > 0.0 && !st->fresh) xsj[q] = gin((const T *)w.XS)[j];
       }
@@ -597,7 +603,7 @@ __global__ __launch_bounds__(PDHG_TILE) void k_primal_pack(const Inst<T> *__rest
   if (staged && top > base) stage_structure<T>(gin(w0.rix16), gin(w0.vt), base, top, sidx, sval);
   int rs = 0, re = 0;
   if (valid) {
-    const TileIx<true> ix{nullptr, nullptr, gin(w0.cofs), gin(w0.rix16), tbase};
+    const TileIx<true, true> ix{nullptr, nullptr, gin(w0.cofs), gin(w0.rix16), tbase};
     ix.bounds(j, base, rs, re);
   }
   __syncthreads();
@@ -670,7 +676,7 @@ __global__ __launch_bounds__(PDHG_TILE) void k_dual_pack(const Inst<T> *__restri
       if (valid) {
         yi[q] = gin((const T *)w.Y[cur])[i];
         axi[q] = gin((const T *)w.AX[cur])[i];
-        bi[q] = ld_stream(gin(w.b) + i);
+        bi[q] = ld_stream<true>(gin(w.b) + i);
         if (st->pending > 0.0 && !st->fresh) ysi[q] = gin((const T *)w.YS)[i];
       }
     }
@@ -680,7 +686,7 @@ __global__ __launch_bounds__(PDHG_TILE) void k_dual_pack(const Inst<T> *__restri
   if (staged && top > base) stage_structure<T>(gin(w0.cix16), gin(w0.v), base, top, sidx, sval);
   int rs = 0, re = 0;
   if (valid) {
-    const TileIx<true> ix{nullptr, nullptr, gin(w0.rofs), gin(w0.cix16), tbase};
+    const TileIx<true, true> ix{nullptr, nullptr, gin(w0.rofs), gin(w0.cix16), tbase};
     ix.bounds(i, base, rs, re);
   }
   __syncthreads();
@@ -722,24 +728,24 @@ __global__ __launch_bounds__(PDHG_TILE) void k_dual_pack(const Inst<T> *__restri
 // With events, the kernel is launched through hipExtLaunchKernelGGL, whose
 // start/stop events take the dispatch's own timestamps (the kernel's
 // duration, without launch gaps).
-template <typename T, bool C>
+template <typename T, bool C, bool NT>
 void launch_primal_as(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
                       hipEvent_t t1) {
   if (t0)
-    hipExtLaunchKernelGGL(k_primal<T, C>, dim3(grid_of(g.n_primal)), dim3(PDHG_TILE), 0, s, t0, t1,
-                          0, I, g);
+    hipExtLaunchKernelGGL(k_primal<T, C, NT>, dim3(grid_of(g.n_primal)), dim3(PDHG_TILE), 0, s, t0,
+                          t1, 0, I, g);
   else
-    k_primal<T, C><<<grid_of(g.n_primal), PDHG_TILE, 0, s>>>(I, g);
+    k_primal<T, C, NT><<<grid_of(g.n_primal), PDHG_TILE, 0, s>>>(I, g);
 }
 
-template <typename T, bool C>
+template <typename T, bool C, bool NT>
 void launch_dual_as(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
                     hipEvent_t t1) {
   if (t0)
-    hipExtLaunchKernelGGL(k_dual<T, C>, dim3(grid_of(g.n_dual)), dim3(PDHG_TILE), 0, s, t0, t1, 0,
-                          I, g);
+    hipExtLaunchKernelGGL(k_dual<T, C, NT>, dim3(grid_of(g.n_dual)), dim3(PDHG_TILE), 0, s, t0, t1,
+                          0, I, g);
   else
-    k_dual<T, C><<<grid_of(g.n_dual), PDHG_TILE, 0, s>>>(I, g);
+    k_dual<T, C, NT><<<grid_of(g.n_dual), PDHG_TILE, 0, s>>>(I, g);
 }
 
 template <typename T>
@@ -754,9 +760,11 @@ void launch_primal(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t 
     return;
   }
   if (g.compact)
-    launch_primal_as<T, true>(I, g, s, t0, t1);
+    g.nt ? launch_primal_as<T, true, true>(I, g, s, t0, t1)
+         : launch_primal_as<T, true, false>(I, g, s, t0, t1);
   else
-    launch_primal_as<T, false>(I, g, s, t0, t1);
+    g.nt ? launch_primal_as<T, false, true>(I, g, s, t0, t1)
+         : launch_primal_as<T, false, false>(I, g, s, t0, t1);
 }
 
 template <typename T>
@@ -770,9 +778,11 @@ void launch_dual(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0
     return;
   }
   if (g.compact)
-    launch_dual_as<T, true>(I, g, s, t0, t1);
+    g.nt ? launch_dual_as<T, true, true>(I, g, s, t0, t1)
+         : launch_dual_as<T, true, false>(I, g, s, t0, t1);
   else
-    launch_dual_as<T, false>(I, g, s, t0, t1);
+    g.nt ? launch_dual_as<T, false, true>(I, g, s, t0, t1)
+         : launch_dual_as<T, false, false>(I, g, s, t0, t1);
 }
 
 #define INST(T)                                                                             \

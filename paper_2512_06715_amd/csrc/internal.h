@@ -235,6 +235,9 @@ struct Groups {
   // PDHG_PACK at a time by the pack kernels, whose grids are these
   int pack;
   int n_primal_pack, n_dual_pack;
+  // 1: the attempt kernels stream the matrix and the read-once vectors with
+  // non-temporal loads; 0: ordinary loads
+  int nt;
 };
 
 // ---------------------------------------------------------------------------

@@ -166,10 +166,10 @@ class Problem:
 
     def partition(self) -> dict:
         """The SpMV partition in use (chosen by the autotuner or the options)."""
-        out = (ctypes.c_int * 5)()
+        out = (ctypes.c_int * 7)()
         L.check(L.load().pdhg_get_partition(self.handle, out))
         return dict(tiles_per_block=out[0], direct=out[1], long_seg=out[2], long_segments=out[3],
-                    compact=out[4])
+                    compact=out[4], stream_nt_fp64=out[5], stream_nt_fp32=out[6])
 
     def time_kernels(self, attempts: int = 200) -> dict:
         """Average ms per launch of the attempt kernels, timed with HIP events."""

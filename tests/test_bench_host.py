@@ -47,6 +47,21 @@ def test_kernel_bytes_closed_form():
         bench.kernel_bytes("control", m, n, nnz, 4)
 
 
+def test_unit_bytes_match_the_scope_table():
+    """The per-unit figures of the scope table on the paper-scale LP: fused
+    primal step 270 / 156 MB, fused dual step 202 / 119 MB, full PDLP attempt
+    16 nnz + 40 n + 36 m (FP32) and 24 nnz + 76 n + 68 m (FP64)."""
+    m, n, nnz = sizes()
+    assert round(bench.unit_bytes("primal", m, n, nnz, 8) / 1e6) == 270
+    assert round(bench.unit_bytes("primal", m, n, nnz, 4) / 1e6) == 156
+    assert round(bench.unit_bytes("dual", m, n, nnz, 8) / 1e6) == 202
+    assert round(bench.unit_bytes("dual", m, n, nnz, 4) / 1e6) == 119
+    assert bench.unit_bytes("attempt", m, n, nnz, 4) == 16 * nnz + 40 * n + 36 * m
+    assert bench.unit_bytes("attempt", m, n, nnz, 8) == 24 * nnz + 76 * n + 68 * m
+    # the merge-path SpMV alone, FP32: 8 nnz + 4 (m + 1) + 4 n + 4 m
+    assert bench.merge_spmv_bytes(m, n, nnz, 4) == 8 * nnz + 4 * (m + 1) + 4 * n + 4 * m
+
+
 def test_traffic_records_follow_the_source(tmp_path, monkeypatch):
     """A counter record counts only for the kernel source it was taken on
     (its hash); for any other source the bench reports no traffic."""

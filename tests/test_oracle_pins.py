@@ -92,6 +92,33 @@ def test_transpose_matches_scipy(oracle_mod, name):
     assert np.array_equal(vt2.view(np.uint64), lp.val.view(np.uint64))
 
 
+def test_csr_matvec_matches_exact_row_sums(oracle_mod):
+    """y = A x against each row's exactly rounded sum (math.fsum of the
+    products, a different summation) on ragged rows with empty ones, and
+    against a dense product; s bounds every summation order's error."""
+    import math
+    rng = np.random.default_rng(5)
+    m, n = 300, 200
+    lens = rng.integers(0, 30, m)
+    lens[[0, 17, 299]] = 0
+    lens[5] = 2000 // 10
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(n, k, replace=False)) for k in lens]).astype(np.int32)
+    val = rng.standard_normal(rp[-1]) * 10.0 ** rng.integers(-3, 4, rp[-1])
+    x = rng.standard_normal(n)
+    y, sabs = oracle_mod.csr_matvec(rp, ci, val, x)
+    dense = np.zeros((m, n))
+    for i in range(m):
+        dense[i, ci[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    for i in range(m):
+        prods = val[rp[i]:rp[i + 1]] * x[ci[rp[i]:rp[i + 1]]]
+        exact = math.fsum(prods)
+        assert abs(y[i] - exact) <= (lens[i] + 1) * 2.0 ** -53 * sabs[i], i
+        assert sabs[i] == pytest.approx(np.abs(prods).sum(), rel=1e-15, abs=0)
+    np.testing.assert_allclose(y, dense @ x, rtol=0, atol=1e-12 * (1 + sabs.max()))
+    assert y[0] == 0.0 and y[17] == 0.0 and y[299] == 0.0
+
+
 def test_scaling_is_exact_power_of_two_equilibration(oracle_mod):
     lp = ucgen.workload("uc1000_t48")
     vs, Dr, Dc = oracle_mod.scale(lp, 10, True)
