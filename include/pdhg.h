@@ -156,12 +156,6 @@ typedef struct {
                              pack of 4 instances per workgroup, the tile's structure
                              loaded once for the pack; 0 (default): one instance per
                              workgroup.  The results do not depend on it */
-  int batch_share_bounds; /* 1 (default): a batched instance whose box differs from its
-                             base's only by fixings to one of the base's own bounds has
-                             the attempt kernels read the base's l, u and a two-bit code
-                             per column (1/4 byte instead of one bound pair per column);
-                             0: every instance with fixings reads bound arrays of its
-                             own.  The results do not depend on it */
   int stream_nt;          /* load policy of the attempt kernels' streams (matrix, read-once
                              vectors): 1 non-temporal, 0 ordinary loads, -1 (default)
                              per precision: non-temporal when the larger attempt kernel

@@ -369,8 +369,6 @@ int check_opts(const pdhg_opts *o) {
   if (!(o->dinf_tol >= 0.0) || !isfinite(o->dinf_tol))
     return fail(PDHG_ERR_ARG, "dinf_tol must be finite and >= 0");
   if (o->batch_pack != 0 && o->batch_pack != 1) return fail(PDHG_ERR_ARG, "batch_pack must be 0 or 1");
-  if (o->batch_share_bounds != 0 && o->batch_share_bounds != 1)
-    return fail(PDHG_ERR_ARG, "batch_share_bounds must be 0 or 1");
   if (o->stream_nt < -1 || o->stream_nt > 1)
     return fail(PDHG_ERR_ARG, "stream_nt must be -1, 0 or 1");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
@@ -1346,7 +1344,6 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->fp32_stall_evals = 300;
   o->dinf_tol = 1e-8;
   o->batch_pack = 0;
-  o->batch_share_bounds = 1;
   o->stream_nt = -1;
 }
 
@@ -1865,8 +1862,6 @@ struct BatchPlan {
   std::vector<uint8_t *> vk;
   std::vector<int32_t *> fix_idx;
   std::vector<double *> fix_val;
-  std::vector<uint32_t *> fixw;  // fixing codes over the base's bounds (attempt kernels)
-  std::vector<int *> fixbad;     // set when the codes cannot express the instance's box
   std::vector<double *> xo, yo;  // staging for host results
   std::vector<double *> x0, y0;  // staging for host warm starts
   GroupDev gd;
@@ -1883,8 +1878,6 @@ size_t batch_layout(pdhg_handle *const *hs, const pdhg_instance *inst, int batch
   P.vk.assign(batch, nullptr);
   P.fix_idx.assign(batch, nullptr);
   P.fix_val.assign(batch, nullptr);
-  P.fixw.assign(batch, nullptr);
-  P.fixbad.assign(batch, nullptr);
   P.xo = P.yo = P.x0 = P.y0 = nd;
   for (int k = 0; k < batch; k++) {
     const pdhg_handle *h = hs[inst[k].base];
@@ -1911,10 +1904,6 @@ size_t batch_layout(pdhg_handle *const *hs, const pdhg_instance *inst, int batch
       if (mixed) {
         P.lf[k] = cv.take<float>(n);
         P.uf[k] = cv.take<float>(n);
-      }
-      if (h->o.batch_share_bounds) {
-        P.fixw[k] = cv.take<uint32_t>((n + 15) / 16);
-        P.fixbad[k] = cv.take<int>(1);
       }
     }
     if (inst[k].n_fix > 0) {
@@ -2046,10 +2035,6 @@ int solve_batch_on(pdhg_handle *const *handles, int n_handles, const pdhg_instan
                           h->hs);
       }
       launch_var_kind(P.l0[k], P.u0[k], n, P.vk[k], h->hs);
-      if (P.fixw[k]) {
-        HC(hipMemsetAsync(P.fixbad[k], 0, sizeof(int), h->hs));
-        launch_fix_codes(P.l0[k], P.u0[k], hb->l0, hb->u0, n, P.fixw[k], P.fixbad[k], h->hs);
-      }
       l0 = P.l0[k];
       u0 = P.u0[k];
     }
@@ -2085,22 +2070,9 @@ int solve_batch_on(pdhg_handle *const *handles, int n_handles, const pdhg_instan
     launch_init_ctl(hb->v, hb->nnz, d.b, d.c, q.b ? P.b0[k] : hb->b0, q.c ? P.c0[k] : hb->c0, m, n,
                     hb->scratch, hb->nscratch, ib.st, hb->o.step_mode, eta0, omega0, h->hs);
     HK();
-    int fix_bad = 1;
-    if (P.fixw[k])
-      HC(hipMemcpyAsync(&fix_bad, P.fixbad[k], sizeof(int), hipMemcpyDeviceToHost, h->hs));
     HC(hipStreamSynchronize(h->hs));  // the base's scratch is reused by the next instance
     i64[k] = make_inst<double>(hb, d, ib);
     i32[k] = make_inst<float>(hb, d, ib);
-    if (!fix_bad) {  // the attempt kernels read the base's bounds and the codes
-      i64[k].w.l = hb->l;
-      i64[k].w.u = hb->u;
-      i64[k].w.fixw = P.fixw[k];
-      if (mixed) {
-        i32[k].w.l = hb->lf;
-        i32[k].w.u = hb->uf;
-        i32[k].w.fixw = P.fixw[k];
-      }
-    }
     if (q.b || q.l || q.u) {  // the base's implied bounds assume its b, l, u
       i64[k].e.ilo = i64[k].e.ihi = nullptr;
       i32[k].e.ilo = i32[k].e.ihi = nullptr;

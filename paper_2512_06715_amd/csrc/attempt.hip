@@ -270,17 +270,6 @@ __device__ __forceinline__ bool primal_finish(int64_t j, T t, T tau, T xj, T cj,
   return xt > lj && xt < uj;
 }
 
-// The box of column j for an instance that shares its base's bounds: its
-// fixing code (two bits per column) replaces one bound by the other.
-template <typename T>
-__device__ __forceinline__ void fixed_box(const AS_G uint32_t *fixw, int64_t j, T &lj, T &uj) {
-  const uint32_t code = (fixw[j >> 4] >> ((j & 15) << 1)) & 3u;
-  if (code == 1u)
-    uj = lj;
-  else if (code == 2u)
-    lj = uj;
-}
-
 // Long column lb of an instance (a workgroup of its own): its row-dot over
 // the stored transpose in FP64, then the primal update by lane 0.
 template <typename T>
@@ -296,9 +285,7 @@ __device__ __forceinline__ void primal_long(const AS_C IterView<T> &w, const AS_
   double t = long_rowdot<T>(gin(w.ri), gin(w.vt), y, cpc[j], cpc[j + 1]);
   if (threadIdx.x == 0) {
     double dd = 0.0;
-    T lj = l[j], uj = u[j];
-    if (w.fixw) fixed_box<T>(gin(w.fixw), j, lj, uj);
-    bool in = primal_finish<T>(j, (T)t, tau, x[j], c[j], lj, uj, xn, nullptr, (T)0, 0.0, 0, dd);
+    bool in = primal_finish<T>(j, (T)t, tau, x[j], c[j], l[j], u[j], xn, nullptr, (T)0, 0.0, 0, dd);
     gout(w.part_dx2)[lb] = dd;
     if (mask && in) record_bit(mask, j);
   }
@@ -323,7 +310,6 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
   const AS_G T *x = gin((const T *)w.X[cur]), *y = gin((const T *)w.Y[cur]);
   AS_G T *xn = gout(w.X[cur ^ 1]);
   AS_G T *xs = gout(w.XS);
-  const AS_G uint32_t *fixw = w.fixw ? gin(w.fixw) : nullptr;
   uint64_t *mask = w.mask_x ? w.mask_x + (st->k - w.mask_k0) * ((n + 63) >> 6) : nullptr;
   double d2[1] = {0.0};
   if (lb < w.n_long_cols) {
@@ -347,7 +333,6 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
       cj = ld_stream<NT>(c + j);
       lj = ld_stream<NT>(l + j);
       uj = ld_stream<NT>(u + j);
-      if (fixw) fixed_box<T>(fixw, j, lj, uj);
       if (fold_read) xsj = xs[j];
     }
     const TileIx<C, NT> ix{cp, ri, gin(w.cofs), gin(w.rix16), C ? cin(w.tb_cols)[t] : 0};
@@ -594,7 +579,6 @@ __global__ __launch_bounds__(PDHG_TILE) void k_primal_pack(const Inst<T> *__rest
         cj[q] = ld_stream<true>(gin(w.c) + j);
         lj[q] = ld_stream<true>(gin(w.l) + j);
         uj[q] = ld_stream<true>(gin(w.u) + j);
-        if (w.fixw) fixed_box<T>(gin(w.fixw), j, lj[q], uj[q]);
         if (st->pending > 0.0 && !st->fresh) xsj[q] = gin((const T *)w.XS)[j];
       }
     }

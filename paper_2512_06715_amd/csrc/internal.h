@@ -88,10 +88,6 @@ struct IterView {
   // equality row or pre-projection y > 0) into words [(k - mask_k0) * words]
   uint64_t *mask_x, *mask_y;
   int64_t mask_k0;
-  // non-null: l and u are the base's arrays, shared by the batch, and this
-  // instance's fixings are two-bit codes, sixteen columns per word (1: both
-  // bounds l_j, 2: both u_j); null: l and u are the instance's own
-  const uint32_t *fixw;
 };
 
 // FP64 evaluation view (always FP64 matrix); iterates of type T.
@@ -169,8 +165,6 @@ template <typename T>
 void launch_spmv_merge(const int32_t *rp, const int32_t *ci, const T *v, const T *x, T *y,
                        int64_t m, int64_t nnz, void *ws, hipStream_t s);
 
-void launch_fix_codes(const double *lk, const double *uk, const double *lb, const double *ub,
-                      int64_t n, uint32_t *codes, int *bad, hipStream_t s);
 void launch_fix_bounds(double *l, double *u, const int32_t *idx, const double *val, int64_t nfix,
                        const int32_t *inv, int64_t n,
                        hipStream_t s);

@@ -314,45 +314,6 @@ __global__ void k_fix_bounds(double *l, double *u, const int32_t *__restrict__ i
   u[j] = val[k];
 }
 
-// Two-bit fixing codes of an instance whose bounds (lk, uk) differ from its
-// base's (lb, ub) only by fixings to one of the base's own bounds, sixteen
-// columns per word: 0 the base's box, 1 both bounds the base's lower one, 2
-// both its upper one.  Any other difference (an override, a fixing to an
-// interior value) sets *bad, and the instance keeps its own bound arrays.
-// Values are compared bit for bit, so the codes reproduce the instance's
-// arrays exactly.
-__device__ __forceinline__ bool same_bits(double a, double b) {
-  return __double_as_longlong(a) == __double_as_longlong(b);
-}
-
-__global__ void k_fix_codes(const double *__restrict__ lk, const double *__restrict__ uk,
-                            const double *__restrict__ lb, const double *__restrict__ ub,
-                            int64_t n, uint32_t *codes, int *bad) {
-  int64_t wd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (wd * 16 >= n) return;
-  uint32_t word = 0;
-  bool odd = false;
-  for (int q = 0; q < 16; q++) {
-    int64_t j = wd * 16 + q;
-    if (j >= n) break;
-    const double l = lk[j], u = uk[j], l0 = lb[j], u0 = ub[j];
-    uint32_t code;
-    if (same_bits(l, l0) && same_bits(u, u0))
-      code = 0;
-    else if (same_bits(l, l0) && same_bits(u, l0))
-      code = 1;
-    else if (same_bits(l, u0) && same_bits(u, u0))
-      code = 2;
-    else {
-      code = 0;
-      odd = true;
-    }
-    word |= code << (2 * q);
-  }
-  codes[wd] = word;
-  if (odd) *bad = 1;
-}
-
 // 16-bit tile-relative structure of a CSR matrix, one workgroup per tile of
 // PDHG_TILE rows: rofs[i] = ptr[i + 1] - ptr[r0] (r0 the tile's first row),
 // ix16[k] = idx[k] - tb[t], tb[t] = the smallest index of the tile's
@@ -402,11 +363,6 @@ __global__ __launch_bounds__(PDHG_BLOCK) void k_compact(const int32_t *__restric
 void launch_fix_bounds(double *l, double *u, const int32_t *idx, const double *val, int64_t nfix,
                        const int32_t *inv, int64_t n, hipStream_t s) {
   if (nfix > 0) k_fix_bounds<<<grid_for(nfix), PDHG_BLOCK, 0, s>>>(l, u, idx, val, nfix, inv, n);
-}
-
-void launch_fix_codes(const double *lk, const double *uk, const double *lb, const double *ub,
-                      int64_t n, uint32_t *codes, int *bad, hipStream_t s) {
-  k_fix_codes<<<grid_for((n + 15) / 16), PDHG_BLOCK, 0, s>>>(lk, uk, lb, ub, n, codes, bad);
 }
 
 void launch_validate(const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *kind,
