@@ -399,7 +399,7 @@ def main():
     ap.add_argument("--cold-attempts", type=int, default=50,
                     help="attempts timed with the caches flushed before each (0 skips)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", default="64,192")
+    ap.add_argument("--cpu-sample", default="64,384")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
     args = ap.parse_args()
