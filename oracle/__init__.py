@@ -26,7 +26,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pdhg_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB points the loader at another build of the same source (the
+# sanitizer build of the tests)
+_DEFAULT_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB = os.environ.get("ORACLE_LIB", _DEFAULT_LIB)
+_SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
 _lib = None
 
 ST_OPTIMAL, ST_ITER_LIMIT, ST_NUMERICAL = 1, 2, 4
@@ -35,12 +39,27 @@ VK_FREE, VK_LOWER, VK_UPPER, VK_BOXED, VK_FIXED = range(5)
 
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc (no FP contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + f".tmp{os.getpid()}"
+    out = _DEFAULT_LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
                                "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
+
+
+def build_sanitized() -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer,
+    every finding fatal (for the sanitizer test; load it with ORACLE_LIB and
+    gcc's libasan preloaded)."""
+    if not os.path.exists(_SAN_LIB) or os.path.getmtime(_SAN_LIB) < os.path.getmtime(_SRC):
+        tmp = _SAN_LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+                               "-fno-fast-math", "-std=c11", "-fPIC", "-shared",
+                               "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SAN_LIB)
+    return _SAN_LIB
 
 
 class _Opts(ctypes.Structure):
@@ -62,7 +81,8 @@ TRACE_FIELDS = ("k", "komega_cur", "komega_avg", "komega_last", "komega_prev", "
 def lib():
     global _lib
     if _lib is None:
-        build()
+        if _LIB == _DEFAULT_LIB:
+            build()
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64

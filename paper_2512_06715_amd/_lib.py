@@ -5,7 +5,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpdhg.so")
+# PDHG_LIB points the loader at another build of the same sources (the
+# host-sanitizer build of the tests); there is no fallback either way
+LIB_PATH = os.environ.get("PDHG_LIB", os.path.join(_HERE, "libpdhg.so"))
 
 PDHG_OK = 0
 ERRORS = {-1: "PDHG_ERR_ARG", -2: "PDHG_ERR_CSR", -3: "PDHG_ERR_BOUNDS",
