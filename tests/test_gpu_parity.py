@@ -329,3 +329,23 @@ def test_objective_offset_is_reported_only(gpu):
         for key in ("primal_obj", "dual_obj", "dual_bound"):
             assert i1[key] == i0[key] + shifted.obj_offset, key
         assert i1["rel_kkt"] == i0["rel_kkt"] and i1["rel_gap"] == i0["rel_gap"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_stream_load_policies_bit_identical(gpu, precision):
+    """Non-temporal and ordinary stream loads read the same values: 300
+    attempts with either policy give the same bits."""
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc1000_t48")
+    print("case stream policy", precision, flush=True)
+    res = []
+    for nt in (0, 1):
+        p = Problem(lp, max_iter=300, tol=1e-12, precision=precision, stream_nt=nt)
+        part = p.partition()
+        assert part["stream_nt_fp64"] == nt and part["stream_nt_fp32"] == nt
+        res.append(p.solve())
+        p.close()
+    (x0, y0, i0), (x1, y1, i1) = res
+    assert i0["attempts"] == i1["attempts"] and i0["accepted"] == i1["accepted"]
+    assert np.array_equal(x0.view(np.uint64), x1.view(np.uint64))
+    assert np.array_equal(y0.view(np.uint64), y1.view(np.uint64))
