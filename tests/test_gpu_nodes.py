@@ -95,3 +95,35 @@ def test_nodes_on_a_device_resident_problem(gpu, oracle_mod):
         assert nd.bound <= opt
         x, y = nd.x.cpu().numpy(), nd.y.cpu().numpy()
         assert oracle_mod.kkt(node_lp(lp, nd), x, y)["rel_kkt"] <= 1.001e-4
+
+
+def test_children_of_the_4224_bus_root(gpu, oracle_mod):
+    """At the size of the batched workload: the 4224-bus, 48-period root in
+    mixed precision, then the children of its two most fractional commitments
+    (four nodes) as one warm-started batch on an FP64 handle.  Every child
+    reaches 1e-4 by the oracle's checker, keeps its fixing, has a finite
+    bound below its objective, and no child's objective lies far below the
+    root's bound."""
+    from paper_2512_06715_amd import nodes as N
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc4224_t48")
+    ucols = lp.meta["u_cols"].ravel()
+    print("case nodes uc4224", flush=True)
+    p = Problem(lp, tol=1e-4, precision="mixed", max_iter=2000000)
+    root = N.solve_nodes(p, [N.root()])[0]
+    p.close()
+    assert root.info["status"] == 1 and np.isfinite(root.bound)
+    kids = [k for j in N.most_fractional(root, ucols, k=2) for k in N.branch(root, int(j))]
+    q = Problem(lp, tol=1e-4, precision="fp64", max_iter=2000000)
+    N.solve_nodes(q, kids, warm=True, weights=True)
+    q.close()
+    for k in kids:
+        assert k.info["status"] == 1, k.info
+        kk = oracle_mod.kkt(node_lp(lp, k), k.x, k.y)
+        assert kk["rel_kkt"] <= 1.001e-4, kk
+        assert np.array_equal(k.x[k.fix_idx], k.fix_val)
+        assert np.isfinite(k.bound) and k.bound <= k.objective
+        # a child's optimum is at least the root's; its reported objective,
+        # within the tolerance of its own, cannot fall far below the root's bound
+        assert k.objective >= root.bound - 2e-3 * abs(root.bound)
+        print("child", k.fixed(), k.info["attempts"], k.objective, k.bound, flush=True)
