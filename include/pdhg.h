@@ -162,6 +162,12 @@ typedef struct {
                              moves at least 192 MiB (three quarters of the 256 MiB
                              Infinity Cache), ordinary below.  The results do not depend
                              on it */
+  int polish_fp32_matrix; /* PDHG_MIXED with tol >= 1e-6: 1 (default) the FP64 phase's
+                             attempt kernels multiply the FP32 copies of the matrix values
+                             (widened exactly; its evaluations, restarts and termination
+                             keep the FP64 matrix); their rounding moves the fixed point
+                             by about 1e-7 relative, so tighter tolerances, and 0, use
+                             the FP64 values */
 } pdhg_opts;
 
 typedef struct {

@@ -42,7 +42,7 @@ class PdhgOpts(ctypes.Structure):
                 ("compact_index", c_int), ("infeas_every", c_int),
                 ("polish_pw_update", c_int), ("fp32_stall_evals", c_int),
                 ("dinf_tol", c_dbl), ("batch_pack", c_int),
-                ("stream_nt", c_int)]
+                ("stream_nt", c_int), ("polish_fp32_matrix", c_int)]
 
 
 class PdhgInfo(ctypes.Structure):

@@ -371,6 +371,8 @@ int check_opts(const pdhg_opts *o) {
   if (o->batch_pack != 0 && o->batch_pack != 1) return fail(PDHG_ERR_ARG, "batch_pack must be 0 or 1");
   if (o->stream_nt < -1 || o->stream_nt > 1)
     return fail(PDHG_ERR_ARG, "stream_nt must be -1, 0 or 1");
+  if (o->polish_fp32_matrix != 0 && o->polish_fp32_matrix != 1)
+    return fail(PDHG_ERR_ARG, "polish_fp32_matrix must be 0 or 1");
   if (o->unroll_iters > 0 && o->precision != PDHG_FP64)
     return fail(PDHG_ERR_ARG, "unrolled mode runs in FP64");
   if (o->unroll_iters > 0 && o->checkpoint_every < 0)
@@ -865,6 +867,8 @@ Inst<double> make_inst<double>(const pdhg_handle *h, const InstData &d, const It
   fill_common(I, h, d, b);
   I.w.v = h->v;
   I.w.vt = h->vt;
+  I.w.v32 = h->vf;  // null unless the handle is mixed
+  I.w.vt32 = h->vtf;
   I.w.b = d.b;
   I.w.c = d.c;
   I.w.l = d.l;
@@ -946,6 +950,8 @@ int upload_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
   g.compact = 1;
   for (int k = 0; k < na; k++) g.compact = g.compact && sel[k].w.cix16 != nullptr;
   g.nt = h->stream_nt[sizeof(T) == 4];
+  g.v32 = sizeof(T) == 8;
+  for (int k = 0; k < na; k++) g.v32 = g.v32 && sel[k].w.use_v32 && sel[k].w.v32 && sel[k].w.vt32;
   g.interleave = na > 1;
   for (int k = 1; k < na && g.interleave; k++) {
     const IterView<T> &a = sel[0].w, &b = sel[k].w;
@@ -958,7 +964,7 @@ int upload_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
   // shared-matrix instances walked a pack at a time (same tiles, partials and
   // bits as one at a time)
   const IterView<T> &w0 = sel[0].w;
-  g.pack = (g.interleave && g.compact && h->o.batch_pack && w0.tpb_rows == 1 &&
+  g.pack = (g.interleave && g.compact && !g.v32 && h->o.batch_pack && w0.tpb_rows == 1 &&
             w0.tpb_cols == 1 && !w0.direct && !w0.mask_x && !w0.mask_y)
                ? PDHG_PACK
                : 0;
@@ -1162,6 +1168,12 @@ int solve_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
   // left it
   if (!h->o.polish_pw_update)
     for (int i : polish) i64[i].e.pw_theta = 0.0;
+  // the FP64 phase's attempt kernels on the FP32 matrix values (its
+  // evaluation keeps the FP64 matrix): their rounding (2^-24 relative per
+  // entry) moves the fixed point by about 1e-7 relative, so only for
+  // tolerances of 1e-6 and above
+  if (h->o.polish_fp32_matrix && h->o.tol >= 1e-6)
+    for (int i : polish) i64[i].w.use_v32 = 1;
   RC(upload_group<float>(h, gd, i32, polish, g));
   Groups g64{};
   RC(upload_group<double>(h, gd, i64, polish, g64));
@@ -1345,6 +1357,7 @@ void pdhg_default_opts(pdhg_opts *o) {
   o->dinf_tol = 1e-8;
   o->batch_pack = 0;
   o->stream_nt = -1;
+  o->polish_fp32_matrix = 1;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }

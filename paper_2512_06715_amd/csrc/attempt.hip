@@ -115,19 +115,20 @@ struct Pair<double> {
 // their slots; lanes past the last pair repeat it and write the same values.
 // The lane's row bounds (rs, re) are loaded after the first loads of the
 // stream.
-template <typename T, bool NT>
-__device__ __forceinline__ void stage_pairs(const TileIx<true, NT> &ix, const AS_G T *v,
+template <typename T, typename V, bool NT>
+__device__ __forceinline__ void stage_pairs(const TileIx<true, NT> &ix, const AS_G V *v,
                                             const AS_G T *x, int base, int top, T *lds, int64_t i,
                                             bool valid, int &rs, int &re) {
   typedef typename Pair<T>::type T2;
+  typedef typename Pair<V>::type V2;
   const int a0 = base & ~1;
   const int npair = (top - a0 + 1) >> 1;
   const AS_G uint32_t *iw = (const AS_G uint32_t *)(ix.ix16 + a0);
-  const AS_G T2 *vw = (const AS_G T2 *)(v + a0);
+  const AS_G V2 *vw = (const AS_G V2 *)(v + a0);
   constexpr int TP = TILE_U / 2;
   for (int p0 = 0; p0 < npair; p0 += TP * PDHG_TILE) {
     uint32_t w[TP];
-    T2 vv[TP];
+    V2 vv[TP];
 #pragma unroll
     for (int q = 0; q < TP; q++) {
       int p = p0 + q * PDHG_TILE + (int)threadIdx.x;
@@ -144,15 +145,15 @@ __device__ __forceinline__ void stage_pairs(const TileIx<true, NT> &ix, const AS
       int c0 = e >= base ? ix.tb + (int)(w[q] & 0xffffu) : ix.tb;
       int c1 = e + 1 < top ? ix.tb + (int)(w[q] >> 16) : ix.tb;
       T2 pr;
-      pr.x = mul_rn(vv[q].x, x[c0]);
-      pr.y = mul_rn(vv[q].y, x[c1]);
+      pr.x = mul_rn((T)vv[q].x, x[c0]);
+      pr.y = mul_rn((T)vv[q].y, x[c1]);
       *(T2 *)(lds + 2 * pc) = pr;
     }
   }
 }
 
-template <typename T, bool C, bool NT>
-__device__ __forceinline__ T tile_rowdot(const TileIx<C, NT> &ix, const AS_G T *v, const AS_G T *x,
+template <typename T, typename V, bool C, bool NT>
+__device__ __forceinline__ T tile_rowdot(const TileIx<C, NT> &ix, const AS_G V *v, const AS_G T *x,
                                          int64_t i, bool valid, int base, int top, int long_seg,
                                          T *lds, int direct, bool &mine) {
   const int cnt = top - base;
@@ -162,7 +163,7 @@ __device__ __forceinline__ T tile_rowdot(const TileIx<C, NT> &ix, const AS_G T *
     const int off = base & 1;  // slot of the tile's first entry
     if constexpr (C) {
       if (cnt > 0)
-        stage_pairs<T, NT>(ix, v, x, base, top, lds, i, valid, rs, re);
+        stage_pairs<T, V, NT>(ix, v, x, base, top, lds, i, valid, rs, re);
       else if (valid)
         ix.bounds(i, base, rs, re);
     }
@@ -174,7 +175,7 @@ __device__ __forceinline__ T tile_rowdot(const TileIx<C, NT> &ix, const AS_G T *
   } else if (!direct && cnt <= TILE_CAP) {
     for (int k0 = 0; k0 < cnt; k0 += TILE_U * PDHG_TILE) {
       int id[TILE_U];
-      T vv[TILE_U];
+      V vv[TILE_U];
 #pragma unroll
       for (int q = 0; q < TILE_U; q++) {
         int k = k0 + q * PDHG_TILE + (int)threadIdx.x;
@@ -187,7 +188,7 @@ __device__ __forceinline__ T tile_rowdot(const TileIx<C, NT> &ix, const AS_G T *
       for (int q = 0; q < TILE_U; q++) {
         int k = k0 + q * PDHG_TILE + (int)threadIdx.x;
         // lanes past the tile write a slot of their own past the staged range
-        lds[k < cnt ? k : TILE_CAP + (int)threadIdx.x] = mul_rn(vv[q], x[id[q]]);
+        lds[k < cnt ? k : TILE_CAP + (int)threadIdx.x] = mul_rn((T)vv[q], x[id[q]]);
       }
     }
     if (cnt == 0 && valid) ix.bounds(i, base, rs, re);
@@ -202,7 +203,7 @@ __device__ __forceinline__ T tile_rowdot(const TileIx<C, NT> &ix, const AS_G T *
     if (mine) {
       for (int k0 = rs; k0 < re; k0 += TILE_U) {
         int id[TILE_U];
-        T vv[TILE_U];
+        V vv[TILE_U];
 #pragma unroll
         for (int q = 0; q < TILE_U; q++) {
           int kc = k0 + q < re ? k0 + q : re - 1;
@@ -211,7 +212,7 @@ __device__ __forceinline__ T tile_rowdot(const TileIx<C, NT> &ix, const AS_G T *
         }
 #pragma unroll
         for (int q = 0; q < TILE_U; q++) {
-          T p = mul_rn(vv[q], x[id[q]]);
+          T p = mul_rn((T)vv[q], x[id[q]]);
           if (k0 + q < re) s += p;
         }
       }
@@ -221,11 +222,12 @@ __device__ __forceinline__ T tile_rowdot(const TileIx<C, NT> &ix, const AS_G T *
 }
 
 // One long row (a workgroup of its own): FP64 sum of the products.
-template <typename T>
-__device__ __forceinline__ double long_rowdot(const AS_G int32_t *idx, const AS_G T *v,
+template <typename T, typename V>
+__device__ __forceinline__ double long_rowdot(const AS_G int32_t *idx, const AS_G V *v,
                                               const AS_G T *x, int s, int e) {
   double acc[1] = {0.0};
-  for (int k = s + threadIdx.x; k < e; k += PDHG_TILE) acc[0] += (double)mul_rn(v[k], x[idx[k]]);
+  for (int k = s + threadIdx.x; k < e; k += PDHG_TILE)
+    acc[0] += (double)mul_rn((T)v[k], x[idx[k]]);
   double tot[1];
   block_reduce<1, PDHG_TILE>(acc, 0u, tot);
   return tot[0];
@@ -270,9 +272,20 @@ __device__ __forceinline__ bool primal_finish(int64_t j, T t, T tau, T xj, T cj,
   return xt > lj && xt < uj;
 }
 
+// Matrix values the attempt kernels multiply: the iterates' own precision,
+// or with FP64 iterates and V = float the FP32 copies, widened exactly (the
+// mixed path's FP64 phase).
+template <typename V, typename T>
+__device__ __forceinline__ const AS_G V *vals(const AS_C IterView<T> &w, bool transpose) {
+  if constexpr (sizeof(V) == sizeof(T))
+    return gin((const V *)(transpose ? w.vt : w.v));
+  else
+    return gin(transpose ? w.vt32 : w.v32);
+}
+
 // Long column lb of an instance (a workgroup of its own): its row-dot over
 // the stored transpose in FP64, then the primal update by lane 0.
-template <typename T>
+template <typename T, typename V>
 __device__ __forceinline__ void primal_long(const AS_C IterView<T> &w, const AS_C CtlState *st,
                                             int lb, uint64_t *mask) {
   const int cur = st->cur;
@@ -282,7 +295,7 @@ __device__ __forceinline__ void primal_long(const AS_C IterView<T> &w, const AS_
   AS_G T *xn = gout(w.X[cur ^ 1]);
   int64_t j = gin(w.long_cols)[lb];
   const AS_C int32_t *cpc = cin(w.cp);
-  double t = long_rowdot<T>(gin(w.ri), gin(w.vt), y, cpc[j], cpc[j + 1]);
+  double t = long_rowdot<T, V>(gin(w.ri), vals<V>(w, true), y, cpc[j], cpc[j + 1]);
   if (threadIdx.x == 0) {
     double dd = 0.0;
     bool in = primal_finish<T>(j, (T)t, tau, x[j], c[j], l[j], u[j], xn, nullptr, (T)0, 0.0, 0, dd);
@@ -291,7 +304,7 @@ __device__ __forceinline__ void primal_long(const AS_C IterView<T> &w, const AS_
   }
 }
 
-template <typename T, bool C, bool NT>
+template <typename T, bool C, bool NT, typename V>
 __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) void k_primal(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ __align__(16) T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -306,14 +319,15 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
   const bool fold_read = pend > 0.0 && !fresh;
   const int64_t n = w.n;
   const AS_G int32_t *cp = gin(w.cp), *ri = gin(w.ri);
-  const AS_G T *vt = gin(w.vt), *c = gin(w.c), *l = gin(w.l), *u = gin(w.u);
+  const AS_G V *vt = vals<V>(w, true);
+  const AS_G T *c = gin(w.c), *l = gin(w.l), *u = gin(w.u);
   const AS_G T *x = gin((const T *)w.X[cur]), *y = gin((const T *)w.Y[cur]);
   AS_G T *xn = gout(w.X[cur ^ 1]);
   AS_G T *xs = gout(w.XS);
   uint64_t *mask = w.mask_x ? w.mask_x + (st->k - w.mask_k0) * ((n + 63) >> 6) : nullptr;
   double d2[1] = {0.0};
   if (lb < w.n_long_cols) {
-    primal_long<T>(w, st, lb, mask);
+    primal_long<T, V>(w, st, lb, mask);
     return;
   }
   const int tpb = w.tpb_cols, long_seg = w.long_seg, direct = w.direct;
@@ -337,7 +351,7 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
     }
     const TileIx<C, NT> ix{cp, ri, gin(w.cofs), gin(w.rix16), C ? cin(w.tb_cols)[t] : 0};
     bool mine;
-    T s = tile_rowdot<T, C, NT>(ix, vt, y, j, j < n, base, top, long_seg, lds, direct, mine);
+    T s = tile_rowdot<T, V, C, NT>(ix, vt, y, j, j < n, base, top, long_seg, lds, direct, mine);
     bool in = false;
     if (mine)
       in = primal_finish<T>(j, s, tau, xj, cj, lj, uj, xn, xs, xsj, pend, fresh, d2[0]);
@@ -370,7 +384,7 @@ __device__ __forceinline__ bool dual_finish(int64_t i, T s, T sigma, T yi, T axi
 
 // Long row lb of an instance: its row-dot over A in FP64, then the dual
 // update by lane 0.
-template <typename T>
+template <typename T, typename V>
 __device__ __forceinline__ void dual_long(const AS_C IterView<T> &w, const AS_C CtlState *st,
                                           int lb, uint64_t *mask) {
   const int cur = st->cur;
@@ -380,7 +394,7 @@ __device__ __forceinline__ void dual_long(const AS_C IterView<T> &w, const AS_C 
   AS_G T *yn = gout(w.Y[cur ^ 1]), *axn = gout(w.AX[cur ^ 1]);
   int64_t i = gin(w.long_rows)[lb];
   const AS_C int32_t *rpc = cin(w.rp);
-  double t = long_rowdot<T>(gin(w.ci), gin(w.v), xn, rpc[i], rpc[i + 1]);
+  double t = long_rowdot<T, V>(gin(w.ci), vals<V>(w, false), xn, rpc[i], rpc[i + 1]);
   if (threadIdx.x == 0) {
     double acc[2] = {0.0, 0.0};
     bool in = dual_finish<T>(i, (T)t, sigma, y[i], ax[i], bb[i], gin(w.kind)[i], yn, axn, nullptr,
@@ -391,7 +405,7 @@ __device__ __forceinline__ void dual_long(const AS_C IterView<T> &w, const AS_C 
   }
 }
 
-template <typename T, bool C, bool NT>
+template <typename T, bool C, bool NT, typename V>
 __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) void k_dual(const Inst<T> *__restrict__ I, Groups g) {
   __shared__ __align__(16) T lds[TILE_CAP + PDHG_TILE];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -406,7 +420,8 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
   const bool fold_read = pend > 0.0 && !fresh;
   const int64_t m = w.m;
   const AS_G int32_t *rp = gin(w.rp), *ci = gin(w.ci);
-  const AS_G T *v = gin(w.v), *bb = gin(w.b);
+  const AS_G V *v = vals<V>(w, false);
+  const AS_G T *bb = gin(w.b);
   const AS_G uint8_t *kind = gin(w.kind);
   const AS_G T *xn = gin((const T *)w.X[cur ^ 1]);
   const AS_G T *y = gin((const T *)w.Y[cur]), *ax = gin((const T *)w.AX[cur]);
@@ -415,7 +430,7 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
   const int64_t G = w.grid_rows;
   double acc[2] = {0.0, 0.0};
   if (lb < w.n_long_rows) {
-    dual_long<T>(w, st, lb, mask);
+    dual_long<T, V>(w, st, lb, mask);
     return;
   }
   const int tpb = w.tpb_rows, long_seg = w.long_seg, direct = w.direct;
@@ -439,7 +454,7 @@ __global__ __launch_bounds__(PDHG_TILE) __attribute__((amdgpu_waves_per_eu(8))) 
     }
     const TileIx<C, NT> ix{rp, ci, gin(w.rofs), gin(w.cix16), C ? cin(w.tb_rows)[t] : 0};
     bool mine;
-    T s = tile_rowdot<T, C, NT>(ix, v, xn, i, i < m, base, top, long_seg, lds, direct, mine);
+    T s = tile_rowdot<T, V, C, NT>(ix, v, xn, i, i < m, base, top, long_seg, lds, direct, mine);
     bool in = false;
     if (mine)
       in = dual_finish<T>(i, s, sigma, yi, axi, bi, ki, yn, axn, ys, ysi, pend, fresh, acc[0],
@@ -544,7 +559,7 @@ __global__ __launch_bounds__(PDHG_TILE) void k_primal_pack(const Inst<T> *__rest
   const int nlong = w0.n_long_cols;
   if (b < nlong * g.ninst) {
     const int inst = b % g.ninst;
-    primal_long<T>(cin(I)[inst].w, cin(cin(I)[inst].st), b / g.ninst, nullptr);
+    primal_long<T, T>(cin(I)[inst].w, cin(cin(I)[inst].st), b / g.ninst, nullptr);
     return;
   }
   const int npk = (g.ninst + NB - 1) / NB;
@@ -629,7 +644,7 @@ __global__ __launch_bounds__(PDHG_TILE) void k_dual_pack(const Inst<T> *__restri
   const int nlong = w0.n_long_rows;
   if (b < nlong * g.ninst) {
     const int inst = b % g.ninst;
-    dual_long<T>(cin(I)[inst].w, cin(cin(I)[inst].st), b / g.ninst, nullptr);
+    dual_long<T, T>(cin(I)[inst].w, cin(cin(I)[inst].st), b / g.ninst, nullptr);
     return;
   }
   const int npk = (g.ninst + NB - 1) / NB;
@@ -712,24 +727,43 @@ __global__ __launch_bounds__(PDHG_TILE) void k_dual_pack(const Inst<T> *__restri
 // With events, the kernel is launched through hipExtLaunchKernelGGL, whose
 // start/stop events take the dispatch's own timestamps (the kernel's
 // duration, without launch gaps).
+template <typename T, bool C, bool NT, typename V>
+void launch_primal_v(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
+                     hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_primal<T, C, NT, V>, dim3(grid_of(g.n_primal)), dim3(PDHG_TILE), 0, s,
+                          t0, t1, 0, I, g);
+  else
+    k_primal<T, C, NT, V><<<grid_of(g.n_primal), PDHG_TILE, 0, s>>>(I, g);
+}
+
+// FP64 iterates on the FP32 matrix values when the group asks for them
 template <typename T, bool C, bool NT>
 void launch_primal_as(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
                       hipEvent_t t1) {
+  if (sizeof(T) == 8 && g.v32)
+    launch_primal_v<T, C, NT, float>(I, g, s, t0, t1);
+  else
+    launch_primal_v<T, C, NT, T>(I, g, s, t0, t1);
+}
+
+template <typename T, bool C, bool NT, typename V>
+void launch_dual_v(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
+                   hipEvent_t t1) {
   if (t0)
-    hipExtLaunchKernelGGL(k_primal<T, C, NT>, dim3(grid_of(g.n_primal)), dim3(PDHG_TILE), 0, s, t0,
+    hipExtLaunchKernelGGL(k_dual<T, C, NT, V>, dim3(grid_of(g.n_dual)), dim3(PDHG_TILE), 0, s, t0,
                           t1, 0, I, g);
   else
-    k_primal<T, C, NT><<<grid_of(g.n_primal), PDHG_TILE, 0, s>>>(I, g);
+    k_dual<T, C, NT, V><<<grid_of(g.n_dual), PDHG_TILE, 0, s>>>(I, g);
 }
 
 template <typename T, bool C, bool NT>
 void launch_dual_as(const Inst<T> *I, const Groups &g, hipStream_t s, hipEvent_t t0,
                     hipEvent_t t1) {
-  if (t0)
-    hipExtLaunchKernelGGL(k_dual<T, C, NT>, dim3(grid_of(g.n_dual)), dim3(PDHG_TILE), 0, s, t0, t1,
-                          0, I, g);
+  if (sizeof(T) == 8 && g.v32)
+    launch_dual_v<T, C, NT, float>(I, g, s, t0, t1);
   else
-    k_dual<T, C, NT><<<grid_of(g.n_dual), PDHG_TILE, 0, s>>>(I, g);
+    launch_dual_v<T, C, NT, T>(I, g, s, t0, t1);
 }
 
 template <typename T>

@@ -88,6 +88,11 @@ struct IterView {
   // equality row or pre-projection y > 0) into words [(k - mask_k0) * words]
   uint64_t *mask_x, *mask_y;
   int64_t mask_k0;
+  // FP32 copies of the matrix values (mixed handles; null otherwise), which
+  // FP64 iterates multiply when use_v32 is set (the mixed path's FP64 phase
+  // with opts.polish_fp32_matrix)
+  const float *v32, *vt32;
+  int use_v32;
 };
 
 // FP64 evaluation view (always FP64 matrix); iterates of type T.
@@ -232,6 +237,9 @@ struct Groups {
   // 1: the attempt kernels stream the matrix and the read-once vectors with
   // non-temporal loads; 0: ordinary loads
   int nt;
+  // 1: FP64 iterates multiply the FP32 matrix values (every instance has
+  // use_v32 set)
+  int v32;
 };
 
 // ---------------------------------------------------------------------------

@@ -54,3 +54,29 @@ def test_mixed_uc1000(gpu, oracle_mod):
     print("objective error", abs(k["pobj"] - ref) / abs(ref), flush=True)
     assert abs(k["pobj"] - ref) <= 1e-4 * abs(ref)
     assert abs(info["primal_obj"] - k["pobj"]) <= 1e-9 * abs(ref)
+
+
+@pytest.mark.parametrize("fp32_matrix", [0, 1])
+def test_fp64_phase_on_fp32_matrix_values(gpu, oracle_mod, fp32_matrix):
+    """The mixed path's FP64 phase on the FP32 copies of the matrix values
+    (the default at tolerances of 1e-6 and above) or on the FP64 values: the
+    1000-bus LP reaches 1e-5, confirmed by the oracle's checker with the FP64
+    matrix, with most attempts in the FP64 phase, and the objective within
+    1e-4 of HiGHS's."""
+    import json
+    import os
+    from paper_2512_06715_amd.solver import Problem
+    lp = ucgen.workload("uc1000_t48")
+    print("case fp64 phase values", fp32_matrix, flush=True)
+    p = Problem(lp, tol=1e-5, max_iter=2000000, precision="mixed",
+                polish_fp32_matrix=fp32_matrix)
+    x, y, info = p.solve()
+    p.close()
+    assert info["status"] == 1, info
+    assert info["attempts"] > info["attempts_fp32"]   # the FP64 phase ran
+    k = oracle_mod.kkt(lp, x, y)
+    assert k["rel_kkt"] <= 1.001e-5, k
+    refs = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lp_refs.json")))
+    ref = refs["uc1000_t48"]["objective"]
+    assert abs(info["primal_obj"] - ref) <= 1e-4 * abs(ref)
+    print("attempts", info["attempts"], "fp32", info["attempts_fp32"], flush=True)
