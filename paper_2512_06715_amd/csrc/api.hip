@@ -1020,13 +1020,15 @@ int capture(pdhg_handle *h, GraphSlot &gs, const Inst<T> *dI, const Groups &g, i
 // (indices into `all`, start points already initialised).  On return
 // status[i] holds each one's status, 0 for an instance stopped because its
 // relative KKT error had not dropped below 0.9 of its best value for
-// `stall_evals` evaluations (0 disables that test).  With reuse_graph the
+// `stall_evals` evaluations (0 disables that test), or, with drift_test,
+// had drifted to 10x above a start point within 10x of the tolerance that
+// it never improved on.  With reuse_graph the
 // slot's graph is kept if it was taken with the same tables.
 template <typename T>
 int run_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
               std::vector<int> active, double tol, int64_t max_iter, double t_start,
               int stall_evals, GraphSlot &gs, bool reuse_graph, std::vector<int> &status,
-              std::vector<CtlState> &final_state) {
+              std::vector<CtlState> &final_state, bool drift_test = true) {
   const int P = h->o.eval_period;
   const bool fp32 = sizeof(T) == 4;
   std::vector<double> best(all.size(), INFINITY), first(all.size(), INFINITY);
@@ -1066,7 +1068,8 @@ int run_group(pdhg_handle *h, GroupDev &gd, const std::vector<Inst<T>> &all,
         since[i] = 0;
       } else if (stall_evals > 0 &&
                  (++since[i] >= stall_evals ||
-                  (best[i] == first[i] && first[i] <= 10.0 * tol && s.rel_kkt > 10.0 * first[i]))) {
+                  (drift_test && best[i] == first[i] && first[i] <= 10.0 * tol &&
+                   s.rel_kkt > 10.0 * first[i]))) {
         // stalled, or drifting away from a start point that was near the target
         // and has not been improved on (the next phase starts from the best point)
         status[i] = 0;
@@ -1171,8 +1174,11 @@ int solve_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
   // the FP64 phase's attempt kernels on the FP32 matrix values (its
   // evaluation keeps the FP64 matrix): their rounding (2^-24 relative per
   // entry) moves the fixed point by about 1e-7 relative, so only for
-  // tolerances of 1e-6 and above
-  if (h->o.polish_fp32_matrix && h->o.tol >= 1e-6)
+  // tolerances of 1e-6 and above, and an instance whose relative KKT error
+  // stalls there (twice the FP32 phase's window: near the tolerance the
+  // FP64 phase improves slowly but steadily) goes on with the FP64 values
+  const bool v32 = h->o.polish_fp32_matrix && h->o.tol >= 1e-6;
+  if (v32)
     for (int i : polish) i64[i].w.use_v32 = 1;
   RC(upload_group<float>(h, gd, i32, polish, g));
   Groups g64{};
@@ -1181,12 +1187,25 @@ int solve_group(pdhg_handle *h, GroupDev &gd, std::vector<Inst<double>> &i64,
   HK();
   std::vector<int> st2(B, 0);
   std::vector<CtlState> fin2(B);
-  RC(run_group<double>(h, gd, i64, polish, h->o.tol, h->o.max_iter, t0, 0, gslots[0],
-                       reuse && B == 1, st2, fin2));
+  RC(run_group<double>(h, gd, i64, polish, h->o.tol, h->o.max_iter, t0,
+                       v32 ? 2 * h->o.fp32_stall_evals : 0, gslots[0], reuse && B == 1 && !v32, st2,
+                       fin2, false));
+  std::vector<int> again;
   for (int i : polish) {
     status[i] = st2[i];
     fin[i] = fin2[i];
     final_fp32[i] = 0;
+    if (v32 && st2[i] == 0) again.push_back(i);
+  }
+  if (again.empty()) return PDHG_OK;
+  for (int i : again) i64[i].w.use_v32 = 0;
+  std::vector<int> st3(B, 0);
+  std::vector<CtlState> fin3(B);
+  RC(run_group<double>(h, gd, i64, again, h->o.tol, h->o.max_iter, t0, 0, gslots[0], false, st3,
+                       fin3));
+  for (int i : again) {
+    status[i] = st3[i];
+    fin[i] = fin3[i];
   }
   return PDHG_OK;
 }
