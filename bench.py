@@ -138,6 +138,17 @@ def reference_objective(workload: str):
     return r["objective"] if r and r.get("status") == "optimal" else None
 
 
+def oracle_run(workload: str, tol: float):
+    """The FP64 oracle's own solve of the workload to the same tolerance, if
+    stored (tests/golden/oracle_runs.json, written by make_oracle_runs.py)."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        runs = json.load(f)
+    return runs.get(f"{workload}@{tol:g}")
+
+
 def fp64_compare(lp, args):
     """One cold FP64 solve of the same LP on the device (for the speedup)."""
     import torch
@@ -557,6 +568,16 @@ def main():
         fp64_relative=(abs(extra["fp64_primal_obj"] - ref) / abs(ref))
         if ref is not None and "fp64_primal_obj" in extra else None,
         dual_bound_gap=(last["primal_obj"] - last["dual_bound"]) / abs(last["primal_obj"]))
+    orc = oracle_run(args.workload, args.tol)
+    if orc is not None:
+        o = orc["info"]["pobj"]
+        extra["objective_error"]["oracle_same_tol"] = dict(
+            objective=o, attempts=orc["info"]["attempts"], rel_kkt=orc["kkt"]["rel_kkt"],
+            relative=abs(last["primal_obj"] - o) / abs(o),
+            fp64_relative=(abs(extra["fp64_primal_obj"] - o) / abs(o))
+            if "fp64_primal_obj" in extra else None,
+            note="the oracle's own FP64 solve to the same tolerance (another trajectory: "
+                 "both points are within the tolerance, not the same point)")
     out = dict(
         metric=METRIC,
         value=round(attempts / elapsed, 1),

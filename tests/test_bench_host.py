@@ -85,3 +85,14 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
+
+
+def test_oracle_run_record_lookup(tmp_path, monkeypatch):
+    """The bench finds the oracle's own solve by workload and tolerance."""
+    (tmp_path / "tests" / "golden").mkdir(parents=True)
+    rec = {"uc6717_t96@0.0001": {"info": {"pobj": 1.0, "attempts": 5}, "kkt": {"rel_kkt": 1e-4}}}
+    (tmp_path / "tests" / "golden" / "oracle_runs.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.oracle_run("uc6717_t96", 1e-4)["info"]["attempts"] == 5
+    assert bench.oracle_run("uc6717_t96", 1e-6) is None
+    assert bench.oracle_run("uc1000_t48", 1e-4) is None
