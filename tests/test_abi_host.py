@@ -37,6 +37,7 @@ def test_default_opts():
     assert o.step_mode == 0 and o.precision == L.PDHG_FP64 and o.pw_theta == 0.5
     assert o.reorder == 1 and o.compact_index == 1 and o.polish_pw_update == 1
     assert o.fp32_stall_evals == 300 and o.dinf_tol == 1e-8
+    assert o.batch_pack == 0 and o.stream_nt == -1 and o.polish_fp32_matrix == 1
 
 
 def _lp_struct(lp, obj_offset=0.0):
@@ -109,7 +110,8 @@ def test_setup_rejects_bad_options_and_small_workspace():
     assert _setup_rc(lp, dict(precision=7))[0] == -1
     assert _setup_rc(lp, dict(pw_theta=2.0))[0] == -1
     for bad in (dict(reorder=2), dict(compact_index=-1), dict(polish_pw_update=3),
-                dict(fp32_stall_evals=-1), dict(dinf_tol=-1.0)):
+                dict(fp32_stall_evals=-1), dict(dinf_tol=-1.0), dict(batch_pack=2),
+                dict(stream_nt=2), dict(polish_fp32_matrix=-1)):
         rc, msg = _setup_rc(lp, bad)
         assert rc == -1 and list(bad)[0] in msg, (bad, msg)
     lib = L.load()
